@@ -1,0 +1,200 @@
+/*
+ * mpt.h -- C ABI of libmpt: the per-particle time step of a Lagrangian
+ * transport model on one AMD Instinct MI355X (gfx950).
+ *
+ * The operation is the model's "chemistry-physics processing" loop
+ * (Sec. 3.2, module list; Sec. 3.4: every air parcel is advanced
+ * independently): for each parcel and time step,
+ *   - module_timesteps  (Sec. 4.3): skip parcels that are not active;
+ *   - module_advection  (Sec. 3.2): kinematic trajectory from the winds,
+ *     here explicit midpoint with 4D (lon, lat, p, t) interpolation;
+ *   - module_position   (Sec. 3.2): keep the parcel inside the domain;
+ *   - module_diffusion_turb / module_diffusion_meso (Sec. 3.2): stochastic
+ *     perturbations, with the random numbers of Sec. 4.3 (Listing 6: three
+ *     normals per parcel and step for each) drawn from a counter-based
+ *     Philox4x32-10 keyed by (parcel id, step, purpose);
+ *   - particle sorting by grid box (Sec. 6 lists the sorting modules).
+ * The meteorological time levels (met0/met1 of Sec. 4.1's data regions)
+ * live on the device for the whole run; the parcel state (atm_t, Sec. 4.4)
+ * is SoA in caller-owned device memory.
+ *
+ * Conventions
+ *   - Units: lon/lat in degrees, p in hPa, u/v in m/s, w (omega) in hPa/s,
+ *     time in seconds, diffusivities in m^2/s.
+ *   - Ownership: the caller owns every device buffer (particles, both
+ *     ping-pong sets, the workspace).  The library never allocates device
+ *     memory; it carves met storage and sort scratch out of the workspace.
+ *     Host arrays passed in (plev, release table) are copied at the call.
+ *   - Streams: every call that enqueues work takes a hipStream_t as void*
+ *     (NULL = the null stream).  Device pointers must stay valid until the
+ *     work enqueued on that stream has completed.  The library never
+ *     synchronizes; device faults surface at the caller's next sync.
+ *   - Errors: every call validates its arguments synchronously and returns
+ *     a negative mpt_status with nothing enqueued on error.  No exceptions
+ *     cross the ABI.  One context per stream; contexts are independent.
+ *   - Determinism: results are a pure function of (inputs, seed, step
+ *     indices); they do not depend on the number of parcels, their order in
+ *     memory or whether they were sorted.
+ */
+#ifndef MPT_H
+#define MPT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mpt_ctx mpt_ctx; /* opaque */
+
+typedef enum {
+    MPT_OK = 0,
+    MPT_ERR_ARG = -1,          /* null/misaligned pointer, bad size or value */
+    MPT_ERR_STATE = -2,        /* met level not initialized, no release table */
+    MPT_ERR_TIME = -3,         /* a step falls outside the resident met levels */
+    MPT_ERR_WORKSPACE = -4,    /* workspace too small or n > n_max */
+    MPT_ERR_HIP = -5,          /* a HIP runtime call failed (or no GPU) */
+    MPT_ERR_UNSUPPORTED = -6   /* combination of options not provided */
+} mpt_status;
+
+/* Arithmetic of the step.  F64: FP64 throughout.  F32: FP32 interpolation,
+ * tendencies and random numbers; FP64 position accumulation and longitude
+ * wrap.  The mesoscale state (up, vp, wp) is double for F64, float for F32. */
+typedef enum { MPT_MATH_F64 = 0, MPT_MATH_F32 = 1 } mpt_math;
+
+/* Storage of the wind fields.  BF16 / F16 store q = RNE(f / s) with one FP32
+ * scale s = max|f| per (variable, level, time level) and decode q * s in
+ * FP32.  BF16 and F16 require MPT_MATH_F32. */
+typedef enum { MPT_DT_F32 = 0, MPT_DT_BF16 = 1, MPT_DT_F16 = 2 } mpt_dtype;
+
+/* Module flags (mpt_params.flags). */
+enum { MPT_ADVECT = 1u, MPT_TURB = 2u, MPT_MESO = 4u };
+
+/* Regular lon-lat grid with fixed pressure levels and nt resident time
+ * levels (read_met / read_met_periodic, Sec. 3.1).
+ *   nx * dlon == 360 (periodic longitude starting at lon0);
+ *   lat0 == -90, lat0 + (ny-1)*dlat == 90;
+ *   plev: host array of nz pressures [hPa], strictly decreasing (copied);
+ *   time level l sits at t_met0 + l*dt_met, l = 0 .. nt-1.
+ * Requires nx >= 2, ny >= 3, nz >= 2, nt >= 2, nx*ny*nz < 2^31. */
+typedef struct {
+    int32_t nx, ny, nz, nt;
+    double lon0, dlon, lat0, dlat;
+    const double *plev;
+    double t_met0, dt_met;
+    int32_t dtype;       /* mpt_dtype */
+    int32_t reserved;    /* must be 0 */
+} mpt_grid;
+
+/* Control parameters (read_ctl, Sec. 3.1).  Step n starts at
+ * t_start + n*dt.  Every step n used must satisfy
+ * t_met0 <= t_n and t_n + dt <= t_met0 + (nt-1)*dt_met. */
+typedef struct {
+    double dt, t_start;        /* s, dt > 0 */
+    double turb_dx, turb_dz;   /* turbulent diffusivities [m^2/s], >= 0 */
+    double meso_fh, meso_fv;   /* mesoscale factors, >= 0 */
+    uint64_t seed;             /* Philox key */
+    int32_t sort_interval;     /* mpt_step sorts before every step n with
+                                  n % sort_interval == 0; 0 = never */
+    int32_t math;              /* mpt_math */
+    uint32_t flags;            /* MPT_ADVECT | MPT_TURB | MPT_MESO */
+    int32_t fuse;              /* max steps one kernel launch may advance
+                                  with the state kept in registers (>= 1) */
+} mpt_params;
+
+/* Parcel state (atm_t, Sec. 4.4, plus the mesoscale state of `cache`).
+ * All pointers are device pointers to arrays of n elements.
+ *   lon, lat, p: double; id: uint32 (the Philox counter uses it);
+ *   up, vp, wp: double (MPT_MATH_F64) or float (MPT_MATH_F32);
+ *   scen: uint16 scenario index per parcel, or NULL (all active from step 0).
+ * The *2 set has the same types and is the target of mpt_sort_particles; it
+ * may be NULL when no sort is requested.  The two sets must not overlap. */
+typedef struct {
+    int64_t n;
+    double *lon, *lat, *p;
+    uint32_t *id;
+    void *up, *vp, *wp;
+    uint16_t *scen;
+    double *lon2, *lat2, *p2;
+    uint32_t *id2;
+    void *up2, *vp2, *wp2;
+    uint16_t *scen2;
+} mpt_particles;
+
+/* Bytes of device workspace needed for this grid and up to n_max parcels
+ * (met storage for nt levels, level table, sort scratch).  Returns 0 on
+ * invalid arguments. */
+size_t mpt_workspace_bytes(const mpt_grid *grid, const mpt_params *params, int64_t n_max);
+
+/* Create a context on the current HIP device.  dev_workspace: caller-owned
+ * device memory of ws_bytes >= mpt_workspace_bytes(grid, params, n_max),
+ * 256-byte aligned.  Copies the level table to the device synchronously.
+ * Returns MPT_ERR_HIP when no GPU is usable. */
+mpt_status mpt_create(const mpt_grid *grid, const mpt_params *params, int64_t n_max,
+                      void *dev_workspace, size_t ws_bytes, mpt_ctx **out);
+
+/* Store time level `level` (0 .. nt-1) from device arrays u, v, w of
+ * nz*ny*nx float each, index (k*ny + j)*nx + i, w in hPa/s (read_met,
+ * Sec. 3.1; the kernel layout packs {u,v,w,0} per grid point, lon fastest;
+ * BF16/F16 grids also compute the per-level scales).  The source arrays
+ * may be freed once the stream has passed this call. */
+mpt_status mpt_init_met(mpt_ctx *ctx, int32_t level, const float *u, const float *v,
+                        const float *w, void *hip_stream);
+
+/* Copy the stored (packed) time level into dst (device, at least
+ * mpt_met_level_bytes(ctx) bytes) and its scales into scales_dst (device,
+ * 3*nz floats, index var*nz + k; all 1 for F32 storage).  Packed layout:
+ * point (k, j, i) at element ((k*ny + j)*nx + i) of {u, v, w, 0} records of
+ * 4 x float (F32) or 4 x uint16 (BF16 / F16 bit patterns). */
+mpt_status mpt_copy_met_level(mpt_ctx *ctx, int32_t level, void *dst, float *scales_dst,
+                              void *hip_stream);
+size_t mpt_met_level_bytes(const mpt_ctx *ctx);
+
+/* Release steps of nscen scenarios (module_timesteps, Sec. 4.3): a parcel
+ * with scen[i] = s stays untouched while step < release_step[s].  Host
+ * array, copied; 1 <= nscen <= 65536.  Required before any call with
+ * particles->scen != NULL. */
+mpt_status mpt_set_release(mpt_ctx *ctx, int32_t nscen, const int32_t *release_step,
+                           void *hip_stream);
+
+/* Advection of every active parcel over step `step`: explicit midpoint
+ * with 4D interpolation, then the position fix (module_advection +
+ * module_position, Sec. 3.2).  In place on particles->lon/lat/p. */
+mpt_status mpt_advect(mpt_ctx *ctx, const mpt_particles *particles, uint32_t step,
+                      void *hip_stream);
+
+/* Turbulent then mesoscale diffusion over step `step`, then the position
+ * fix (module_diffusion_turb, module_diffusion_meso, module_position,
+ * Sec. 3.2; random numbers per Sec. 4.3).  Honours MPT_TURB / MPT_MESO of
+ * params.flags.  mpt_advect followed by mpt_diffuse equals one mpt_step
+ * without sorting, bit for bit. */
+mpt_status mpt_diffuse(mpt_ctx *ctx, const mpt_particles *particles, uint32_t step,
+                       void *hip_stream);
+
+/* Sort parcels by grid box: key = 8 x 8 x 4 (lon x lat x level) tile of
+ * the cell holding the parcel, tiles numbered lon fastest; parcels with
+ * non-finite positions go last.  Scatters the whole state into the *2 set
+ * and swaps the primary and *2 pointers inside *particles (the caller must
+ * re-read them).  Order inside a tile is unspecified.  Needs n <= n_max. */
+mpt_status mpt_sort_particles(mpt_ctx *ctx, mpt_particles *particles, void *hip_stream);
+
+/* nsteps time steps step0 .. step0+nsteps-1 (advection, turbulent and
+ * mesoscale diffusion per params.flags), sorting before every step that is
+ * a multiple of params.sort_interval (then the pointers in *particles are
+ * swapped as by mpt_sort_particles).  Consecutive steps between sorts are
+ * fused into launches of at most params.fuse steps. */
+mpt_status mpt_step(mpt_ctx *ctx, mpt_particles *particles, uint32_t step0, int32_t nsteps,
+                    void *hip_stream);
+
+/* Release the context (the workspace stays the caller's). */
+mpt_status mpt_destroy(mpt_ctx *ctx);
+
+/* Static description of a status code. */
+const char *mpt_status_string(mpt_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPT_H */

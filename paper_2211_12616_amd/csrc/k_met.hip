@@ -1,0 +1,119 @@
+// k_met.hip -- storing meteorological time levels in the kernel layout:
+// one {u, v, w, 0} record per grid point, longitude fastest, so that a cell
+// corner is one 16-byte (F32) or 8-byte (BF16 / F16) load.  Reduced
+// precision stores q = RNE(f * (1/s)) with s = max|f| per (variable, level).
+#include "mpt_internal.h"
+
+namespace mpt {
+
+__global__ __launch_bounds__(256) void k_pack_f32(const float *__restrict__ u,
+                                                  const float *__restrict__ v,
+                                                  const float *__restrict__ w,
+                                                  float4 *__restrict__ dst, int64_t npts) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < npts; q += stride)
+    dst[q] = make_float4(u[q], v[q], w[q], 0.0f);
+}
+
+// One block per (level k, variable): max |f| over the nx*ny points of that
+// level; a zero maximum is stored as scale 1 (then every q is 0).
+__global__ __launch_bounds__(256) void k_level_absmax(const float *__restrict__ u,
+                                                      const float *__restrict__ v,
+                                                      const float *__restrict__ w, int64_t nxy,
+                                                      int nz, float *__restrict__ scales) {
+  const int k = blockIdx.x, var = blockIdx.y;
+  const float *src = (var == 0 ? u : var == 1 ? v : w) + (int64_t)k * nxy;
+  float m = 0.0f;
+  for (int64_t q = threadIdx.x; q < nxy; q += blockDim.x) m = fmaxf(m, fabsf(src[q]));
+  __shared__ float red[256];
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) scales[var * nz + k] = red[0] > 0.0f ? red[0] : 1.0f;
+}
+
+__device__ __forceinline__ unsigned short to_bf16_rne(float x) {
+  uint32_t b = __float_as_uint(x);
+  b += 0x7FFFu + ((b >> 16) & 1u);
+  return (unsigned short)(b >> 16);
+}
+
+// The FP32 product is rounded first and only then converted: the empty asm
+// pins x as a 32-bit register value, which keeps the compiler from fusing
+// multiply and conversion into one mixed-precision FMA (a single rounding
+// of the exact product instead of the defined FP32-then-FP16 rounding).
+__device__ __forceinline__ unsigned short to_f16_rne(float x) {
+  asm volatile("" : "+v"(x));
+  return __builtin_bit_cast(unsigned short, (_Float16)x);
+}
+
+template <int F>
+__global__ __launch_bounds__(256) void k_pack_r16(const float *__restrict__ u,
+                                                  const float *__restrict__ v,
+                                                  const float *__restrict__ w,
+                                                  const float *__restrict__ scales,
+                                                  ushort4 *__restrict__ dst, int64_t nxy, int nz) {
+  const int64_t npts = nxy * nz;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < npts; q += stride) {
+    const int k = (int)(q / nxy);
+    const float iu = __fdiv_rn(1.0f, scales[k]);
+    const float iv = __fdiv_rn(1.0f, scales[nz + k]);
+    const float iw = __fdiv_rn(1.0f, scales[2 * nz + k]);
+    const float a = __fmul_rn(u[q], iu), b = __fmul_rn(v[q], iv), c = __fmul_rn(w[q], iw);
+    ushort4 r;
+    if (F == kBF16) {
+      r.x = to_bf16_rne(a); r.y = to_bf16_rne(b); r.z = to_bf16_rne(c);
+    } else {
+      r.x = to_f16_rne(a); r.y = to_f16_rne(b); r.z = to_f16_rne(c);
+    }
+    r.w = 0;
+    dst[q] = r;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_fill_f32(float *dst, float value, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) dst[q] = value;
+}
+
+static unsigned grid_for(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  if (b > 65536) b = 65536;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+hipError_t launch_pack_f32(const float *u, const float *v, const float *w, float4 *dst, int64_t npts,
+                           hipStream_t stream) {
+  hipLaunchKernelGGL(k_pack_f32, dim3(grid_for(npts)), dim3(256), 0, stream, u, v, w, dst, npts);
+  return hipGetLastError();
+}
+
+hipError_t launch_level_absmax(const float *u, const float *v, const float *w, int64_t nxy, int nz,
+                               float *scales, hipStream_t stream) {
+  hipLaunchKernelGGL(k_level_absmax, dim3((unsigned)nz, 3), dim3(256), 0, stream, u, v, w, nxy, nz,
+                     scales);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_r16(int field, const float *u, const float *v, const float *w,
+                           const float *scales, ushort4 *dst, int64_t nxy, int nz,
+                           hipStream_t stream) {
+  const unsigned g = grid_for(nxy * nz);
+  if (field == kBF16)
+    hipLaunchKernelGGL(k_pack_r16<kBF16>, dim3(g), dim3(256), 0, stream, u, v, w, scales, dst, nxy, nz);
+  else
+    hipLaunchKernelGGL(k_pack_r16<kF16>, dim3(g), dim3(256), 0, stream, u, v, w, scales, dst, nxy, nz);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f32(float *dst, float value, int64_t n, hipStream_t stream) {
+  hipLaunchKernelGGL(k_fill_f32, dim3(grid_for(n)), dim3(256), 0, stream, dst, value, n);
+  return hipGetLastError();
+}
+
+}  // namespace mpt

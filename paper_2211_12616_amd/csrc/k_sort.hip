@@ -1,0 +1,169 @@
+// k_sort.hip -- counting sort of parcels by grid-box tile: tile key and
+// histogram, exclusive scan of the histogram, scatter of the whole parcel
+// state into the second buffer set.  Parcels that are already nearly
+// sorted share keys across a wavefront, so both the histogram and the
+// scatter cursors are bumped once per run of equal keys within a wave.
+#include "mpt_internal.h"
+
+namespace mpt {
+
+constexpr int kScanChunk = 1024;   // entries per scan block (256 threads x 4)
+
+// For lanes holding `key` (valid lanes form a prefix of the wave), add the
+// length of each run of equal keys to counters[key] once and return, for
+// every lane, the old counter value plus the lane's rank inside its run.
+__device__ __forceinline__ uint32_t wave_run_add(uint32_t *counters, uint32_t key, bool valid) {
+  const int lane = (int)__lane_id();
+  const uint32_t prev = __shfl_up(key, 1);
+  const bool head = valid && (lane == 0 || prev != key);
+  const uint64_t heads = __ballot(head);
+  const uint64_t valids = __ballot(valid);
+  if (heads == 0) return 0;
+  const uint64_t le = heads & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull));
+  const int myhead = le ? 63 - __clzll((long long)le) : 0;
+  const uint64_t above = heads & (myhead == 63 ? 0ull : ~((2ull << myhead) - 1ull));
+  const int endl = above ? __ffsll((long long)above) - 1 : 64 - __clzll((long long)valids);
+  uint32_t base = 0;
+  if (head) base = atomicAdd(&counters[key], (uint32_t)(endl - myhead));
+  base = __shfl(base, myhead);
+  return base + (uint32_t)(lane - myhead);
+}
+
+__global__ __launch_bounds__(kBlock) void k_sort_keys(const SortArgs a) {
+  __shared__ double s_plev[kMaxLevels];
+  for (int q = threadIdx.x; q < a.nz; q += kBlock) s_plev[q] = a.plev[q];
+  __syncthreads();
+  const int lb = logical_block((int)blockIdx.x, a.per_xcd);
+  if (lb >= a.nblk) return;
+  const int64_t i = (int64_t)lb * kBlock + threadIdx.x;
+  const bool valid = i < a.n;
+  uint32_t key = 0xFFFFFFFFu;
+  if (valid) {
+    const double lon = a.lon[i], lat = a.lat[i], p = a.p[i];
+    if (!finite3(lon, lat, p)) {
+      key = a.nkeys - 1;
+    } else {
+      const double lam = lon - 360.0 * floor((lon - a.lon0) * (1.0 / 360.0));
+      int i0 = (int)floor((lam - a.lon0) * a.inv_dlon);
+      if (i0 >= a.nx) i0 -= a.nx;
+      if (i0 < 0) i0 += a.nx;
+      const double phi = fmin(fmax(lat, a.lat0), a.lat_hi);
+      int j = (int)floor((phi - a.lat0) * a.inv_dlat);
+      j = min(max(j, 0), a.ny - 2);
+      const double pc = fmin(fmax(p, a.p_top), a.p_bot);
+      int lo = 0, hi = a.nz - 2;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_plev[mid] >= pc) lo = mid; else hi = mid - 1;
+      }
+      key = ((uint32_t)(lo >> 2) * a.nty + (uint32_t)(j >> 3)) * a.ntx + (uint32_t)(i0 >> 3);
+    }
+    a.keys[i] = key;
+  }
+  wave_run_add(a.hist, key, valid);
+}
+
+// Exclusive scan, phase 1: each block scans kScanChunk entries in place
+// and records the chunk total.
+__global__ __launch_bounds__(256) void k_scan_local(uint32_t *data, uint32_t n, uint32_t *sums) {
+  __shared__ uint32_t s[256];
+  const uint32_t base = blockIdx.x * kScanChunk + threadIdx.x * 4;
+  uint32_t v[4];
+  uint32_t t = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    v[q] = (base + q < n) ? data[base + q] : 0u;
+    t += v[q];
+  }
+  s[threadIdx.x] = t;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {       // Hillis-Steele inclusive scan
+    const uint32_t x = ((int)threadIdx.x >= off) ? s[threadIdx.x - off] : 0u;
+    __syncthreads();
+    s[threadIdx.x] += x;
+    __syncthreads();
+  }
+  uint32_t run = s[threadIdx.x] - t;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (base + q < n) data[base + q] = run;
+    run += v[q];
+  }
+  if (threadIdx.x == 255) sums[blockIdx.x] = s[255];
+}
+
+// Phase 2: one block scans the chunk totals (any count) exclusively.
+__global__ __launch_bounds__(256) void k_scan_sums(uint32_t *sums, uint32_t nb) {
+  __shared__ uint32_t s[256];
+  uint32_t carry = 0;
+  for (uint32_t start = 0; start < nb; start += 256) {
+    const uint32_t q = start + threadIdx.x;
+    const uint32_t v = q < nb ? sums[q] : 0u;
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+      const uint32_t x = ((int)threadIdx.x >= off) ? s[threadIdx.x - off] : 0u;
+      __syncthreads();
+      s[threadIdx.x] += x;
+      __syncthreads();
+    }
+    if (q < nb) sums[q] = carry + s[threadIdx.x] - v;
+    const uint32_t total = s[255];
+    __syncthreads();
+    carry += total;
+  }
+}
+
+// Phase 3: add each chunk's prefix.
+__global__ __launch_bounds__(256) void k_scan_add(uint32_t *data, uint32_t n, const uint32_t *sums) {
+  const uint32_t add = sums[blockIdx.x];
+  const uint32_t base = blockIdx.x * kScanChunk + threadIdx.x * 4;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (base + q < n) data[base + q] += add;
+}
+
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t *dst, uint32_t n) {
+  for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) dst[q] = 0u;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sort_scatter(const ScatterArgs a) {
+  const int lb = logical_block((int)blockIdx.x, a.per_xcd);
+  if (lb >= a.nblk) return;
+  const int64_t i = (int64_t)lb * kBlock + threadIdx.x;
+  const bool valid = i < a.n;
+  const uint32_t key = valid ? a.keys[i] : 0xFFFFFFFFu;
+  const uint32_t pos = wave_run_add(a.cursor, key, valid);
+  if (!valid) return;
+  a.lon2[pos] = a.lon[i];
+  a.lat2[pos] = a.lat[i];
+  a.p2[pos] = a.p[i];
+  a.id2[pos] = a.id[i];
+  if (a.scen) a.scen2[pos] = a.scen[i];
+  if (a.meso_bytes == 8) {
+    static_cast<double *>(a.up2)[pos] = static_cast<const double *>(a.up)[i];
+    static_cast<double *>(a.vp2)[pos] = static_cast<const double *>(a.vp)[i];
+    static_cast<double *>(a.wp2)[pos] = static_cast<const double *>(a.wp)[i];
+  } else if (a.meso_bytes == 4) {
+    static_cast<float *>(a.up2)[pos] = static_cast<const float *>(a.up)[i];
+    static_cast<float *>(a.vp2)[pos] = static_cast<const float *>(a.vp)[i];
+    static_cast<float *>(a.wp2)[pos] = static_cast<const float *>(a.wp)[i];
+  }
+}
+
+size_t scan_block_sums_len(uint32_t nkeys) { return (nkeys + kScanChunk - 1) / kScanChunk; }
+
+hipError_t launch_sort(const SortArgs &sa, const ScatterArgs &xa, hipStream_t stream) {
+  const uint32_t nb = (uint32_t)scan_block_sums_len(sa.nkeys);
+  unsigned fill_grid = (sa.nkeys + 255) / 256;
+  if (fill_grid > 4096) fill_grid = 4096;
+  hipLaunchKernelGGL(k_fill_u32, dim3(fill_grid), dim3(256), 0, stream, sa.hist, sa.nkeys);
+  hipLaunchKernelGGL(k_sort_keys, dim3((unsigned)(sa.per_xcd * kXcds)), dim3(kBlock), 0, stream, sa);
+  hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(256), 0, stream, sa.hist, sa.nkeys, sa.block_sums);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(256), 0, stream, sa.block_sums, nb);
+  hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(256), 0, stream, sa.hist, sa.nkeys, sa.block_sums);
+  hipLaunchKernelGGL(k_sort_scatter, dim3((unsigned)(xa.per_xcd * kXcds)), dim3(kBlock), 0, stream, xa);
+  return hipGetLastError();
+}
+
+}  // namespace mpt

@@ -1,0 +1,78 @@
+// k_step.hip -- the fused particle time step (advection, position,
+// turbulent and mesoscale diffusion, position) for one or more steps per
+// launch, one parcel per thread, state held in registers across steps.
+#include "mpt_device.h"
+#include "mpt_internal.h"
+
+namespace mpt {
+
+template <int F, typename R>
+__global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
+  __shared__ double s_plev[kMaxLevels];
+  __shared__ double s_idp[kMaxLevels];
+  for (int q = threadIdx.x; q < a.nz; q += kBlock) {
+    s_plev[q] = a.plev[q];
+    s_idp[q] = (q < a.nz - 1) ? a.inv_dp[q] : 0.0;
+  }
+  __syncthreads();
+  const int lb = logical_block((int)blockIdx.x, a.per_xcd);
+  if (lb >= a.nblk) return;
+  const int64_t i = (int64_t)lb * kBlock + threadIdx.x;
+  if (i >= a.n) return;
+
+  double lon = a.lon[i], lat = a.lat[i], p = a.p[i];
+  if (!finite3(lon, lat, p)) return;
+  const uint32_t id = a.id[i];
+  int64_t rel = INT64_MIN;
+  if (a.scen) rel = a.release[a.scen[i]];
+  const bool do_meso = (a.flags & kMeso) != 0;
+  R up = 0, vp = 0, wp = 0;
+  if (do_meso) {
+    up = static_cast<const R *>(a.up)[i];
+    vp = static_cast<const R *>(a.vp)[i];
+    wp = static_cast<const R *>(a.wp)[i];
+  }
+  bool moved = false;
+  for (int s = 0; s < a.nsteps; ++s) {
+    const uint32_t step = a.step0 + (uint32_t)s;
+    if ((int64_t)step < rel) continue;
+    if (!finite3(lon, lat, p)) break;
+    moved = true;
+    const double t = a.t_start + (double)step * a.dt;
+    if (a.flags & kAdvect) {
+      advect<F, R>(a, s_plev, s_idp, t, lon, lat, p);
+      position(a, lon, lat, p);
+    }
+    if (a.flags & (kTurb | kMeso)) {
+      if (a.flags & kTurb) turb<R>(a, id, step, lon, lat, p);
+      if (do_meso) meso<F, R>(a, s_plev, s_idp, id, step, t + 0.5 * a.dt, lon, lat, p, up, vp, wp);
+      position(a, lon, lat, p);
+    }
+  }
+  if (!moved) return;
+  a.lon[i] = lon;
+  a.lat[i] = lat;
+  a.p[i] = p;
+  if (do_meso) {
+    static_cast<R *>(a.up)[i] = up;
+    static_cast<R *>(a.vp)[i] = vp;
+    static_cast<R *>(a.wp)[i] = wp;
+  }
+}
+
+hipError_t launch_step(int field, int math_f64, const StepArgs &args, hipStream_t stream) {
+  const dim3 grid((unsigned)(args.per_xcd * kXcds)), block(kBlock);
+  if (math_f64) {
+    if (field != kF32) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_step<kF32, double>), grid, block, 0, stream, args);
+  } else if (field == kF32) {
+    hipLaunchKernelGGL((k_step<kF32, float>), grid, block, 0, stream, args);
+  } else if (field == kBF16) {
+    hipLaunchKernelGGL((k_step<kBF16, float>), grid, block, 0, stream, args);
+  } else {
+    hipLaunchKernelGGL((k_step<kF16, float>), grid, block, 0, stream, args);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace mpt

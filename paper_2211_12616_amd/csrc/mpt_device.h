@@ -1,0 +1,408 @@
+// mpt_device.h -- device building blocks of the particle time step (gfx950).
+//
+// Internal to libmpt.  Everything here is compiled with -ffp-contract=off:
+// fused multiply-adds appear only where written as fma(), so the fused
+// multi-step kernel and the split advect / diffuse kernels execute the same
+// floating-point operations in the same order (bitwise-equal results).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mpt {
+
+// ---- constants of the method ------------------------------------------------
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kREarth = 6371000.0;                 // m
+constexpr double kH0 = 7000.0;                        // scale height, dz -> dp [m]
+constexpr double kDeg = 180.0 / (kPi * kREarth);      // metres -> degrees of arc
+constexpr int kMaxLevels = 512;                       // LDS level table capacity
+constexpr int kBlock = 256;                           // 4 wave64 per block
+constexpr int kXcds = 8;                              // MI355X: 8 XCDs, 32 CUs each
+
+enum : uint32_t { kAdvect = 1u, kTurb = 2u, kMeso = 4u };
+enum FieldKind { kF32 = 0, kBF16 = 1, kF16 = 2 };
+
+// Arguments of the step kernels, passed by value.
+struct StepArgs {
+  double *lon, *lat, *p;
+  const uint32_t *id;
+  void *up, *vp, *wp;
+  const uint16_t *scen;        // may be null
+  const int32_t *release;      // per scenario, device; null when scen is null
+  int64_t n;
+
+  const void *met;             // packed levels, level l at met + l*level_elems records
+  int64_t level_elems;         // nx*ny*nz
+  const float *scales;         // [nt][3][nz] (R16 storage)
+  const double *plev;          // [nz] device
+  const double *inv_dp;        // [nz-1] 1 / (plev[k] - plev[k+1])
+  int nx, ny, nz, nt;
+  double lon0, inv_dlon, lat0, inv_dlat, lat_hi, p_top, p_bot;
+  double t_met0, dt_met, inv_dt_met;
+
+  double dt, t_start;
+  double sig_h, sig_z;         // sqrt(2 D dt) [m]
+  double r_ar, rs_fh, rs_fv;   // AR(1): r, sqrt(1-r^2)*fh, sqrt(1-r^2)*fv
+  double cos_cap;              // cos(89.999 deg)
+  uint64_t seed;
+  uint32_t step0;
+  int32_t nsteps;
+  uint32_t flags;
+  int32_t nblk;                // logical blocks
+  int32_t per_xcd;             // logical blocks per XCD
+};
+
+// Map the hardware block index to a logical block so that each XCD walks a
+// contiguous range of (sorted) parcels: hardware dispatch is round-robin
+// over the XCDs, so block b runs on XCD b % 8.
+__device__ __forceinline__ int logical_block(int b, int per_xcd) {
+  return (b % kXcds) * per_xcd + b / kXcds;
+}
+
+// ---- Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) ----------------------
+__device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                              uint32_t k0, uint32_t k1, uint32_t out[4]) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c0 = n0;
+    c1 = (uint32_t)p1;
+    c2 = n2;
+    c3 = (uint32_t)p0;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+template <typename R> struct Math;
+
+template <> struct Math<double> {
+  static __device__ __forceinline__ double uni(uint32_t x) {
+    return ((double)(x >> 8) + 0.5) * (1.0 / 16777216.0);
+  }
+  static __device__ __forceinline__ double log_(double x) { return log(x); }
+  static __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
+  static __device__ __forceinline__ double cos_(double x) { return cos(x); }
+  static __device__ __forceinline__ void sincos_(double x, double *s, double *c) { sincos(x, s, c); }
+  static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+};
+
+template <> struct Math<float> {
+  static __device__ __forceinline__ float uni(uint32_t x) {
+    return ((float)(x >> 8) + 0.5f) * (1.0f / 16777216.0f);
+  }
+  static __device__ __forceinline__ float log_(float x) { return __logf(x); }
+  static __device__ __forceinline__ float sqrt_(float x) { return __fsqrt_rn(x); }
+  static __device__ __forceinline__ float cos_(float x) { return __cosf(x); }
+  static __device__ __forceinline__ void sincos_(float x, float *s, float *c) { __sincosf(x, s, c); }
+  static __device__ __forceinline__ float rcp(float x) { return __frcp_rn(x); }
+};
+
+// Three standard normals for (id, step, purpose): Box-Muller on one Philox
+// block, uniforms ((x >> 8) + 1/2) / 2^24.
+template <typename R>
+__device__ __forceinline__ void normals3(uint64_t seed, uint32_t id, uint32_t step, uint32_t purpose,
+                                         R xi[3]) {
+  uint32_t x[4];
+  philox4x32_10(id, step, purpose, 0u, (uint32_t)seed, (uint32_t)(seed >> 32), x);
+  const R u0 = Math<R>::uni(x[0]), u1 = Math<R>::uni(x[1]);
+  const R u2 = Math<R>::uni(x[2]), u3 = Math<R>::uni(x[3]);
+  const R twopi = (R)(2.0 * kPi);
+  const R r0 = Math<R>::sqrt_((R)-2 * Math<R>::log_(u0));
+  const R r1 = Math<R>::sqrt_((R)-2 * Math<R>::log_(u2));
+  R s1, c1;
+  Math<R>::sincos_(twopi * u1, &s1, &c1);
+  xi[0] = r0 * c1;
+  xi[1] = r0 * s1;
+  xi[2] = r1 * Math<R>::cos_(twopi * u3);
+}
+
+// ---- field records -----------------------------------------------------------
+template <int F> struct Rec;
+template <> struct Rec<kF32> { using T = float4; };
+template <> struct Rec<kBF16> { using T = ushort4; };
+template <> struct Rec<kF16> { using T = ushort4; };
+
+template <int F> __device__ __forceinline__ float dec(unsigned short q);
+template <> __device__ __forceinline__ float dec<kBF16>(unsigned short q) {
+  return __uint_as_float((uint32_t)q << 16);
+}
+template <> __device__ __forceinline__ float dec<kF16>(unsigned short q) {
+  return (float)__builtin_bit_cast(_Float16, q);
+}
+
+// The three stored values of one grid point as R (decoded with the scales of
+// its (level, time level) for R16 storage).
+template <int F, typename R>
+struct Fetch {
+  static __device__ __forceinline__ void get(const typename Rec<F>::T &v, const float *sc, R o[3]) {
+    o[0] = (R)(dec<F>(v.x) * sc[0]);
+    o[1] = (R)(dec<F>(v.y) * sc[1]);
+    o[2] = (R)(dec<F>(v.z) * sc[2]);
+  }
+};
+template <typename R>
+struct Fetch<kF32, R> {
+  static __device__ __forceinline__ void get(const float4 &v, const float *, R o[3]) {
+    o[0] = (R)v.x;
+    o[1] = (R)v.y;
+    o[2] = (R)v.z;
+  }
+};
+
+// ---- locate ----------------------------------------------------------------------
+template <typename R>
+struct Loc {
+  int i0, i1, j, k, l;
+  R fx, fy, fz, ft;
+};
+
+// Horizontal and vertical part of the cell location.  Longitude periodic,
+// latitude and pressure clamped; k = largest index <= nz-2 with
+// plev[k] >= p (binary search in the LDS copy of the level table).
+template <typename R>
+__device__ __forceinline__ void locate_xyz(const StepArgs &a, const double *s_plev,
+                                           const double *s_idp, double lon, double lat, double p,
+                                           Loc<R> &L) {
+  const double lam = lon - 360.0 * floor((lon - a.lon0) * (1.0 / 360.0));
+  const double x = (lam - a.lon0) * a.inv_dlon;
+  const double xf = floor(x);
+  int i0 = (int)xf;
+  if (i0 >= a.nx) i0 -= a.nx;
+  if (i0 < 0) i0 += a.nx;
+  L.i0 = i0;
+  L.i1 = (i0 + 1 == a.nx) ? 0 : i0 + 1;
+  L.fx = (R)(x - xf);
+
+  const double phi = fmin(fmax(lat, a.lat0), a.lat_hi);
+  const double y = (phi - a.lat0) * a.inv_dlat;
+  int j = (int)floor(y);
+  j = min(max(j, 0), a.ny - 2);
+  L.j = j;
+  L.fy = (R)(y - (double)j);
+
+  const double pc = fmin(fmax(p, a.p_top), a.p_bot);
+  int lo = 0, hi = a.nz - 2;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (s_plev[mid] >= pc) lo = mid; else hi = mid - 1;
+  }
+  L.k = lo;
+  L.fz = (R)((s_plev[lo] - pc) * s_idp[lo]);
+}
+
+// Time-level pair bracketing t and the weight of the later level.
+template <typename R>
+__device__ __forceinline__ void locate_t(const StepArgs &a, double t, Loc<R> &L) {
+  double tl = floor((t - a.t_met0) * a.inv_dt_met);
+  int l = (int)tl;
+  if (tl < 0.0) l = 0;
+  if (l > a.nt - 2) l = a.nt - 2;
+  L.l = l;
+  L.ft = (R)((t - (a.t_met0 + (double)l * a.dt_met)) * a.inv_dt_met);
+}
+
+template <typename R>
+__device__ __forceinline__ R lerp(R a, R b, R f) { return fma(f, b - a, a); }
+
+// Gather the 16 records (2 time levels x 2 levels x 2 rows x 2 columns) of
+// the cell and return the values of all three variables: v[dl][dk][dj][di][var].
+template <int F, typename R>
+__device__ __forceinline__ void gather16(const StepArgs &a, const Loc<R> &L, R v[2][2][2][2][3]) {
+  using T = typename Rec<F>::T;
+  const T *base = reinterpret_cast<const T *>(a.met);
+  const int nxy = a.nx * a.ny;
+  const int r0 = L.k * nxy + L.j * a.nx;
+  T rec[2][2][2][2];
+#pragma unroll
+  for (int dl = 0; dl < 2; ++dl) {
+    const T *lev = base + (int64_t)(L.l + dl) * a.level_elems;
+#pragma unroll
+    for (int dk = 0; dk < 2; ++dk)
+#pragma unroll
+      for (int dj = 0; dj < 2; ++dj) {
+        const T *row = lev + r0 + dk * nxy + dj * a.nx;
+        rec[dl][dk][dj][0] = row[L.i0];
+        rec[dl][dk][dj][1] = row[L.i1];
+      }
+  }
+#pragma unroll
+  for (int dl = 0; dl < 2; ++dl)
+#pragma unroll
+    for (int dk = 0; dk < 2; ++dk) {
+      float sc[3] = {1.f, 1.f, 1.f};
+      if (F != kF32) {
+        const float *s = a.scales + (int64_t)(L.l + dl) * 3 * a.nz + (L.k + dk);
+        sc[0] = s[0];
+        sc[1] = s[a.nz];
+        sc[2] = s[2 * a.nz];
+      }
+#pragma unroll
+      for (int dj = 0; dj < 2; ++dj)
+#pragma unroll
+        for (int di = 0; di < 2; ++di) Fetch<F, R>::get(rec[dl][dk][dj][di], sc, v[dl][dk][dj][di]);
+    }
+}
+
+// Quadrilinear interpolation: along lon, then lat, then p, at both time
+// levels, then in time.
+template <typename R>
+__device__ __forceinline__ void interp16(const R v[2][2][2][2][3], const Loc<R> &L, R out[3]) {
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    R zl[2];
+#pragma unroll
+    for (int dl = 0; dl < 2; ++dl) {
+      R yk[2];
+#pragma unroll
+      for (int dk = 0; dk < 2; ++dk) {
+        const R x0 = lerp(v[dl][dk][0][0][q], v[dl][dk][0][1][q], L.fx);
+        const R x1 = lerp(v[dl][dk][1][0][q], v[dl][dk][1][1][q], L.fx);
+        yk[dk] = lerp(x0, x1, L.fy);
+      }
+      zl[dl] = lerp(yk[0], yk[1], L.fz);
+    }
+    out[q] = lerp(zl[0], zl[1], L.ft);
+  }
+}
+
+// Population standard deviation (two-pass) of the 16 values of each variable.
+template <typename R>
+__device__ __forceinline__ void sigma16(const R v[2][2][2][2][3], R out[3]) {
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    R s = 0;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) s += v[c >> 3][(c >> 2) & 1][(c >> 1) & 1][c & 1][q];
+    const R mean = s * (R)(1.0 / 16.0);
+    R ss = 0;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      const R d = v[c >> 3][(c >> 2) & 1][(c >> 1) & 1][c & 1][q] - mean;
+      ss = fma(d, d, ss);
+    }
+    const R var = ss * (R)(1.0 / 16.0);
+    out[q] = Math<R>::sqrt_(var > (R)0 ? var : (R)0);
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ R cos_floor(const StepArgs &a, double lat) {
+  const R c = Math<R>::cos_((R)(lat * (kPi / 180.0)));
+  return c > (R)a.cos_cap ? c : (R)a.cos_cap;
+}
+
+// ---- modules -----------------------------------------------------------------------
+
+// Explicit midpoint: x_mid = x + dt/2 f(x, t); x' = x + dt f(x_mid, t + dt/2),
+// f = (u / (R cos lat), v / R, omega) in degrees and hPa per second.
+template <int F, typename R>
+__device__ __forceinline__ void advect(const StepArgs &a, const double *s_plev, const double *s_idp,
+                                       double t, double &lon, double &lat, double &p) {
+  R v[2][2][2][2][3];
+  R w0[3], w1[3];
+  Loc<R> L;
+  locate_xyz<R>(a, s_plev, s_idp, lon, lat, p, L);
+  locate_t<R>(a, t, L);
+  gather16<F, R>(a, L, v);
+  interp16<R>(v, L, w0);
+  const R hdt = (R)(0.5 * a.dt);
+  const R kdeg = (R)kDeg;
+  const R d0lon = w0[0] * kdeg * Math<R>::rcp(cos_floor<R>(a, lat));
+  const R d0lat = w0[1] * kdeg;
+  const double lonm = lon + (double)(hdt * d0lon);
+  const double latm = lat + (double)(hdt * d0lat);
+  const double pm = p + (double)(hdt * w0[2]);
+
+  locate_xyz<R>(a, s_plev, s_idp, lonm, latm, pm, L);
+  locate_t<R>(a, t + 0.5 * a.dt, L);
+  gather16<F, R>(a, L, v);
+  interp16<R>(v, L, w1);
+  const R fdt = (R)a.dt;
+  const R d1lon = w1[0] * kdeg * Math<R>::rcp(cos_floor<R>(a, latm));
+  const R d1lat = w1[1] * kdeg;
+  lon = lon + (double)(fdt * d1lon);
+  lat = lat + (double)(fdt * d1lat);
+  p = p + (double)(fdt * w1[2]);
+}
+
+// Reflect over the poles, wrap lon to [0, 360), clamp p.  Equal to
+// fmod-based wrapping for every input (the short path is exact for
+// -360 < lon < 720).
+__device__ __forceinline__ void position(const StepArgs &a, double &lon, double &lat, double &p) {
+  if (lat > 90.0) {
+    lat = 180.0 - lat;
+    lon = lon + 180.0;
+  } else if (lat < -90.0) {
+    lat = -180.0 - lat;
+    lon = lon + 180.0;
+  }
+  double x = lon;
+  if (x >= 720.0 || x <= -360.0) x = fmod(x, 360.0);
+  else if (x >= 360.0) x = x - 360.0;
+  if (x < 0.0) x = x + 360.0;
+  if (x >= 360.0) x = 0.0;
+  lon = x;
+  p = fmin(fmax(p, a.p_top), a.p_bot);
+}
+
+// Fickian random walk: sigma_h = sqrt(2 Dx dt), sigma_z = sqrt(2 Dz dt) [m];
+// dp = -p dz / H0.
+template <typename R>
+__device__ __forceinline__ void turb(const StepArgs &a, uint32_t id, uint32_t step, double &lon,
+                                     double &lat, double &p) {
+  R xi[3];
+  normals3<R>(a.seed, id, step, 0u, xi);
+  const R kdeg = (R)kDeg;
+  const R dx = (R)a.sig_h * xi[0];
+  const R dy = (R)a.sig_h * xi[1];
+  const R dz = (R)a.sig_z * xi[2];
+  const R dlon = dx * kdeg * Math<R>::rcp(cos_floor<R>(a, lat));
+  const R dlat = dy * kdeg;
+  const R dp = -dz * (R)p * (R)(1.0 / kH0);
+  lon = lon + (double)dlon;
+  lat = lat + (double)dlat;
+  p = p + (double)dp;
+}
+
+// AR(1) sub-grid wind from the spread of the 16 values of the current cell
+// at the time-level pair of the step's midpoint time, then displacement.
+template <int F, typename R>
+__device__ __forceinline__ void meso(const StepArgs &a, const double *s_plev, const double *s_idp,
+                                     uint32_t id, uint32_t step, double t_mid, double &lon,
+                                     double &lat, double &p, R &up, R &vp, R &wp) {
+  R xi[3];
+  normals3<R>(a.seed, id, step, 1u, xi);
+  R v[2][2][2][2][3];
+  Loc<R> L;
+  locate_xyz<R>(a, s_plev, s_idp, lon, lat, p, L);
+  locate_t<R>(a, t_mid, L);
+  gather16<F, R>(a, L, v);
+  R sg[3];
+  sigma16<R>(v, sg);
+  const R r = (R)a.r_ar;
+  up = fma(r, up, (R)a.rs_fh * sg[0] * xi[0]);
+  vp = fma(r, vp, (R)a.rs_fh * sg[1] * xi[1]);
+  wp = fma(r, wp, (R)a.rs_fv * sg[2] * xi[2]);
+  const R fdt = (R)a.dt;
+  const R kdeg = (R)kDeg;
+  const R dlon = up * fdt * kdeg * Math<R>::rcp(cos_floor<R>(a, lat));
+  const R dlat = vp * fdt * kdeg;
+  const R dp = wp * fdt;
+  lon = lon + (double)dlon;
+  lat = lat + (double)dlat;
+  p = p + (double)dp;
+}
+
+__device__ __forceinline__ bool finite3(double a, double b, double c) {
+  return isfinite(a) && isfinite(b) && isfinite(c);
+}
+
+}  // namespace mpt

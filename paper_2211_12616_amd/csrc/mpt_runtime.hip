@@ -1,0 +1,443 @@
+// mpt_runtime.hip -- host side of libmpt: argument validation, workspace
+// carving, launch configuration, sort cadence.  Implements include/mpt.h.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+
+#include "../../include/mpt.h"
+#include "mpt_internal.h"
+
+using namespace mpt;
+
+struct mpt_ctx {
+  mpt_grid grid;
+  mpt_params params;
+  int device;
+  int64_t n_max;
+  // workspace carve-out (device)
+  unsigned char *ws;
+  size_t ws_bytes;
+  void *met;              // nt levels
+  size_t level_bytes;     // bytes per packed level
+  int64_t npts;
+  float *scales;          // [nt][3][nz]
+  double *plev, *inv_dp;  // [nz]
+  int32_t *release;       // [kMaxScen]
+  uint32_t *keys, *hist, *block_sums;
+  uint32_t ntx, nty, ntz, nkeys;
+  // host state
+  double plev_h[kMaxLevels];
+  uint64_t levels_ready;  // bit l set once level l was stored (nt <= 64)
+  int32_t nscen;
+};
+
+namespace {
+
+constexpr int kMaxScen = 65536;
+constexpr int kMaxTimeLevels = 64;
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+size_t rec_bytes(int dtype) { return dtype == MPT_DT_F32 ? 16 : 8; }
+
+mpt_status check_grid(const mpt_grid *g) {
+  if (!g || !g->plev) return MPT_ERR_ARG;
+  if (g->nx < 2 || g->ny < 3 || g->nz < 2 || g->nt < 2) return MPT_ERR_ARG;
+  if (g->nz > kMaxLevels || g->nt > kMaxTimeLevels) return MPT_ERR_UNSUPPORTED;
+  if ((int64_t)g->nx * g->ny * g->nz >= ((int64_t)1 << 31)) return MPT_ERR_UNSUPPORTED;
+  if (g->dtype < MPT_DT_F32 || g->dtype > MPT_DT_F16 || g->reserved != 0) return MPT_ERR_ARG;
+  if (!(g->dlon > 0) || fabs(g->nx * g->dlon - 360.0) > 1e-9) return MPT_ERR_ARG;
+  if (!(g->dlat > 0) || fabs(g->lat0 + 90.0) > 1e-12 ||
+      fabs(g->lat0 + (g->ny - 1) * g->dlat - 90.0) > 1e-9)
+    return MPT_ERR_ARG;
+  if (!isfinite(g->lon0) || !isfinite(g->t_met0) || !(g->dt_met > 0) || !isfinite(g->dt_met))
+    return MPT_ERR_ARG;
+  for (int k = 0; k < g->nz; ++k) {
+    if (!isfinite(g->plev[k]) || !(g->plev[k] > 0)) return MPT_ERR_ARG;
+    if (k > 0 && !(g->plev[k] < g->plev[k - 1])) return MPT_ERR_ARG;
+  }
+  return MPT_OK;
+}
+
+mpt_status check_params(const mpt_params *p, const mpt_grid *g) {
+  if (!p) return MPT_ERR_ARG;
+  if (!(p->dt > 0) || !isfinite(p->dt) || !isfinite(p->t_start)) return MPT_ERR_ARG;
+  if (!(p->turb_dx >= 0) || !(p->turb_dz >= 0) || !(p->meso_fh >= 0) || !(p->meso_fv >= 0))
+    return MPT_ERR_ARG;
+  if (!isfinite(p->turb_dx) || !isfinite(p->turb_dz) || !isfinite(p->meso_fh) || !isfinite(p->meso_fv))
+    return MPT_ERR_ARG;
+  if (p->sort_interval < 0 || p->fuse < 1) return MPT_ERR_ARG;
+  if (p->math != MPT_MATH_F64 && p->math != MPT_MATH_F32) return MPT_ERR_ARG;
+  if (p->flags & ~(uint32_t)(MPT_ADVECT | MPT_TURB | MPT_MESO)) return MPT_ERR_ARG;
+  if (p->math == MPT_MATH_F64 && g->dtype != MPT_DT_F32) return MPT_ERR_UNSUPPORTED;
+  return MPT_OK;
+}
+
+struct Layout {
+  size_t met, scales, plev, inv_dp, release, keys, hist, block_sums, total;
+  uint32_t ntx, nty, ntz, nkeys;
+};
+
+Layout layout(const mpt_grid *g, int64_t n_max) {
+  Layout L;
+  const size_t npts = (size_t)g->nx * g->ny * g->nz;
+  L.ntx = (uint32_t)((g->nx + 7) / 8);
+  L.nty = (uint32_t)((g->ny - 1 + 7) / 8);
+  L.ntz = (uint32_t)((g->nz - 1 + 3) / 4);
+  L.nkeys = L.ntx * L.nty * L.ntz + 1;
+  size_t off = 0;
+  L.met = off;        off += align_up(npts * rec_bytes(g->dtype) * g->nt);
+  L.scales = off;     off += align_up(sizeof(float) * 3 * g->nz * g->nt);
+  L.plev = off;       off += align_up(sizeof(double) * g->nz);
+  L.inv_dp = off;     off += align_up(sizeof(double) * g->nz);
+  L.release = off;    off += align_up(sizeof(int32_t) * kMaxScen);
+  L.keys = off;       off += align_up(sizeof(uint32_t) * (size_t)(n_max > 0 ? n_max : 0));
+  L.hist = off;       off += align_up(sizeof(uint32_t) * L.nkeys);
+  L.block_sums = off; off += align_up(sizeof(uint32_t) * scan_block_sums_len(L.nkeys));
+  L.total = off;
+  return L;
+}
+
+mpt_status from_hip(hipError_t e) { return e == hipSuccess ? MPT_OK : MPT_ERR_HIP; }
+
+void fill_step_args(const mpt_ctx *c, const mpt_particles *P, uint32_t step0, int nsteps,
+                    uint32_t flags, StepArgs &a) {
+  const mpt_grid &g = c->grid;
+  const mpt_params &q = c->params;
+  a.lon = P->lon; a.lat = P->lat; a.p = P->p; a.id = P->id;
+  a.up = P->up; a.vp = P->vp; a.wp = P->wp;
+  a.scen = P->scen;
+  a.release = P->scen ? c->release : nullptr;
+  a.n = P->n;
+  a.met = c->met;
+  a.level_elems = c->npts;
+  a.scales = c->scales;
+  a.plev = c->plev;
+  a.inv_dp = c->inv_dp;
+  a.nx = g.nx; a.ny = g.ny; a.nz = g.nz; a.nt = g.nt;
+  a.lon0 = g.lon0; a.inv_dlon = 1.0 / g.dlon;
+  a.lat0 = g.lat0; a.inv_dlat = 1.0 / g.dlat;
+  a.lat_hi = g.lat0 + (g.ny - 1) * g.dlat;
+  a.p_top = c->plev_h[g.nz - 1];
+  a.p_bot = c->plev_h[0];
+  a.t_met0 = g.t_met0; a.dt_met = g.dt_met; a.inv_dt_met = 1.0 / g.dt_met;
+  a.dt = q.dt; a.t_start = q.t_start;
+  a.sig_h = sqrt(2.0 * q.turb_dx * q.dt);
+  a.sig_z = sqrt(2.0 * q.turb_dz * q.dt);
+  double r = 1.0 - 2.0 * q.dt / g.dt_met;
+  if (r < 0.0) r = 0.0;
+  const double rs = sqrt(1.0 - r * r);
+  a.r_ar = r;
+  a.rs_fh = rs * q.meso_fh;
+  a.rs_fv = rs * q.meso_fv;
+  a.cos_cap = cos(89.999 * kPi / 180.0);
+  a.seed = q.seed;
+  a.step0 = step0;
+  a.nsteps = nsteps;
+  a.flags = flags;
+  const int64_t nblk = (P->n + kBlock - 1) / kBlock;
+  a.nblk = (int32_t)nblk;
+  a.per_xcd = (int32_t)((nblk + kXcds - 1) / kXcds);
+}
+
+mpt_status check_particles(const mpt_ctx *c, const mpt_particles *P, bool need_pingpong) {
+  if (!P) return MPT_ERR_ARG;
+  if (P->n < 0) return MPT_ERR_ARG;
+  if (P->n > ((int64_t)1 << 31) * kBlock / 2) return MPT_ERR_UNSUPPORTED;
+  if (P->n == 0) return MPT_OK;
+  const size_t ms = c->params.math == MPT_MATH_F64 ? 8 : 4;
+  const bool meso = (c->params.flags & MPT_MESO) != 0;
+  if (!P->lon || !P->lat || !P->p || !P->id) return MPT_ERR_ARG;
+  if (!aligned(P->lon, 8) || !aligned(P->lat, 8) || !aligned(P->p, 8) || !aligned(P->id, 4))
+    return MPT_ERR_ARG;
+  if (meso || need_pingpong) {
+    if (!P->up || !P->vp || !P->wp) return MPT_ERR_ARG;
+    if (!aligned(P->up, ms) || !aligned(P->vp, ms) || !aligned(P->wp, ms)) return MPT_ERR_ARG;
+  }
+  if (P->scen) {
+    if (!aligned(P->scen, 2)) return MPT_ERR_ARG;
+    if (c->nscen <= 0) return MPT_ERR_STATE;
+  }
+  if (need_pingpong) {
+    if (P->n > c->n_max) return MPT_ERR_WORKSPACE;
+    if (!P->lon2 || !P->lat2 || !P->p2 || !P->id2 || !P->up2 || !P->vp2 || !P->wp2)
+      return MPT_ERR_ARG;
+    if (!aligned(P->lon2, 8) || !aligned(P->lat2, 8) || !aligned(P->p2, 8) || !aligned(P->id2, 4) ||
+        !aligned(P->up2, ms) || !aligned(P->vp2, ms) || !aligned(P->wp2, ms))
+      return MPT_ERR_ARG;
+    if (P->scen && (!P->scen2 || !aligned(P->scen2, 2))) return MPT_ERR_ARG;
+    if (P->lon2 == P->lon || P->id2 == P->id) return MPT_ERR_ARG;
+  }
+  return MPT_OK;
+}
+
+// Every step in [step0, step0 + nsteps) must lie inside the resident levels.
+mpt_status check_time(const mpt_ctx *c, uint32_t step0, int64_t nsteps) {
+  if (nsteps < 0) return MPT_ERR_ARG;
+  if (nsteps == 0) return MPT_OK;
+  if ((uint64_t)step0 + (uint64_t)nsteps - 1 > 0xFFFFFFFFull) return MPT_ERR_ARG;
+  const mpt_grid &g = c->grid;
+  const double t_lo = g.t_met0, t_hi = g.t_met0 + (g.nt - 1) * g.dt_met;
+  const double eps = 1e-9 * g.dt_met;
+  const double t_first = c->params.t_start + (double)step0 * c->params.dt;
+  const double t_last_end = c->params.t_start + (double)(step0 + (uint64_t)nsteps - 1) * c->params.dt +
+                            c->params.dt;
+  if (t_first < t_lo - eps || t_last_end > t_hi + eps) return MPT_ERR_TIME;
+  const uint64_t all = (g.nt >= 64) ? ~0ull : ((1ull << g.nt) - 1ull);
+  if ((c->levels_ready & all) != all) return MPT_ERR_STATE;
+  return MPT_OK;
+}
+
+mpt_status do_sort(mpt_ctx *c, mpt_particles *P, hipStream_t s) {
+  const mpt_grid &g = c->grid;
+  SortArgs sa;
+  sa.lon = P->lon; sa.lat = P->lat; sa.p = P->p;
+  sa.plev = c->plev; sa.inv_dp = c->inv_dp;
+  sa.nx = g.nx; sa.ny = g.ny; sa.nz = g.nz;
+  sa.lon0 = g.lon0; sa.inv_dlon = 1.0 / g.dlon;
+  sa.lat0 = g.lat0; sa.inv_dlat = 1.0 / g.dlat;
+  sa.lat_hi = g.lat0 + (g.ny - 1) * g.dlat;
+  sa.p_top = c->plev_h[g.nz - 1]; sa.p_bot = c->plev_h[0];
+  sa.ntx = c->ntx; sa.nty = c->nty; sa.ntz = c->ntz; sa.nkeys = c->nkeys;
+  sa.n = P->n;
+  sa.keys = c->keys; sa.hist = c->hist; sa.block_sums = c->block_sums;
+  const int64_t nblk = (P->n + kBlock - 1) / kBlock;
+  sa.nblk = (int)nblk;
+  sa.per_xcd = (int)((nblk + kXcds - 1) / kXcds);
+  ScatterArgs xa;
+  xa.n = P->n; xa.keys = c->keys; xa.cursor = c->hist;
+  xa.lon = P->lon; xa.lat = P->lat; xa.p = P->p; xa.id = P->id;
+  xa.up = P->up; xa.vp = P->vp; xa.wp = P->wp; xa.scen = P->scen;
+  xa.lon2 = P->lon2; xa.lat2 = P->lat2; xa.p2 = P->p2; xa.id2 = P->id2;
+  xa.up2 = P->up2; xa.vp2 = P->vp2; xa.wp2 = P->wp2; xa.scen2 = P->scen2;
+  xa.meso_bytes = c->params.math == MPT_MATH_F64 ? 8 : 4;
+  xa.nblk = sa.nblk; xa.per_xcd = sa.per_xcd;
+  const mpt_status st = from_hip(launch_sort(sa, xa, s));
+  if (st != MPT_OK) return st;
+  // the sorted state now lives in the *2 set: swap the sets
+  double *t;
+  t = P->lon; P->lon = P->lon2; P->lon2 = t;
+  t = P->lat; P->lat = P->lat2; P->lat2 = t;
+  t = P->p; P->p = P->p2; P->p2 = t;
+  uint32_t *ti = P->id; P->id = P->id2; P->id2 = ti;
+  void *tv;
+  tv = P->up; P->up = P->up2; P->up2 = tv;
+  tv = P->vp; P->vp = P->vp2; P->vp2 = tv;
+  tv = P->wp; P->wp = P->wp2; P->wp2 = tv;
+  uint16_t *ts = P->scen; P->scen = P->scen2; P->scen2 = ts;
+  return MPT_OK;
+}
+
+mpt_status run_steps(mpt_ctx *c, const mpt_particles *P, uint32_t step0, int nsteps, uint32_t flags,
+                     hipStream_t s) {
+  StepArgs a;
+  fill_step_args(c, P, step0, nsteps, flags, a);
+  return from_hip(launch_step(c->grid.dtype, c->params.math == MPT_MATH_F64, a, s));
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t mpt_workspace_bytes(const mpt_grid *grid, const mpt_params *params, int64_t n_max) {
+  if (check_grid(grid) != MPT_OK || check_params(params, grid) != MPT_OK || n_max < 0) return 0;
+  return layout(grid, n_max).total;
+}
+
+mpt_status mpt_create(const mpt_grid *grid, const mpt_params *params, int64_t n_max,
+                      void *dev_workspace, size_t ws_bytes, mpt_ctx **out) {
+  if (!out) return MPT_ERR_ARG;
+  *out = nullptr;
+  mpt_status st = check_grid(grid);
+  if (st != MPT_OK) return st;
+  st = check_params(params, grid);
+  if (st != MPT_OK) return st;
+  if (n_max < 0) return MPT_ERR_ARG;
+  if (!dev_workspace || !aligned(dev_workspace, 256)) return MPT_ERR_ARG;
+  const Layout L = layout(grid, n_max);
+  if (ws_bytes < L.total) return MPT_ERR_WORKSPACE;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return MPT_ERR_HIP;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return MPT_ERR_HIP;
+
+  mpt_ctx *c = new (std::nothrow) mpt_ctx();
+  if (!c) return MPT_ERR_HIP;
+  c->grid = *grid;
+  c->params = *params;
+  c->device = dev;
+  c->n_max = n_max;
+  for (int k = 0; k < grid->nz; ++k) c->plev_h[k] = grid->plev[k];
+  c->grid.plev = c->plev_h;
+  unsigned char *ws = static_cast<unsigned char *>(dev_workspace);
+  c->ws = ws;
+  c->ws_bytes = ws_bytes;
+  c->npts = (int64_t)grid->nx * grid->ny * grid->nz;
+  c->level_bytes = (size_t)c->npts * rec_bytes(grid->dtype);
+  c->met = ws + L.met;
+  c->scales = reinterpret_cast<float *>(ws + L.scales);
+  c->plev = reinterpret_cast<double *>(ws + L.plev);
+  c->inv_dp = reinterpret_cast<double *>(ws + L.inv_dp);
+  c->release = reinterpret_cast<int32_t *>(ws + L.release);
+  c->keys = reinterpret_cast<uint32_t *>(ws + L.keys);
+  c->hist = reinterpret_cast<uint32_t *>(ws + L.hist);
+  c->block_sums = reinterpret_cast<uint32_t *>(ws + L.block_sums);
+  c->ntx = L.ntx; c->nty = L.nty; c->ntz = L.ntz; c->nkeys = L.nkeys;
+
+  double idp[kMaxLevels];
+  for (int k = 0; k < grid->nz - 1; ++k) idp[k] = 1.0 / (grid->plev[k] - grid->plev[k + 1]);
+  idp[grid->nz - 1] = 0.0;
+  if (hipMemcpy(c->plev, c->plev_h, sizeof(double) * grid->nz, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->inv_dp, idp, sizeof(double) * grid->nz, hipMemcpyHostToDevice) != hipSuccess) {
+    delete c;
+    return MPT_ERR_HIP;
+  }
+  if (launch_fill_f32(c->scales, 1.0f, (int64_t)3 * grid->nz * grid->nt, nullptr) != hipSuccess ||
+      hipStreamSynchronize(nullptr) != hipSuccess) {
+    delete c;
+    return MPT_ERR_HIP;
+  }
+  *out = c;
+  return MPT_OK;
+}
+
+mpt_status mpt_init_met(mpt_ctx *c, int32_t level, const float *u, const float *v, const float *w,
+                        void *hip_stream) {
+  if (!c || !u || !v || !w) return MPT_ERR_ARG;
+  if (level < 0 || level >= c->grid.nt) return MPT_ERR_ARG;
+  if (!aligned(u, 4) || !aligned(v, 4) || !aligned(w, 4)) return MPT_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const int64_t nxy = (int64_t)c->grid.nx * c->grid.ny;
+  unsigned char *dst = static_cast<unsigned char *>(c->met) + c->level_bytes * (size_t)level;
+  float *sc = c->scales + (size_t)level * 3 * c->grid.nz;
+  hipError_t e;
+  if (c->grid.dtype == MPT_DT_F32) {
+    e = launch_pack_f32(u, v, w, reinterpret_cast<float4 *>(dst), c->npts, s);
+  } else {
+    e = launch_level_absmax(u, v, w, nxy, c->grid.nz, sc, s);
+    if (e == hipSuccess)
+      e = launch_pack_r16(c->grid.dtype, u, v, w, sc, reinterpret_cast<ushort4 *>(dst), nxy,
+                          c->grid.nz, s);
+  }
+  if (e != hipSuccess) return MPT_ERR_HIP;
+  c->levels_ready |= 1ull << level;
+  return MPT_OK;
+}
+
+size_t mpt_met_level_bytes(const mpt_ctx *c) { return c ? c->level_bytes : 0; }
+
+mpt_status mpt_copy_met_level(mpt_ctx *c, int32_t level, void *dst, float *scales_dst,
+                              void *hip_stream) {
+  if (!c || !dst || !scales_dst) return MPT_ERR_ARG;
+  if (level < 0 || level >= c->grid.nt) return MPT_ERR_ARG;
+  if (!(c->levels_ready & (1ull << level))) return MPT_ERR_STATE;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const unsigned char *src = static_cast<const unsigned char *>(c->met) + c->level_bytes * (size_t)level;
+  if (hipMemcpyAsync(dst, src, c->level_bytes, hipMemcpyDeviceToDevice, s) != hipSuccess) return MPT_ERR_HIP;
+  if (hipMemcpyAsync(scales_dst, c->scales + (size_t)level * 3 * c->grid.nz,
+                     sizeof(float) * 3 * c->grid.nz, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return MPT_ERR_HIP;
+  return MPT_OK;
+}
+
+mpt_status mpt_set_release(mpt_ctx *c, int32_t nscen, const int32_t *release_step, void *hip_stream) {
+  if (!c || !release_step || nscen < 1 || nscen > kMaxScen) return MPT_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  // copied synchronously: the host array may be reused right after the call
+  if (hipMemcpyAsync(c->release, release_step, sizeof(int32_t) * nscen, hipMemcpyHostToDevice, s) !=
+          hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return MPT_ERR_HIP;
+  c->nscen = nscen;
+  return MPT_OK;
+}
+
+mpt_status mpt_advect(mpt_ctx *c, const mpt_particles *P, uint32_t step, void *hip_stream) {
+  if (!c) return MPT_ERR_ARG;
+  mpt_status st = check_particles(c, P, false);
+  if (st != MPT_OK) return st;
+  st = check_time(c, step, 1);
+  if (st != MPT_OK) return st;
+  if (P->n == 0 || !(c->params.flags & MPT_ADVECT)) return MPT_OK;
+  return run_steps(c, P, step, 1, MPT_ADVECT, static_cast<hipStream_t>(hip_stream));
+}
+
+mpt_status mpt_diffuse(mpt_ctx *c, const mpt_particles *P, uint32_t step, void *hip_stream) {
+  if (!c) return MPT_ERR_ARG;
+  mpt_status st = check_particles(c, P, false);
+  if (st != MPT_OK) return st;
+  st = check_time(c, step, 1);
+  if (st != MPT_OK) return st;
+  const uint32_t f = c->params.flags & (MPT_TURB | MPT_MESO);
+  if (P->n == 0 || !f) return MPT_OK;
+  return run_steps(c, P, step, 1, f, static_cast<hipStream_t>(hip_stream));
+}
+
+mpt_status mpt_sort_particles(mpt_ctx *c, mpt_particles *P, void *hip_stream) {
+  if (!c) return MPT_ERR_ARG;
+  const mpt_status st = check_particles(c, P, true);
+  if (st != MPT_OK) return st;
+  if (P->n == 0) return MPT_OK;
+  return do_sort(c, P, static_cast<hipStream_t>(hip_stream));
+}
+
+mpt_status mpt_step(mpt_ctx *c, mpt_particles *P, uint32_t step0, int32_t nsteps, void *hip_stream) {
+  if (!c) return MPT_ERR_ARG;
+  const int S = c->params.sort_interval;
+  bool sorts = false;
+  if (S > 0 && nsteps > 0) {
+    for (int64_t s = step0; s < (int64_t)step0 + nsteps; ++s)
+      if (s % S == 0) { sorts = true; break; }
+  }
+  mpt_status st = check_particles(c, P, sorts);
+  if (st != MPT_OK) return st;
+  st = check_time(c, step0, nsteps);
+  if (st != MPT_OK) return st;
+  if (P->n == 0 || nsteps == 0) return MPT_OK;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const uint32_t flags = c->params.flags;
+  int64_t cur = step0;
+  const int64_t end = (int64_t)step0 + nsteps;
+  while (cur < end) {
+    if (S > 0 && cur % S == 0) {
+      st = do_sort(c, P, s);
+      if (st != MPT_OK) return st;
+    }
+    int64_t stop = end;
+    if (S > 0) {
+      const int64_t next_sort = (cur / S + 1) * S;
+      if (next_sort < stop) stop = next_sort;
+    }
+    if (stop - cur > c->params.fuse) stop = cur + c->params.fuse;
+    if (flags) {
+      st = run_steps(c, P, (uint32_t)cur, (int)(stop - cur), flags, s);
+      if (st != MPT_OK) return st;
+    }
+    cur = stop;
+  }
+  return MPT_OK;
+}
+
+mpt_status mpt_destroy(mpt_ctx *c) {
+  if (!c) return MPT_ERR_ARG;
+  delete c;
+  return MPT_OK;
+}
+
+const char *mpt_status_string(mpt_status s) {
+  switch (s) {
+    case MPT_OK: return "ok";
+    case MPT_ERR_ARG: return "invalid argument";
+    case MPT_ERR_STATE: return "invalid state (met level or release table not set)";
+    case MPT_ERR_TIME: return "step outside the resident met time levels";
+    case MPT_ERR_WORKSPACE: return "workspace too small or n > n_max";
+    case MPT_ERR_HIP: return "HIP runtime error (or no GPU)";
+    case MPT_ERR_UNSUPPORTED: return "unsupported combination";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

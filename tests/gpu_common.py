@@ -1,0 +1,77 @@
+"""Shared helpers of the GPU tests: run the HIP path through the C ABI and
+the oracle on the same seeded inputs, compare by parcel id."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+
+TOL_F64_DEG, TOL_F64_HPA = 1e-9, 1e-7
+TOL_R32_DEG, TOL_R32_HPA = 1e-4, 0.05
+
+
+def require_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2211_12616_amd as mpt
+    mpt.lib()                       # fails loudly when the library is missing
+    return mpt
+
+
+def say(msg: str):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_run(met, part, step0, nsteps, math=0, dtype=0, flags=7, sort_interval=0, fuse=1,
+            scen=None, release=None, n_max=None, seed=oracle.SEED, **kw):
+    """Run the HIP path; returns host Particles ordered by id."""
+    import torch
+    import paper_2211_12616_amd as mpt
+    params = mpt.make_params(math=math, flags=flags, sort_interval=sort_interval, fuse=fuse,
+                             seed=seed, **kw)
+    ctx = mpt.Context(met, params, n_max=part.n if n_max is None else n_max, dtype=dtype)
+    ctx.upload_met(met)
+    if release is not None:
+        ctx.set_release(release)
+    P = mpt.DeviceParticles.from_host(part, math=math, scen=scen, pingpong=sort_interval > 0)
+    ctx.step(P, step0, nsteps)
+    torch.cuda.synchronize()
+    out = P.to_host()
+    return by_id(out)
+
+
+def by_id(part):
+    order = np.argsort(part.id, kind="stable")
+    return part.subset(order)
+
+
+def oracle_run(met, part, step0, nsteps, flags=7, release=None, **kw):
+    m = oracle.Met(met)
+    c = oracle.ctl(flags=flags, **kw)
+    out = part.copy()
+    oracle.run(m, c, out, step0, nsteps, release=release)
+    return by_id(out)
+
+
+def compare(gpu, ref, tol_deg, tol_hpa, label=""):
+    np.testing.assert_array_equal(gpu.id, ref.id)
+    d = oracle.chord_deg(gpu.lon, gpu.lat, ref.lon, ref.lat)
+    dp = np.abs(gpu.p - ref.p)
+    say(f"[{label}] n={len(d)} max chord {d.max():.3e} deg  p99 {np.percentile(d, 99):.3e}  "
+        f"max |dp| {dp.max():.3e} hPa")
+    assert np.all(np.isfinite(gpu.lon)) == np.all(np.isfinite(ref.lon))
+    assert d.max() <= tol_deg, (label, d.max(), int(np.argmax(d)))
+    assert dp.max() <= tol_hpa, (label, dp.max(), int(np.argmax(dp)))
+    assert np.all((gpu.lon >= 0) & (gpu.lon < 360))
+    return d.max(), dp.max()
+
+
+def assert_bitwise(a, b):
+    for f in ("lon", "lat", "p", "up", "vp", "wp", "id"):
+        np.testing.assert_array_equal(getattr(a, f), getattr(b, f), err_msg=f)

@@ -1,0 +1,130 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads,
+exports every entry point include/mpt.h declares, and rejects bad
+arguments synchronously, before any HIP call."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import inputs
+import paper_2211_12616_amd as mpt
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    txt = open(os.path.join(ROOT, "include", "mpt.h")).read()
+    return sorted(set(re.findall(r"\b(mpt_[a-z_]+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol():
+    L = mpt.lib()
+    names = declared()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(L, name), name
+    assert sorted(mpt.exported_symbols()) == names
+
+
+def grid_params(dtype=mpt.DT_F32, math=mpt.MATH_F64, **kw):
+    met = inputs.empty_met(180, 91, inputs.levels_log(30), 3)
+    g, plev = mpt.make_grid(met, dtype)
+    return g, plev, mpt.make_params(math=math, **kw)
+
+
+def ws_bytes(g, p, n=0):
+    return mpt.lib().mpt_workspace_bytes(ctypes.byref(g), ctypes.byref(p), n)
+
+
+def create(g, p, n_max=0, ws=0x100000, nbytes=None):
+    h = ctypes.c_void_p()
+    nb = ws_bytes(g, p, n_max) if nbytes is None else nbytes
+    return mpt.lib().mpt_create(ctypes.byref(g), ctypes.byref(p), n_max, ws, nb, ctypes.byref(h))
+
+
+def test_workspace_bytes():
+    g, plev, p = grid_params()
+    nb = ws_bytes(g, p, 1000)
+    assert nb >= 180 * 91 * 30 * 16 * 3 + 4000
+    assert ws_bytes(g, p, 2000) > nb
+    g2, plev2, p2 = grid_params(dtype=mpt.DT_BF16, math=mpt.MATH_F32)
+    assert ws_bytes(g2, p2, 1000) < nb
+
+
+@pytest.mark.parametrize("case", ["nz", "nt", "plev", "dlon", "lat0", "dtype", "reserved"])
+def test_bad_grid_is_rejected(case):
+    g, plev, p = grid_params()
+    if case == "nz":
+        g.nz = 1
+    elif case == "nt":
+        g.nt = 1
+    elif case == "plev":
+        plev[5] = plev[4] + 1.0                   # not strictly decreasing
+    elif case == "dlon":
+        g.dlon = 2.5
+    elif case == "lat0":
+        g.lat0 = -80.0
+    elif case == "dtype":
+        g.dtype = 7
+    else:
+        g.reserved = 1
+    assert ws_bytes(g, p) == 0
+    assert create(g, p, nbytes=1 << 30) == -1
+
+
+@pytest.mark.parametrize("case", ["dt", "turb", "sort", "fuse", "flags", "math"])
+def test_bad_params_are_rejected(case):
+    g, plev, p = grid_params()
+    if case == "dt":
+        p.dt = 0.0
+    elif case == "turb":
+        p.turb_dx = -1.0
+    elif case == "sort":
+        p.sort_interval = -1
+    elif case == "fuse":
+        p.fuse = 0
+    elif case == "flags":
+        p.flags = 8
+    else:
+        p.math = 3
+    assert ws_bytes(g, p) == 0
+    assert create(g, p, nbytes=1 << 30) == -1
+
+
+def test_f64_with_16bit_storage_unsupported():
+    g, plev, p = grid_params(dtype=mpt.DT_BF16, math=mpt.MATH_F64)
+    assert create(g, p, nbytes=1 << 30) == -6
+
+
+def test_workspace_checks():
+    g, plev, p = grid_params()
+    assert create(g, p, ws=0) == -1                                   # null
+    assert create(g, p, ws=0x100010) == -1                            # misaligned
+    assert create(g, p, nbytes=ws_bytes(g, p) - 1) == -4              # too small
+    h = ctypes.c_void_p()
+    assert mpt.lib().mpt_create(ctypes.byref(g), ctypes.byref(p), -1, 0x100000, 1 << 30,
+                                ctypes.byref(h)) == -1                # n_max < 0
+
+
+def test_no_gpu_gives_hip_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    g, plev, p = grid_params()
+    assert create(g, p) == -5
+
+
+def test_null_context_calls():
+    L = mpt.lib()
+    s = mpt.ParticlesC(n=0)
+    assert L.mpt_advect(None, ctypes.byref(s), 0, None) == -1
+    assert L.mpt_diffuse(None, ctypes.byref(s), 0, None) == -1
+    assert L.mpt_step(None, ctypes.byref(s), 0, 1, None) == -1
+    assert L.mpt_sort_particles(None, ctypes.byref(s), None) == -1
+    assert L.mpt_init_met(None, 0, None, None, None, None) == -1
+    assert L.mpt_set_release(None, 1, None, None) == -1
+    assert L.mpt_destroy(None) == -1
+    assert L.mpt_met_level_bytes(None) == 0
+    assert L.mpt_status_string(-3) == b"step outside the resident met time levels"

@@ -1,0 +1,209 @@
+"""GPU parity on the tiny workload (2 deg grid, 30 levels): the HIP path
+through the C ABI against the FP64 oracle, element by element by parcel id,
+plus the invariants the method guarantees (step = advect then diffuse,
+sort neutrality, restart, fusion, repeatability, activity gating)."""
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+from gpu_common import (TOL_F64_DEG, TOL_F64_HPA, TOL_R32_DEG, TOL_R32_HPA, assert_bitwise,
+                        by_id, compare, gpu_run, oracle_run, require_gpu, say)
+from oracle import encode
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mpt():
+    return require_gpu()
+
+
+@pytest.fixture(scope="module")
+def met2():
+    return inputs.make_met_c1(seed=11, nt=2)
+
+
+@pytest.fixture(scope="module")
+def met3():
+    return inputs.make_met_c1(seed=11, nt=3)
+
+
+def test_tiny_workload_advection_f64(mpt, met2):
+    """Config: 1e4 parcels, 60 midpoint steps of 180 s, no diffusion, FP64."""
+    say("tiny advection-only F64, n=10000, 60 steps")
+    part = inputs.make_particles(10_000, 21)
+    g = gpu_run(met2, part, 0, 60, flags=oracle.ADVECT)
+    r = oracle_run(met2, part, 0, 60, flags=oracle.ADVECT)
+    compare(g, r, TOL_F64_DEG, TOL_F64_HPA, "c1 advect F64")
+
+
+def test_tiny_full_step_sorted_fused_f64(mpt, met3):
+    say("tiny all modules F64, n=10000, 240 steps, sort/10, fuse 10")
+    part = inputs.make_particles(10_000, 22)
+    g = gpu_run(met3, part, 0, 240, sort_interval=10, fuse=10)
+    r = oracle_run(met3, part, 0, 240)
+    compare(g, r, TOL_F64_DEG, TOL_F64_HPA, "c1 full F64")
+    np.testing.assert_allclose(g.up, r.up, atol=1e-9)
+    np.testing.assert_allclose(g.vp, r.vp, atol=1e-9)
+    np.testing.assert_allclose(g.wp, r.wp, atol=1e-11)
+
+
+@pytest.mark.parametrize("n", [1, 63, 255, 257, 1000, 4097])
+def test_ragged_sizes(mpt, met3, n):
+    say(f"ragged n={n}")
+    part = inputs.make_particles(n, 100 + n)
+    g = gpu_run(met3, part, 5, 20, sort_interval=4, fuse=3)
+    r = oracle_run(met3, part, 5, 20)
+    compare(g, r, TOL_F64_DEG, TOL_F64_HPA, f"ragged {n}")
+
+
+def test_empty(mpt, met3):
+    import torch
+    part = inputs.make_particles(0, 1)
+    ctx = mpt.Context(met3, mpt.make_params(sort_interval=10), n_max=16)
+    ctx.upload_met(met3)
+    P = mpt.DeviceParticles.from_host(part)
+    ctx.step(P, 0, 20)
+    ctx.sort(P)
+    torch.cuda.synchronize()
+    assert P.n == 0
+
+
+def test_step_equals_advect_then_diffuse(mpt, met3):
+    import torch
+    say("step == advect;diffuse bitwise")
+    part = inputs.make_particles(3000, 23)
+    params = mpt.make_params()
+    ctx = mpt.Context(met3, params, n_max=part.n)
+    ctx.upload_met(met3)
+    A = mpt.DeviceParticles.from_host(part, pingpong=False)
+    B = mpt.DeviceParticles.from_host(part, pingpong=False)
+    for s in range(12):
+        ctx.step(A, s, 1)
+        ctx.advect(B, s)
+        ctx.diffuse(B, s)
+    torch.cuda.synchronize()
+    assert_bitwise(A.to_host(), B.to_host())
+
+
+def test_sort_neutral_and_valid(mpt, met3):
+    say("sort neutrality + validity")
+    part = inputs.make_particles(20_000, 24)
+    a = gpu_run(met3, part, 0, 60, sort_interval=10, fuse=10)
+    b = gpu_run(met3, part, 0, 60, sort_interval=0, fuse=10)
+    assert_bitwise(a, b)
+    # one explicit sort: permutation of ids, keys non-decreasing
+    import torch
+    ctx = mpt.Context(met3, mpt.make_params(sort_interval=1), n_max=part.n)
+    ctx.upload_met(met3)
+    P = mpt.DeviceParticles.from_host(part)
+    ctx.sort(P)
+    torch.cuda.synchronize()
+    h = P.to_host()
+    np.testing.assert_array_equal(np.sort(h.id), np.arange(part.n, dtype=np.uint32))
+    keys = oracle.tile_keys(oracle.Met(met3), h.lon, h.lat, h.p)
+    assert np.all(np.diff(keys.astype(np.int64)) >= 0)
+    np.testing.assert_array_equal(h.lon, part.lon[h.id])
+
+
+def test_restart_fusion_repeat_bitwise(mpt, met3):
+    say("restart / fuse / repeat bitwise")
+    part = inputs.make_particles(5000, 25)
+    a = gpu_run(met3, part, 0, 50, fuse=1)
+    b = gpu_run(met3, part, 0, 50, fuse=7)
+    c = gpu_run(met3, part, 0, 50, fuse=7)
+    assert_bitwise(a, b)
+    assert_bitwise(b, c)
+    half = gpu_run(met3, part, 0, 23, fuse=5)
+    rest = gpu_run(met3, half, 23, 27, fuse=5)
+    assert_bitwise(a, rest)
+
+
+def test_subset_independence(mpt, met3):
+    part = inputs.make_particles(6000, 26)
+    idx = np.arange(1000, 1800)
+    full = gpu_run(met3, part, 0, 40, sort_interval=10, fuse=10)
+    sub = gpu_run(met3, part.subset(idx), 0, 40, sort_interval=10, fuse=10)
+    assert_bitwise(full.subset(idx), sub)
+
+
+def test_release_gating(mpt, met3):
+    say("scenario release gating")
+    part = inputs.make_particles(4000, 27)
+    scen = (np.arange(4000) % 5).astype(np.uint16)
+    rel_s = np.array([0, 3, 17, 30, 1000], np.int32)
+    g = gpu_run(met3, part, 0, 40, scen=scen, release=rel_s, sort_interval=10, fuse=10)
+    r = oracle_run(met3, part, 0, 40, release=rel_s[scen])
+    compare(g, r, TOL_F64_DEG, TOL_F64_HPA, "release")
+    never = np.where(scen == 4)[0]
+    np.testing.assert_array_equal(g.lon[never], part.lon[never])
+
+
+def test_nonfinite_parcels_untouched(mpt, met3):
+    part = inputs.make_particles(700, 28)
+    part.lon[5] = np.nan
+    part.p[9] = np.inf
+    g = gpu_run(met3, part, 0, 15, sort_interval=5, fuse=5)
+    r = oracle_run(met3, part, 0, 15)
+    assert np.isnan(g.lon[5]) and np.isinf(g.p[9])
+    ok = np.isfinite(r.lon) & np.isfinite(r.p)
+    d = oracle.chord_deg(g.lon[ok], g.lat[ok], r.lon[ok], r.lat[ok])
+    assert d.max() <= TOL_F64_DEG
+
+
+def test_f32_form(mpt, met3):
+    say("F32 form vs oracle")
+    part = inputs.make_particles(10_000, 29)
+    g = gpu_run(met3, part, 0, 240, math=1, sort_interval=10, fuse=10)
+    r = oracle_run(met3, part, 0, 240)
+    compare(g, r, TOL_R32_DEG, TOL_R32_HPA, "c1 F32")
+
+
+@pytest.mark.parametrize("kind", [encode.BF16, encode.F16])
+def test_r16_encoding_bitwise(mpt, met3, kind):
+    import torch
+    ctx = mpt.Context(met3, mpt.make_params(math=1), dtype=kind)
+    ctx.upload_met(met3)
+    for l in range(met3.nt):
+        packed, sc = ctx.copy_met_level(l)
+        torch.cuda.synchronize()
+        rec = packed.cpu().numpy().view(np.uint16).reshape(met3.nz, met3.ny, met3.nx, 4)
+        scales = sc.cpu().numpy().reshape(3, met3.nz)
+        for q, name in enumerate(("u", "v", "w")):
+            want_q, want_s = encode.encode_level(getattr(met3, name)[l], kind)
+            np.testing.assert_array_equal(scales[q], want_s)
+            np.testing.assert_array_equal(rec[..., q], want_q)
+        assert np.all(rec[..., 3] == 0)
+
+
+@pytest.mark.parametrize("kind", [encode.BF16, encode.F16])
+def test_r16_form(mpt, met3, kind):
+    say(f"R16 form kind={kind} vs oracle on decoded fields")
+    part = inputs.make_particles(10_000, 30)
+    g = gpu_run(met3, part, 0, 240, math=1, dtype=kind, sort_interval=10, fuse=10)
+    deq = encode.dequantized_met(met3, kind)
+    r = oracle_run(deq, part, 0, 240)
+    compare(g, r, TOL_R32_DEG, TOL_R32_HPA, f"c1 R16 {kind}")
+
+
+def test_errors_on_gpu(mpt, met3):
+    part = inputs.make_particles(100, 31)
+    ctx = mpt.Context(met3, mpt.make_params(sort_interval=10), n_max=50)
+    P = mpt.DeviceParticles.from_host(part)
+    with pytest.raises(mpt.MptError) as e:
+        ctx.step(P, 0, 1)                         # met not stored yet
+    assert e.value.code == -2
+    ctx.upload_met(met3)
+    with pytest.raises(mpt.MptError) as e:
+        ctx.step(P, 230, 20)                      # beyond the last met level
+    assert e.value.code == -3
+    with pytest.raises(mpt.MptError) as e:
+        ctx.step(P, 0, 5)                         # sorts, but n > n_max
+    assert e.value.code == -4
+    ctx2 = mpt.Context(met3, mpt.make_params(), n_max=100)
+    ctx2.upload_met(met3)
+    Q = mpt.DeviceParticles.from_host(part, scen=np.zeros(100, np.uint16), pingpong=False)
+    with pytest.raises(mpt.MptError) as e:
+        ctx2.step(Q, 0, 1)                        # scenarios without a release table
+    assert e.value.code == -2
