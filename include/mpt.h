@@ -172,20 +172,40 @@ mpt_status mpt_advect(mpt_ctx *ctx, const mpt_particles *particles, uint32_t ste
 mpt_status mpt_diffuse(mpt_ctx *ctx, const mpt_particles *particles, uint32_t step,
                        void *hip_stream);
 
-/* Sort parcels by grid box: key = 8 x 8 x 4 (lon x lat x level) tile of
- * the cell holding the parcel, tiles numbered lon fastest; parcels with
- * non-finite positions go last.  Scatters the whole state into the *2 set
- * and swaps the primary and *2 pointers inside *particles (the caller must
- * re-read them).  Order inside a tile is unspecified.  Needs n <= n_max. */
+/* Sort parcels by grid box (the sorting modules of Sec. 6): key = 8 x 8 x 4
+ * (lon x lat x level) tile of the cell holding the parcel, tiles numbered
+ * lon fastest.  With scenarios, parcels not yet released at the step the
+ * sort precedes go behind all tiles, grouped by their scenario's rank in
+ * release order; parcels with non-finite positions go last.  Scatters the
+ * whole state into the *2 set and swaps the primary and *2 pointers inside
+ * *particles (the caller must re-read them).  Order inside a key is
+ * unspecified.  Needs n <= n_max.  (This entry point sorts as if before
+ * step 0; mpt_step sorts before the step it is about to run.) */
 mpt_status mpt_sort_particles(mpt_ctx *ctx, mpt_particles *particles, void *hip_stream);
 
 /* nsteps time steps step0 .. step0+nsteps-1 (advection, turbulent and
- * mesoscale diffusion per params.flags), sorting before every step that is
- * a multiple of params.sort_interval (then the pointers in *particles are
- * swapped as by mpt_sort_particles).  Consecutive steps between sorts are
- * fused into launches of at most params.fuse steps. */
+ * mesoscale diffusion per params.flags; the time loop of Sec. 4.3), sorting
+ * before every step that is a multiple of params.sort_interval (then the
+ * pointers in *particles are swapped as by mpt_sort_particles).
+ * Consecutive steps between sorts are fused into launches of at most
+ * params.fuse steps.  With scenarios, launches that follow a sort inside
+ * the same call use a persistent grid that walks only the parcels released
+ * so far (their count is read from the sort's device-side cursors; no
+ * host round trip). */
 mpt_status mpt_step(mpt_ctx *ctx, mpt_particles *particles, uint32_t step0, int32_t nsteps,
                     void *hip_stream);
+
+/* The same steps as mpt_step, bit for bit, with the launch sequence of two
+ * sort windows (2 * sort_interval steps: sort, fused steps, sort, fused
+ * steps) captured once into a HIP graph and replayed nsteps / (2 *
+ * sort_interval) times; the kernels read the step index from device
+ * memory, which the graph advances.  Requires sort_interval > 0,
+ * step0 % sort_interval == 0, nsteps % (2 * sort_interval) == 0 and a
+ * created (non-null) stream.  The graph is cached in the context and
+ * re-captured when the particle pointers or n change.  After the call the
+ * state is in the same set it started in (an even number of sorts). */
+mpt_status mpt_step_graph(mpt_ctx *ctx, mpt_particles *particles, uint32_t step0, int32_t nsteps,
+                          void *hip_stream);
 
 /* Release the context (the workspace stays the caller's). */
 mpt_status mpt_destroy(mpt_ctx *ctx);

@@ -83,11 +83,13 @@ def lib() -> ctypes.CDLL:
         L.mpt_diffuse.argtypes = [P, P, ctypes.c_uint32, P]
         L.mpt_sort_particles.argtypes = [P, P, P]
         L.mpt_step.argtypes = [P, P, ctypes.c_uint32, ctypes.c_int32, P]
+        L.mpt_step_graph.argtypes = [P, P, ctypes.c_uint32, ctypes.c_int32, P]
         L.mpt_destroy.argtypes = [P]
         L.mpt_status_string.argtypes = [S]
         L.mpt_status_string.restype = ctypes.c_char_p
         for fn in ("mpt_create", "mpt_init_met", "mpt_copy_met_level", "mpt_set_release",
-                   "mpt_advect", "mpt_diffuse", "mpt_sort_particles", "mpt_step", "mpt_destroy"):
+                   "mpt_advect", "mpt_diffuse", "mpt_sort_particles", "mpt_step", "mpt_step_graph",
+                   "mpt_destroy"):
             getattr(L, fn).restype = S
         _lib = L
     return _lib
@@ -96,7 +98,8 @@ def lib() -> ctypes.CDLL:
 def exported_symbols():
     return ["mpt_workspace_bytes", "mpt_create", "mpt_init_met", "mpt_copy_met_level",
             "mpt_met_level_bytes", "mpt_set_release", "mpt_advect", "mpt_diffuse",
-            "mpt_sort_particles", "mpt_step", "mpt_destroy", "mpt_status_string"]
+            "mpt_sort_particles", "mpt_step", "mpt_step_graph", "mpt_destroy",
+            "mpt_status_string"]
 
 
 def _check(fn: str, code: int):
@@ -279,4 +282,12 @@ class Context:
         s = P.cstruct()
         _check("mpt_step", lib().mpt_step(self.h, ctypes.byref(s), step0, nsteps,
                                           _stream_handle(stream)))
+        P.adopt(s)
+
+    def step_graph(self, P: DeviceParticles, step0: int, nsteps: int, stream):
+        """mpt_step_graph on ``stream`` (a created torch.cuda.Stream, not the
+        null stream); the caller orders it with its other work."""
+        s = P.cstruct()
+        _check("mpt_step_graph", lib().mpt_step_graph(self.h, ctypes.byref(s), step0, nsteps,
+                                                      _stream_handle(stream)))
         P.adopt(s)

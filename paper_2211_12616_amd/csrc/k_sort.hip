@@ -38,10 +38,13 @@ __global__ __launch_bounds__(kBlock) void k_sort_keys(const SortArgs a) {
   const int64_t i = (int64_t)lb * kBlock + threadIdx.x;
   const bool valid = i < a.n;
   uint32_t key = 0xFFFFFFFFu;
+  const uint32_t step = a.step + (a.step_dev ? *a.step_dev : 0u);
   if (valid) {
     const double lon = a.lon[i], lat = a.lat[i], p = a.p[i];
     if (!finite3(lon, lat, p)) {
       key = a.nkeys - 1;
+    } else if (a.scen && (int64_t)step < (int64_t)a.release[a.scen[i]]) {
+      key = a.ntx * a.nty * a.ntz + (uint32_t)a.rank[a.scen[i]];
     } else {
       const double lam = lon - 360.0 * floor((lon - a.lon0) * (1.0 / 360.0));
       int i0 = (int)floor((lam - a.lon0) * a.inv_dlon);

@@ -1,25 +1,18 @@
 // k_step.hip -- the fused particle time step (advection, position,
 // turbulent and mesoscale diffusion, position) for one or more steps per
 // launch, one parcel per thread, state held in registers across steps.
+//
+// Two launch shapes: one block per 256 parcels (XCD-aware order), or a
+// persistent grid that walks 256-parcel chunks of the active prefix of a
+// scenario run, whose length it reads from device memory.
 #include "mpt_device.h"
 #include "mpt_internal.h"
 
 namespace mpt {
 
 template <int F, typename R>
-__global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
-  __shared__ double s_plev[kMaxLevels];
-  __shared__ double s_idp[kMaxLevels];
-  for (int q = threadIdx.x; q < a.nz; q += kBlock) {
-    s_plev[q] = a.plev[q];
-    s_idp[q] = (q < a.nz - 1) ? a.inv_dp[q] : 0.0;
-  }
-  __syncthreads();
-  const int lb = logical_block((int)blockIdx.x, a.per_xcd);
-  if (lb >= a.nblk) return;
-  const int64_t i = (int64_t)lb * kBlock + threadIdx.x;
-  if (i >= a.n) return;
-
+__device__ __forceinline__ void step_parcel(const StepArgs &a, const double *s_plev,
+                                            const double *s_idp, int64_t i, uint32_t step0) {
   double lon = a.lon[i], lat = a.lat[i], p = a.p[i];
   if (!finite3(lon, lat, p)) return;
   const uint32_t id = a.id[i];
@@ -34,7 +27,7 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
   }
   bool moved = false;
   for (int s = 0; s < a.nsteps; ++s) {
-    const uint32_t step = a.step0 + (uint32_t)s;
+    const uint32_t step = step0 + (uint32_t)s;
     if ((int64_t)step < rel) continue;
     if (!finite3(lon, lat, p)) break;
     moved = true;
@@ -60,8 +53,50 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
   }
 }
 
+// Number of parcels a persistent launch must walk: the active prefix left
+// by the last sort, extended by the pending scenarios released by `last`.
+__device__ __forceinline__ int64_t active_bound(const StepArgs &a, uint32_t last) {
+  int lo = 0, hi = a.nscen;              // r = #(rel_sorted[r] <= last)
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if ((int64_t)a.rel_sorted[mid] <= (int64_t)last) lo = mid + 1; else hi = mid;
+  }
+  const int64_t b = a.cursor[a.ntiles - 1 + (uint32_t)lo];
+  return b < a.n ? b : a.n;
+}
+
+template <int F, typename R>
+__global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
+  __shared__ double s_plev[kMaxLevels];
+  __shared__ double s_idp[kMaxLevels];
+  for (int q = threadIdx.x; q < a.nz; q += kBlock) {
+    s_plev[q] = a.plev[q];
+    s_idp[q] = (q < a.nz - 1) ? a.inv_dp[q] : 0.0;
+  }
+  __syncthreads();
+  const uint32_t step0 = a.step0 + (a.step_dev ? *a.step_dev : 0u);
+  if (!a.persistent) {
+    const int lb = logical_block((int)blockIdx.x, a.per_xcd);
+    if (lb >= a.nblk) return;
+    const int64_t i = (int64_t)lb * kBlock + threadIdx.x;
+    if (i < a.n) step_parcel<F, R>(a, s_plev, s_idp, i, step0);
+    return;
+  }
+  // persistent: XCD x owns an even share of the chunks of the prefix and its
+  // blocks stride through that share
+  const int64_t bound = active_bound(a, step0 + (uint32_t)(a.nsteps - 1));
+  const int64_t nchunks = (bound + kBlock - 1) / kBlock;
+  const int xcd = (int)blockIdx.x % kXcds;
+  const int q = (int)blockIdx.x / kXcds, nq = (int)gridDim.x / kXcds;
+  const int64_t c_lo = nchunks * xcd / kXcds, c_hi = nchunks * (xcd + 1) / kXcds;
+  for (int64_t c = c_lo + q; c < c_hi; c += nq) {
+    const int64_t i = c * kBlock + threadIdx.x;
+    if (i < bound) step_parcel<F, R>(a, s_plev, s_idp, i, step0);
+  }
+}
+
 hipError_t launch_step(int field, int math_f64, const StepArgs &args, hipStream_t stream) {
-  const dim3 grid((unsigned)(args.per_xcd * kXcds)), block(kBlock);
+  const dim3 grid((unsigned)(args.persistent ? args.nblk : args.per_xcd * kXcds)), block(kBlock);
   if (math_f64) {
     if (field != kF32) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_step<kF32, double>), grid, block, 0, stream, args);
@@ -72,6 +107,19 @@ hipError_t launch_step(int field, int math_f64, const StepArgs &args, hipStream_
   } else {
     hipLaunchKernelGGL((k_step<kF16, float>), grid, block, 0, stream, args);
   }
+  return hipGetLastError();
+}
+
+__global__ void k_add_u32(uint32_t *p, uint32_t v) { *p += v; }
+__global__ void k_set_u32(uint32_t *p, uint32_t v) { *p = v; }
+
+hipError_t launch_set_u32(uint32_t *p, uint32_t v, hipStream_t stream) {
+  hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, stream, p, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_u32(uint32_t *p, uint32_t v, hipStream_t stream) {
+  hipLaunchKernelGGL(k_add_u32, dim3(1), dim3(1), 0, stream, p, v);
   return hipGetLastError();
 }
 

@@ -46,11 +46,23 @@ struct StepArgs {
   double r_ar, rs_fh, rs_fv;   // AR(1): r, sqrt(1-r^2)*fh, sqrt(1-r^2)*fv
   double cos_cap;              // cos(89.999 deg)
   uint64_t seed;
-  uint32_t step0;
+  uint32_t step0;              // first step (added to *step_dev when that is set)
   int32_t nsteps;
   uint32_t flags;
   int32_t nblk;                // logical blocks
   int32_t per_xcd;             // logical blocks per XCD
+
+  // Step index in device memory (replayable graphs); null = step0 alone.
+  const uint32_t *step_dev;
+  // Persistent mode (scenario runs right after a sort): parcels are ordered
+  // active-by-tile, then pending scenarios by release rank, then non-finite;
+  // the kernel walks only the prefix of parcels released by the launch's
+  // last step: cursor[ntiles - 1 + r], r = #(rel_sorted <= last step).
+  int32_t persistent;
+  int32_t nscen;
+  uint32_t ntiles;
+  const uint32_t *cursor;      // sort cursors after the scatter (bucket ends)
+  const int32_t *rel_sorted;   // release steps in ascending order [nscen]
 };
 
 // Map the hardware block index to a logical block so that each XCD walks a
@@ -212,15 +224,18 @@ __device__ __forceinline__ void locate_t(const StepArgs &a, double t, Loc<R> &L)
 template <typename R>
 __device__ __forceinline__ R lerp(R a, R b, R f) { return fma(f, b - a, a); }
 
-// Gather the 16 records (2 time levels x 2 levels x 2 rows x 2 columns) of
-// the cell and return the values of all three variables: v[dl][dk][dj][di][var].
+// The 16 records of a cell: 2 time levels x 2 levels x 2 rows x 2 columns.
+template <int F>
+struct Cell16 {
+  typename Rec<F>::T r[2][2][2][2];   // [dl][dk][dj][di]
+};
+
 template <int F, typename R>
-__device__ __forceinline__ void gather16(const StepArgs &a, const Loc<R> &L, R v[2][2][2][2][3]) {
+__device__ __forceinline__ void load_cell(const StepArgs &a, const Loc<R> &L, Cell16<F> &c) {
   using T = typename Rec<F>::T;
   const T *base = reinterpret_cast<const T *>(a.met);
   const int nxy = a.nx * a.ny;
   const int r0 = L.k * nxy + L.j * a.nx;
-  T rec[2][2][2][2];
 #pragma unroll
   for (int dl = 0; dl < 2; ++dl) {
     const T *lev = base + (int64_t)(L.l + dl) * a.level_elems;
@@ -229,66 +244,89 @@ __device__ __forceinline__ void gather16(const StepArgs &a, const Loc<R> &L, R v
 #pragma unroll
       for (int dj = 0; dj < 2; ++dj) {
         const T *row = lev + r0 + dk * nxy + dj * a.nx;
-        rec[dl][dk][dj][0] = row[L.i0];
-        rec[dl][dk][dj][1] = row[L.i1];
+        c.r[dl][dk][dj][0] = row[L.i0];
+        c.r[dl][dk][dj][1] = row[L.i1];
       }
   }
+}
+
+// Scales of the (time level, level) slabs a cell touches (R16 storage).
+template <int F, typename R>
+__device__ __forceinline__ void cell_scales(const StepArgs &a, const Loc<R> &L, float sc[2][2][3]) {
 #pragma unroll
   for (int dl = 0; dl < 2; ++dl)
 #pragma unroll
     for (int dk = 0; dk < 2; ++dk) {
-      float sc[3] = {1.f, 1.f, 1.f};
-      if (F != kF32) {
+      if (F == kF32) {
+        sc[dl][dk][0] = sc[dl][dk][1] = sc[dl][dk][2] = 1.0f;
+      } else {
         const float *s = a.scales + (int64_t)(L.l + dl) * 3 * a.nz + (L.k + dk);
-        sc[0] = s[0];
-        sc[1] = s[a.nz];
-        sc[2] = s[2 * a.nz];
+        sc[dl][dk][0] = s[0];
+        sc[dl][dk][1] = s[a.nz];
+        sc[dl][dk][2] = s[2 * a.nz];
       }
-#pragma unroll
-      for (int dj = 0; dj < 2; ++dj)
-#pragma unroll
-        for (int di = 0; di < 2; ++di) Fetch<F, R>::get(rec[dl][dk][dj][di], sc, v[dl][dk][dj][di]);
     }
 }
 
-// Quadrilinear interpolation: along lon, then lat, then p, at both time
-// levels, then in time.
-template <typename R>
-__device__ __forceinline__ void interp16(const R v[2][2][2][2][3], const Loc<R> &L, R out[3]) {
+// Quadrilinear interpolation, the time weight applied first at each of the
+// 8 corners, then along lon, lat and p.  Equal to interpolating in space at
+// both time levels and then in time (multilinear), up to rounding.
+template <int F, typename R>
+__device__ __forceinline__ void interp_cell(const StepArgs &a, const Cell16<F> &c, const Loc<R> &L,
+                                            R out[3]) {
+  float sc[2][2][3];
+  cell_scales<F, R>(a, L, sc);
+  R cv[2][2][2][3];   // [dk][dj][di][var], time-interpolated
+#pragma unroll
+  for (int dk = 0; dk < 2; ++dk)
+#pragma unroll
+    for (int dj = 0; dj < 2; ++dj)
+#pragma unroll
+      for (int di = 0; di < 2; ++di) {
+        R v0[3], v1[3];
+        Fetch<F, R>::get(c.r[0][dk][dj][di], sc[0][dk], v0);
+        Fetch<F, R>::get(c.r[1][dk][dj][di], sc[1][dk], v1);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) cv[dk][dj][di][q] = lerp(v0[q], v1[q], L.ft);
+      }
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
-    R zl[2];
+    R yk[2];
 #pragma unroll
-    for (int dl = 0; dl < 2; ++dl) {
-      R yk[2];
-#pragma unroll
-      for (int dk = 0; dk < 2; ++dk) {
-        const R x0 = lerp(v[dl][dk][0][0][q], v[dl][dk][0][1][q], L.fx);
-        const R x1 = lerp(v[dl][dk][1][0][q], v[dl][dk][1][1][q], L.fx);
-        yk[dk] = lerp(x0, x1, L.fy);
-      }
-      zl[dl] = lerp(yk[0], yk[1], L.fz);
+    for (int dk = 0; dk < 2; ++dk) {
+      const R x0 = lerp(cv[dk][0][0][q], cv[dk][0][1][q], L.fx);
+      const R x1 = lerp(cv[dk][1][0][q], cv[dk][1][1][q], L.fx);
+      yk[dk] = lerp(x0, x1, L.fy);
     }
-    out[q] = lerp(zl[0], zl[1], L.ft);
+    out[q] = lerp(yk[0], yk[1], L.fz);
   }
 }
 
-// Population standard deviation (two-pass) of the 16 values of each variable.
-template <typename R>
-__device__ __forceinline__ void sigma16(const R v[2][2][2][2][3], R out[3]) {
+// Population standard deviation of the 16 values of each variable, in one
+// pass over values shifted by the first one (sum and sum of squares of
+// x - x_0; the shift bounds the cancellation by the spread of the cell).
+template <int F, typename R>
+__device__ __forceinline__ void sigma_cell(const StepArgs &a, const Cell16<F> &c, const Loc<R> &L,
+                                           R out[3]) {
+  float sc[2][2][3];
+  cell_scales<F, R>(a, L, sc);
+  R x0[3], s1[3] = {0, 0, 0}, s2[3] = {0, 0, 0};
+  Fetch<F, R>::get(c.r[0][0][0][0], sc[0][0], x0);
+#pragma unroll
+  for (int n = 1; n < 16; ++n) {
+    const int dl = n >> 3, dk = (n >> 2) & 1, dj = (n >> 1) & 1, di = n & 1;
+    R x[3];
+    Fetch<F, R>::get(c.r[dl][dk][dj][di], sc[dl][dk], x);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const R d = x[q] - x0[q];
+      s1[q] += d;
+      s2[q] = fma(d, d, s2[q]);
+    }
+  }
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
-    R s = 0;
-#pragma unroll
-    for (int c = 0; c < 16; ++c) s += v[c >> 3][(c >> 2) & 1][(c >> 1) & 1][c & 1][q];
-    const R mean = s * (R)(1.0 / 16.0);
-    R ss = 0;
-#pragma unroll
-    for (int c = 0; c < 16; ++c) {
-      const R d = v[c >> 3][(c >> 2) & 1][(c >> 1) & 1][c & 1][q] - mean;
-      ss = fma(d, d, ss);
-    }
-    const R var = ss * (R)(1.0 / 16.0);
+    const R var = (s2[q] - s1[q] * s1[q] * (R)(1.0 / 16.0)) * (R)(1.0 / 16.0);
     out[q] = Math<R>::sqrt_(var > (R)0 ? var : (R)0);
   }
 }
@@ -306,13 +344,13 @@ __device__ __forceinline__ R cos_floor(const StepArgs &a, double lat) {
 template <int F, typename R>
 __device__ __forceinline__ void advect(const StepArgs &a, const double *s_plev, const double *s_idp,
                                        double t, double &lon, double &lat, double &p) {
-  R v[2][2][2][2][3];
+  Cell16<F> c;
   R w0[3], w1[3];
   Loc<R> L;
   locate_xyz<R>(a, s_plev, s_idp, lon, lat, p, L);
   locate_t<R>(a, t, L);
-  gather16<F, R>(a, L, v);
-  interp16<R>(v, L, w0);
+  load_cell<F, R>(a, L, c);
+  interp_cell<F, R>(a, c, L, w0);
   const R hdt = (R)(0.5 * a.dt);
   const R kdeg = (R)kDeg;
   const R d0lon = w0[0] * kdeg * Math<R>::rcp(cos_floor<R>(a, lat));
@@ -323,8 +361,8 @@ __device__ __forceinline__ void advect(const StepArgs &a, const double *s_plev, 
 
   locate_xyz<R>(a, s_plev, s_idp, lonm, latm, pm, L);
   locate_t<R>(a, t + 0.5 * a.dt, L);
-  gather16<F, R>(a, L, v);
-  interp16<R>(v, L, w1);
+  load_cell<F, R>(a, L, c);
+  interp_cell<F, R>(a, c, L, w1);
   const R fdt = (R)a.dt;
   const R d1lon = w1[0] * kdeg * Math<R>::rcp(cos_floor<R>(a, latm));
   const R d1lat = w1[1] * kdeg;
@@ -380,13 +418,13 @@ __device__ __forceinline__ void meso(const StepArgs &a, const double *s_plev, co
                                      double &lat, double &p, R &up, R &vp, R &wp) {
   R xi[3];
   normals3<R>(a.seed, id, step, 1u, xi);
-  R v[2][2][2][2][3];
+  Cell16<F> c;
   Loc<R> L;
   locate_xyz<R>(a, s_plev, s_idp, lon, lat, p, L);
   locate_t<R>(a, t_mid, L);
-  gather16<F, R>(a, L, v);
+  load_cell<F, R>(a, L, c);
   R sg[3];
-  sigma16<R>(v, sg);
+  sigma_cell<F, R>(a, c, L, sg);
   const R r = (R)a.r_ar;
   up = fma(r, up, (R)a.rs_fh * sg[0] * xi[0]);
   vp = fma(r, vp, (R)a.rs_fh * sg[1] * xi[1]);

@@ -27,8 +27,14 @@ struct SortArgs {
   const double *plev, *inv_dp;
   int nx, ny, nz;
   double lon0, inv_dlon, lat0, inv_dlat, lat_hi, p_top, p_bot;
-  uint32_t ntx, nty, ntz, nkeys;   // nkeys = ntx*nty*ntz + 1 (last: non-finite)
+  uint32_t ntx, nty, ntz, nkeys;   // nkeys = ntiles + max scenarios + 1
   int64_t n;
+  // scenario runs: parcels not yet released at the sort's step go behind the
+  // tiles, ordered by the release rank of their scenario; non-finite last
+  const uint16_t *scen;            // null: no scenarios
+  const int32_t *release, *rank;   // per scenario (device)
+  uint32_t step;                   // step the sort precedes (+ *step_dev if set)
+  const uint32_t *step_dev;
   uint32_t *keys;
   uint32_t *hist;                  // nkeys counters, then scanned in place
   uint32_t *block_sums;
@@ -52,6 +58,10 @@ struct ScatterArgs {
 };
 
 hipError_t launch_sort(const SortArgs &sa, const ScatterArgs &xa, hipStream_t stream);
+
+// Single-word device helpers (k_step.hip).
+hipError_t launch_set_u32(uint32_t *p, uint32_t v, hipStream_t stream);
+hipError_t launch_add_u32(uint32_t *p, uint32_t v, hipStream_t stream);
 size_t scan_block_sums_len(uint32_t nkeys);
 
 }  // namespace mpt

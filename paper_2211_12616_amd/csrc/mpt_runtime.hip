@@ -23,19 +23,28 @@ struct mpt_ctx {
   int64_t npts;
   float *scales;          // [nt][3][nz]
   double *plev, *inv_dp;  // [nz]
-  int32_t *release;       // [kMaxScen]
+  int32_t *release;       // [kMaxScen] release step per scenario
+  int32_t *rank;          // [kMaxScen] rank of the scenario in release order
+  int32_t *rel_sorted;    // [kMaxScen] release steps in ascending order
+  uint32_t *step_dev;     // step index read by graph-replayed kernels
   uint32_t *keys, *hist, *block_sums;
-  uint32_t ntx, nty, ntz, nkeys;
+  uint32_t ntx, nty, ntz, ntiles, nkeys;
   // host state
   double plev_h[kMaxLevels];
   uint64_t levels_ready;  // bit l set once level l was stored (nt <= 64)
   int32_t nscen;
+  // captured step loop (mpt_step_graph)
+  hipGraph_t graph;
+  hipGraphExec_t graph_exec;
+  mpt_particles graph_key;
+  int32_t graph_nsteps;
 };
 
 namespace {
 
 constexpr int kMaxScen = 65536;
 constexpr int kMaxTimeLevels = 64;
+constexpr int kPersistentBlocks = 2048;   // 256 CUs x 8 blocks
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -77,8 +86,9 @@ mpt_status check_params(const mpt_params *p, const mpt_grid *g) {
 }
 
 struct Layout {
-  size_t met, scales, plev, inv_dp, release, keys, hist, block_sums, total;
-  uint32_t ntx, nty, ntz, nkeys;
+  size_t met, scales, plev, inv_dp, release, rank, rel_sorted, step_dev, keys, hist, block_sums,
+      total;
+  uint32_t ntx, nty, ntz, ntiles, nkeys;
 };
 
 Layout layout(const mpt_grid *g, int64_t n_max) {
@@ -87,13 +97,17 @@ Layout layout(const mpt_grid *g, int64_t n_max) {
   L.ntx = (uint32_t)((g->nx + 7) / 8);
   L.nty = (uint32_t)((g->ny - 1 + 7) / 8);
   L.ntz = (uint32_t)((g->nz - 1 + 3) / 4);
-  L.nkeys = L.ntx * L.nty * L.ntz + 1;
+  L.ntiles = L.ntx * L.nty * L.ntz;
+  L.nkeys = L.ntiles + kMaxScen + 1;
   size_t off = 0;
   L.met = off;        off += align_up(npts * rec_bytes(g->dtype) * g->nt);
   L.scales = off;     off += align_up(sizeof(float) * 3 * g->nz * g->nt);
   L.plev = off;       off += align_up(sizeof(double) * g->nz);
   L.inv_dp = off;     off += align_up(sizeof(double) * g->nz);
   L.release = off;    off += align_up(sizeof(int32_t) * kMaxScen);
+  L.rank = off;       off += align_up(sizeof(int32_t) * kMaxScen);
+  L.rel_sorted = off; off += align_up(sizeof(int32_t) * kMaxScen);
+  L.step_dev = off;   off += align_up(sizeof(uint32_t));
   L.keys = off;       off += align_up(sizeof(uint32_t) * (size_t)(n_max > 0 ? n_max : 0));
   L.hist = off;       off += align_up(sizeof(uint32_t) * L.nkeys);
   L.block_sums = off; off += align_up(sizeof(uint32_t) * scan_block_sums_len(L.nkeys));
@@ -141,6 +155,12 @@ void fill_step_args(const mpt_ctx *c, const mpt_particles *P, uint32_t step0, in
   const int64_t nblk = (P->n + kBlock - 1) / kBlock;
   a.nblk = (int32_t)nblk;
   a.per_xcd = (int32_t)((nblk + kXcds - 1) / kXcds);
+  a.step_dev = nullptr;
+  a.persistent = 0;
+  a.nscen = c->nscen;
+  a.ntiles = c->ntiles;
+  a.cursor = c->hist;
+  a.rel_sorted = c->rel_sorted;
 }
 
 mpt_status check_particles(const mpt_ctx *c, const mpt_particles *P, bool need_pingpong) {
@@ -191,7 +211,8 @@ mpt_status check_time(const mpt_ctx *c, uint32_t step0, int64_t nsteps) {
   return MPT_OK;
 }
 
-mpt_status do_sort(mpt_ctx *c, mpt_particles *P, hipStream_t s) {
+// Sort before step `step` (added to the device step index when dev_step).
+mpt_status do_sort(mpt_ctx *c, mpt_particles *P, uint32_t step, bool dev_step, hipStream_t s) {
   const mpt_grid &g = c->grid;
   SortArgs sa;
   sa.lon = P->lon; sa.lat = P->lat; sa.p = P->p;
@@ -203,6 +224,11 @@ mpt_status do_sort(mpt_ctx *c, mpt_particles *P, hipStream_t s) {
   sa.p_top = c->plev_h[g.nz - 1]; sa.p_bot = c->plev_h[0];
   sa.ntx = c->ntx; sa.nty = c->nty; sa.ntz = c->ntz; sa.nkeys = c->nkeys;
   sa.n = P->n;
+  sa.scen = P->scen;
+  sa.release = c->release;
+  sa.rank = c->rank;
+  sa.step = step;
+  sa.step_dev = dev_step ? c->step_dev : nullptr;
   sa.keys = c->keys; sa.hist = c->hist; sa.block_sums = c->block_sums;
   const int64_t nblk = (P->n + kBlock - 1) / kBlock;
   sa.nblk = (int)nblk;
@@ -231,11 +257,57 @@ mpt_status do_sort(mpt_ctx *c, mpt_particles *P, hipStream_t s) {
   return MPT_OK;
 }
 
+// persistent: parcels are in the order the last sort of this call left
+// them (scenario runs only), so the launch may walk the active prefix.
 mpt_status run_steps(mpt_ctx *c, const mpt_particles *P, uint32_t step0, int nsteps, uint32_t flags,
-                     hipStream_t s) {
+                     bool dev_step, bool persistent, hipStream_t s) {
   StepArgs a;
   fill_step_args(c, P, step0, nsteps, flags, a);
+  if (dev_step) a.step_dev = c->step_dev;
+  if (persistent && P->scen) {
+    a.persistent = 1;
+    a.nblk = kPersistentBlocks;
+  }
   return from_hip(launch_step(c->grid.dtype, c->params.math == MPT_MATH_F64, a, s));
+}
+
+// The launch sequence of steps [first, first + count), all of them inside
+// one sort window or starting with its sort: sort at window starts, fused
+// launches of at most params.fuse steps.  Step indices are offsets from the
+// device step index when dev_step.
+mpt_status enqueue_steps(mpt_ctx *c, mpt_particles *P, int64_t first, int64_t count, bool dev_step,
+                         hipStream_t s) {
+  const int S = c->params.sort_interval;
+  const uint32_t flags = c->params.flags;
+  bool sorted = false;
+  int64_t cur = first;
+  const int64_t end = first + count;
+  while (cur < end) {
+    if (S > 0 && cur % S == 0) {
+      mpt_status st = do_sort(c, P, (uint32_t)cur, dev_step, s);
+      if (st != MPT_OK) return st;
+      sorted = true;
+    }
+    int64_t stop = end;
+    if (S > 0) {
+      const int64_t next_sort = (cur / S + 1) * S;
+      if (next_sort < stop) stop = next_sort;
+    }
+    if (stop - cur > c->params.fuse) stop = cur + c->params.fuse;
+    if (flags) {
+      mpt_status st = run_steps(c, P, (uint32_t)cur, (int)(stop - cur), flags, dev_step, sorted, s);
+      if (st != MPT_OK) return st;
+    }
+    cur = stop;
+  }
+  return MPT_OK;
+}
+
+void drop_graph(mpt_ctx *c) {
+  if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) hipGraphDestroy(c->graph);
+  c->graph_exec = nullptr;
+  c->graph = nullptr;
 }
 
 }  // namespace
@@ -282,10 +354,13 @@ mpt_status mpt_create(const mpt_grid *grid, const mpt_params *params, int64_t n_
   c->plev = reinterpret_cast<double *>(ws + L.plev);
   c->inv_dp = reinterpret_cast<double *>(ws + L.inv_dp);
   c->release = reinterpret_cast<int32_t *>(ws + L.release);
+  c->rank = reinterpret_cast<int32_t *>(ws + L.rank);
+  c->rel_sorted = reinterpret_cast<int32_t *>(ws + L.rel_sorted);
+  c->step_dev = reinterpret_cast<uint32_t *>(ws + L.step_dev);
   c->keys = reinterpret_cast<uint32_t *>(ws + L.keys);
   c->hist = reinterpret_cast<uint32_t *>(ws + L.hist);
   c->block_sums = reinterpret_cast<uint32_t *>(ws + L.block_sums);
-  c->ntx = L.ntx; c->nty = L.nty; c->ntz = L.ntz; c->nkeys = L.nkeys;
+  c->ntx = L.ntx; c->nty = L.nty; c->ntz = L.ntz; c->ntiles = L.ntiles; c->nkeys = L.nkeys;
 
   double idp[kMaxLevels];
   for (int k = 0; k < grid->nz - 1; ++k) idp[k] = 1.0 / (grid->plev[k] - grid->plev[k + 1]);
@@ -346,12 +421,41 @@ mpt_status mpt_copy_met_level(mpt_ctx *c, int32_t level, void *dst, float *scale
 mpt_status mpt_set_release(mpt_ctx *c, int32_t nscen, const int32_t *release_step, void *hip_stream) {
   if (!c || !release_step || nscen < 1 || nscen > kMaxScen) return MPT_ERR_ARG;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  // copied synchronously: the host array may be reused right after the call
-  if (hipMemcpyAsync(c->release, release_step, sizeof(int32_t) * nscen, hipMemcpyHostToDevice, s) !=
-          hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess)
+  // rank of each scenario in release order (ties by index), sorted table
+  int32_t *order = new (std::nothrow) int32_t[nscen];
+  int32_t *rank = new (std::nothrow) int32_t[nscen];
+  int32_t *sorted = new (std::nothrow) int32_t[nscen];
+  if (!order || !rank || !sorted) {
+    delete[] order; delete[] rank; delete[] sorted;
     return MPT_ERR_HIP;
+  }
+  for (int i = 0; i < nscen; ++i) order[i] = i;
+  // insertion sort by (release, index): stable, nscen <= 65536
+  for (int i = 1; i < nscen; ++i) {
+    const int32_t v = order[i];
+    int j = i - 1;
+    while (j >= 0 && release_step[order[j]] > release_step[v]) {
+      order[j + 1] = order[j];
+      --j;
+    }
+    order[j + 1] = v;
+  }
+  for (int r = 0; r < nscen; ++r) {
+    rank[order[r]] = r;
+    sorted[r] = release_step[order[r]];
+  }
+  // copied synchronously: the host arrays may be reused right after the call
+  const bool ok =
+      hipMemcpyAsync(c->release, release_step, sizeof(int32_t) * nscen, hipMemcpyHostToDevice, s) ==
+          hipSuccess &&
+      hipMemcpyAsync(c->rank, rank, sizeof(int32_t) * nscen, hipMemcpyHostToDevice, s) == hipSuccess &&
+      hipMemcpyAsync(c->rel_sorted, sorted, sizeof(int32_t) * nscen, hipMemcpyHostToDevice, s) ==
+          hipSuccess &&
+      hipStreamSynchronize(s) == hipSuccess;
+  delete[] order; delete[] rank; delete[] sorted;
+  if (!ok) return MPT_ERR_HIP;
   c->nscen = nscen;
+  drop_graph(c);
   return MPT_OK;
 }
 
@@ -362,7 +466,7 @@ mpt_status mpt_advect(mpt_ctx *c, const mpt_particles *P, uint32_t step, void *h
   st = check_time(c, step, 1);
   if (st != MPT_OK) return st;
   if (P->n == 0 || !(c->params.flags & MPT_ADVECT)) return MPT_OK;
-  return run_steps(c, P, step, 1, MPT_ADVECT, static_cast<hipStream_t>(hip_stream));
+  return run_steps(c, P, step, 1, MPT_ADVECT, false, false, static_cast<hipStream_t>(hip_stream));
 }
 
 mpt_status mpt_diffuse(mpt_ctx *c, const mpt_particles *P, uint32_t step, void *hip_stream) {
@@ -373,7 +477,7 @@ mpt_status mpt_diffuse(mpt_ctx *c, const mpt_particles *P, uint32_t step, void *
   if (st != MPT_OK) return st;
   const uint32_t f = c->params.flags & (MPT_TURB | MPT_MESO);
   if (P->n == 0 || !f) return MPT_OK;
-  return run_steps(c, P, step, 1, f, static_cast<hipStream_t>(hip_stream));
+  return run_steps(c, P, step, 1, f, false, false, static_cast<hipStream_t>(hip_stream));
 }
 
 mpt_status mpt_sort_particles(mpt_ctx *c, mpt_particles *P, void *hip_stream) {
@@ -381,7 +485,7 @@ mpt_status mpt_sort_particles(mpt_ctx *c, mpt_particles *P, void *hip_stream) {
   const mpt_status st = check_particles(c, P, true);
   if (st != MPT_OK) return st;
   if (P->n == 0) return MPT_OK;
-  return do_sort(c, P, static_cast<hipStream_t>(hip_stream));
+  return do_sort(c, P, 0u, false, static_cast<hipStream_t>(hip_stream));
 }
 
 mpt_status mpt_step(mpt_ctx *c, mpt_particles *P, uint32_t step0, int32_t nsteps, void *hip_stream) {
@@ -397,32 +501,55 @@ mpt_status mpt_step(mpt_ctx *c, mpt_particles *P, uint32_t step0, int32_t nsteps
   st = check_time(c, step0, nsteps);
   if (st != MPT_OK) return st;
   if (P->n == 0 || nsteps == 0) return MPT_OK;
+  return enqueue_steps(c, P, step0, nsteps, false, static_cast<hipStream_t>(hip_stream));
+}
+
+mpt_status mpt_step_graph(mpt_ctx *c, mpt_particles *P, uint32_t step0, int32_t nsteps,
+                          void *hip_stream) {
+  if (!c) return MPT_ERR_ARG;
+  const int S = c->params.sort_interval;
+  if (!hip_stream) return MPT_ERR_ARG;                 // capture needs a created stream
+  if (S <= 0 || step0 % (uint32_t)S != 0 || nsteps < 0 || nsteps % (2 * S) != 0)
+    return MPT_ERR_ARG;
+  mpt_status st = check_particles(c, P, nsteps > 0);
+  if (st != MPT_OK) return st;
+  st = check_time(c, step0, nsteps);
+  if (st != MPT_OK) return st;
+  if (P->n == 0 || nsteps == 0) return MPT_OK;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  const uint32_t flags = c->params.flags;
-  int64_t cur = step0;
-  const int64_t end = (int64_t)step0 + nsteps;
-  while (cur < end) {
-    if (S > 0 && cur % S == 0) {
-      st = do_sort(c, P, s);
-      if (st != MPT_OK) return st;
+  const bool same = c->graph_exec && memcmp(&c->graph_key, P, sizeof(*P)) == 0 &&
+                    c->graph_nsteps == 2 * S;
+  if (!same) {
+    drop_graph(c);
+    mpt_particles Q = *P;
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return MPT_ERR_HIP;
+    st = enqueue_steps(c, &Q, 0, 2 * S, true, s);
+    if (st == MPT_OK && launch_add_u32(c->step_dev, (uint32_t)(2 * S), s) != hipSuccess) st = MPT_ERR_HIP;
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &g);
+    if (st != MPT_OK || e != hipSuccess || !g) {
+      if (g) hipGraphDestroy(g);
+      return st != MPT_OK ? st : MPT_ERR_HIP;
     }
-    int64_t stop = end;
-    if (S > 0) {
-      const int64_t next_sort = (cur / S + 1) * S;
-      if (next_sort < stop) stop = next_sort;
+    hipGraphExec_t x = nullptr;
+    if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) {
+      hipGraphDestroy(g);
+      return MPT_ERR_HIP;
     }
-    if (stop - cur > c->params.fuse) stop = cur + c->params.fuse;
-    if (flags) {
-      st = run_steps(c, P, (uint32_t)cur, (int)(stop - cur), flags, s);
-      if (st != MPT_OK) return st;
-    }
-    cur = stop;
+    c->graph = g;
+    c->graph_exec = x;
+    c->graph_key = *P;
+    c->graph_nsteps = 2 * S;
   }
+  if (launch_set_u32(c->step_dev, step0, s) != hipSuccess) return MPT_ERR_HIP;
+  for (int32_t r = 0; r < nsteps / (2 * S); ++r)
+    if (hipGraphLaunch(c->graph_exec, s) != hipSuccess) return MPT_ERR_HIP;
   return MPT_OK;
 }
 
 mpt_status mpt_destroy(mpt_ctx *c) {
   if (!c) return MPT_ERR_ARG;
+  drop_graph(c);
   delete c;
   return MPT_OK;
 }
