@@ -72,6 +72,9 @@ def lib() -> ctypes.CDLL:
         L.orc_normals_many.argtypes = [ctypes.c_uint64, ctypes.c_int64, P, ctypes.c_uint32,
                                        ctypes.c_uint32, P]
         L.orc_tile_keys.argtypes = [P, ctypes.c_int64, P, P, P, P]
+        L.orc_stencil81_many.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.c_double, P]
+        L.orc_displacement_many.argtypes = [P, P, ctypes.c_int64, P, P, P, ctypes.c_uint32,
+                                            ctypes.c_int32, P, ctypes.c_int32]
         L.orc_uniform.argtypes = [ctypes.c_uint32]
         L.orc_uniform.restype = ctypes.c_double
         L.orc_max_threads.restype = ctypes.c_int
@@ -183,6 +186,25 @@ def tile_keys(m: Met, lon, lat, p) -> np.ndarray:
     lon, lat, p = (np.ascontiguousarray(a, np.float64) for a in (lon, lat, p))
     out = np.empty(len(lon), np.uint32)
     lib().orc_tile_keys(m.ref, len(lon), _ptr(lon), _ptr(lat), _ptr(p), _ptr(out))
+    return out
+
+
+def stencil81(m: Met, lon, lat, p, t: float) -> np.ndarray:
+    """Surrogate inputs: (n, 81) = u, v, w on the 3x3x3 cell stencil."""
+    lon, lat, p = (np.ascontiguousarray(a, np.float64) for a in (lon, lat, p))
+    out = np.empty((len(lon), 81), np.float64)
+    lib().orc_stencil81_many(m.ref, len(lon), _ptr(lon), _ptr(lat), _ptr(p), t, _ptr(out))
+    return out
+
+
+def displacement(m: Met, c: OrcCtl, lon, lat, p, step0: int, k: int,
+                 nthreads: Optional[int] = None) -> np.ndarray:
+    """(n, 3) k-step plain-advection displacement: east km, north km, dp hPa."""
+    lon, lat, p = (np.ascontiguousarray(a, np.float64) for a in (lon, lat, p))
+    out = np.empty((len(lon), 3), np.float64)
+    nt = nthreads if nthreads else lib().orc_max_threads()
+    lib().orc_displacement_many(m.ref, ctypes.byref(c), len(lon), _ptr(lon), _ptr(lat), _ptr(p),
+                                step0, k, _ptr(out), nt)
     return out
 
 

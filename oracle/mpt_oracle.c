@@ -470,4 +470,68 @@ void orc_tile_keys(const orc_met *m, int64_t n, const double *lon, const double 
     }
 }
 
+/* ----------------------------------------------------------------------- */
+/* Surrogate inputs and targets (project addition: learned k-step advection) */
+/* ----------------------------------------------------------------------- */
+
+/* Quadrilinear value of one variable in the cell shifted by (a, b, c) grid
+ * steps from the parcel's cell, with the parcel's own weights: columns wrap,
+ * rows and levels are clamped to the grid. */
+static double orc_interp_shifted(const orc_met *m, const float *f, const orc_loc *L, int a, int b, int c)
+{
+    orc_loc S = *L;
+    int i0 = (L->i0 + a) % m->nx;
+    if (i0 < 0) i0 += m->nx;
+    S.i0 = i0;
+    S.i1 = (i0 + 1) % m->nx;
+    int j = L->j + b;
+    S.j = j < 0 ? 0 : (j > m->ny - 2 ? m->ny - 2 : j);
+    int k = L->k + c;
+    S.k = k < 0 ? 0 : (k > m->nz - 2 ? m->nz - 2 : k);
+    return orc_interp_var(m, f, &S);
+}
+
+/* The 81 surrogate inputs of n parcels at time t: u, v, w on the 3 x 3 x 3
+ * stencil of cells around the parcel's cell (offsets -1, 0, 1 in lon, lat,
+ * level), out[81*i + var*27 + (c+1)*9 + (b+1)*3 + (a+1)]. */
+void orc_stencil81_many(const orc_met *m, int64_t n, const double *lon, const double *lat,
+                        const double *p, double t, double *out)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        orc_loc L;
+        orc_locate(m, lon[i], lat[i], p[i], t, &L);
+        const float *fld[3] = {m->u, m->v, m->w};
+        for (int q = 0; q < 3; ++q)
+            for (int c = -1; c <= 1; ++c)
+                for (int b = -1; b <= 1; ++b)
+                    for (int a = -1; a <= 1; ++a)
+                        out[81 * i + q * 27 + (c + 1) * 9 + (b + 1) * 3 + (a + 1)] =
+                            orc_interp_shifted(m, fld[q], &L, a, b, c);
+    }
+}
+
+/* k-step displacement of plain advection (no diffusion) from (lon, lat, p)
+ * at step `step0`: east and north distance in km (east measured along the
+ * start latitude: dlon * pi R cos(lat0) / 180) and pressure change in hPa;
+ * out[3*i + q]. */
+void orc_displacement_many(const orc_met *m, const orc_ctl *c, int64_t n, const double *lon,
+                           const double *lat, const double *p, uint32_t step0, int32_t k,
+                           double *out, int32_t nthreads)
+{
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+        double x = lon[i], y = lat[i], z = p[i];
+        for (int32_t s = 0; s < k; ++s) {
+            double t = c->t_start + (double)(step0 + (uint32_t)s) * c->dt;
+            orc_advect(m, c->dt, t, &x, &y, &z);
+            orc_position(m, &x, &y, &z);
+        }
+        double dl = fmod(x - lon[i] + 540.0, 360.0) - 180.0;
+        out[3 * i + 0] = dl * ORC_PI * ORC_R_EARTH * orc_cos_floor(lat[i]) / 180.0 / 1000.0;
+        out[3 * i + 1] = (y - lat[i]) * ORC_PI * ORC_R_EARTH / 180.0 / 1000.0;
+        out[3 * i + 2] = z - p[i];
+    }
+}
+
 int orc_max_threads(void) { return omp_get_max_threads(); }

@@ -72,6 +72,25 @@ def compare(gpu, ref, tol_deg, tol_hpa, label=""):
     return d.max(), dp.max()
 
 
+def compare_flips(gpu, ref, tol_deg, tol_hpa, max_frac, label=""):
+    """Reduced-precision full-physics trajectories.  The mesoscale spread is
+    a step function of the grid cell that holds the parcel; FP32 arithmetic
+    moves a parcel by ~1e-6 deg relative to the FP64 oracle, so now and then
+    the two sides take the spread from neighbouring cells and the AR(1)
+    state carries the difference on.  Such parcels may exceed the
+    tolerance; their fraction is bounded and reported, everything else must
+    be within the tolerance."""
+    np.testing.assert_array_equal(gpu.id, ref.id)
+    d = oracle.chord_deg(gpu.lon, gpu.lat, ref.lon, ref.lat)
+    dp = np.abs(gpu.p - ref.p)
+    bad = (d > tol_deg) | (dp > tol_hpa)
+    say(f"[{label}] n={len(d)} max chord {d.max():.3e} deg  p99 {np.percentile(d, 99):.3e}  "
+        f"max |dp| {dp.max():.3e} hPa  beyond tolerance {bad.sum()} ({bad.mean():.2e})")
+    assert bad.mean() <= max_frac, (label, bad.sum())
+    assert np.percentile(d, 99) <= tol_deg
+    return d, dp
+
+
 def assert_bitwise(a, b):
     for f in ("lon", "lat", "p", "up", "vp", "wp", "id"):
         np.testing.assert_array_equal(getattr(a, f), getattr(b, f), err_msg=f)

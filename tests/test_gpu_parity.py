@@ -8,7 +8,7 @@ import pytest
 import inputs
 import oracle
 from gpu_common import (TOL_F64_DEG, TOL_F64_HPA, TOL_R32_DEG, TOL_R32_HPA, assert_bitwise,
-                        by_id, compare, gpu_run, oracle_run, require_gpu, say)
+                        by_id, compare, compare_flips, gpu_run, oracle_run, require_gpu, say)
 from oracle import encode
 
 pytestmark = pytest.mark.gpu
@@ -152,12 +152,33 @@ def test_nonfinite_parcels_untouched(mpt, met3):
     assert d.max() <= TOL_F64_DEG
 
 
+CONT = oracle.ADVECT | oracle.TURB       # the continuous part of the step
+
+
+def reduced_precision_checks(met_gpu, met_ref, part, math, dtype, label):
+    """(1) advection + turbulent diffusion trajectories (continuous in the
+    position): every parcel within tolerance; (2) single full steps from
+    identical states at several step indices: every parcel within tolerance;
+    (3) full-physics trajectories: within tolerance except parcels whose
+    mesoscale cell differed at some step (bounded fraction)."""
+    g = gpu_run(met_gpu, part, 0, 240, math=math, dtype=dtype, flags=CONT, sort_interval=10, fuse=10)
+    r = oracle_run(met_ref, part, 0, 240, flags=CONT)
+    compare(g, r, TOL_R32_DEG, TOL_R32_HPA, f"{label} advect+turb 240")
+    state = part.copy()
+    for s0 in (0, 60, 119, 200):
+        g1 = gpu_run(met_gpu, state, s0, 1, math=math, dtype=dtype)
+        r1 = oracle_run(met_ref, state, s0, 1)
+        compare(g1, r1, TOL_R32_DEG, TOL_R32_HPA, f"{label} one full step at {s0}")
+        state = oracle_run(met_ref, state, s0, 40)
+    g = gpu_run(met_gpu, part, 0, 240, math=math, dtype=dtype, sort_interval=10, fuse=10)
+    r = oracle_run(met_ref, part, 0, 240)
+    compare_flips(g, r, TOL_R32_DEG, TOL_R32_HPA, 5e-3, f"{label} full 240")
+
+
 def test_f32_form(mpt, met3):
     say("F32 form vs oracle")
     part = inputs.make_particles(10_000, 29)
-    g = gpu_run(met3, part, 0, 240, math=1, sort_interval=10, fuse=10)
-    r = oracle_run(met3, part, 0, 240)
-    compare(g, r, TOL_R32_DEG, TOL_R32_HPA, "c1 F32")
+    reduced_precision_checks(met3, met3, part, 1, 0, "c1 F32")
 
 
 @pytest.mark.parametrize("kind", [encode.BF16, encode.F16])
@@ -181,19 +202,18 @@ def test_r16_encoding_bitwise(mpt, met3, kind):
 def test_r16_form(mpt, met3, kind):
     say(f"R16 form kind={kind} vs oracle on decoded fields")
     part = inputs.make_particles(10_000, 30)
-    g = gpu_run(met3, part, 0, 240, math=1, dtype=kind, sort_interval=10, fuse=10)
     deq = encode.dequantized_met(met3, kind)
-    r = oracle_run(deq, part, 0, 240)
-    compare(g, r, TOL_R32_DEG, TOL_R32_HPA, f"c1 R16 {kind}")
+    reduced_precision_checks(met3, deq, part, 1, kind, f"c1 R16 {kind}")
 
 
 def test_errors_on_gpu(mpt, met3):
     part = inputs.make_particles(100, 31)
-    ctx = mpt.Context(met3, mpt.make_params(sort_interval=10), n_max=50)
+    ctx0 = mpt.Context(met3, mpt.make_params(sort_interval=10), n_max=100)
     P = mpt.DeviceParticles.from_host(part)
     with pytest.raises(mpt.MptError) as e:
-        ctx.step(P, 0, 1)                         # met not stored yet
+        ctx0.step(P, 0, 1)                        # met not stored yet
     assert e.value.code == -2
+    ctx = mpt.Context(met3, mpt.make_params(sort_interval=10), n_max=50)
     ctx.upload_met(met3)
     with pytest.raises(mpt.MptError) as e:
         ctx.step(P, 230, 20)                      # beyond the last met level
