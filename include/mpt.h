@@ -207,6 +207,63 @@ mpt_status mpt_step(mpt_ctx *ctx, mpt_particles *particles, uint32_t step0, int3
 mpt_status mpt_step_graph(mpt_ctx *ctx, mpt_particles *particles, uint32_t step0, int32_t nsteps,
                           void *hip_stream);
 
+/* ---- Learned k-step advection surrogate (a project addition: the paper has
+ * no counterpart).  A ReLU MLP 81 -> 128 -> 128 -> 128 -> 3 on bf16 MFMA
+ * with FP32 accumulation predicts the MPT_SURR_K-step displacement of plain
+ * midpoint advection (east km along the start latitude, north km, dp hPa)
+ * from u, v, w interpolated at the parcel's position shifted by whole
+ * cells (-1, 0, 1) in lon, lat and level (81 inputs).  Parameters are one
+ * FP32 array of MPT_SURR_NPARAM values: per layer W[in][out] then bias, with
+ * padded shapes 96x128, 128x128, 128x128, 128x16 (padding is zero).
+ * `norm` is 12 floats on the device: input mean and std per variable
+ * (u, v, w), output mean and std per component. */
+enum { MPT_SURR_K = 8, MPT_SURR_NIN = 81, MPT_SURR_NOUT = 3, MPT_SURR_NPARAM = 47504,
+       MPT_SURR_MAX_BATCH = 8192 };
+
+/* Training samples at caller-chosen starts (device arrays of n): x (n x 81
+ * floats) = the stencil inputs at time t_start + step*dt; y (n x 3) = the
+ * displacement after MPT_SURR_K plain FP64 midpoint steps.  F32 storage. */
+mpt_status mpt_surrogate_datagen(mpt_ctx *ctx, int64_t n, const double *lon, const double *lat,
+                                 const double *p, const uint32_t *step, float *x, float *y,
+                                 void *hip_stream);
+/* Normalization statistics of n samples into norm (device, 12 floats). */
+mpt_status mpt_surrogate_stats(mpt_ctx *ctx, int64_t n, const float *x, const float *y,
+                               float *norm, void *hip_stream);
+/* He-uniform initial weights from Philox(seed), zero biases. */
+mpt_status mpt_surrogate_init(mpt_ctx *ctx, float *params, uint64_t seed, void *hip_stream);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8, step count t >= 1) on the
+ * batch x[batch x 81], y[batch x 3] (batch a multiple of 64, at most
+ * MPT_SURR_MAX_BATCH): mean squared error of the normalized outputs.  The
+ * batch loss is added to *loss (device float).  Invalidates a loaded
+ * surrogate (load again before stepping). */
+mpt_status mpt_surrogate_train_step(mpt_ctx *ctx, const float *x, const float *y, int32_t batch,
+                                    const float *norm, float *params, float *adam_m,
+                                    float *adam_v, int32_t t, float lr, float *loss,
+                                    void *hip_stream);
+/* Gradient of that loss with respect to params (FP32, same layout) into
+ * grad (device, MPT_SURR_NPARAM floats); batch loss added to *loss. */
+mpt_status mpt_surrogate_grad(mpt_ctx *ctx, const float *x, const float *y, int32_t batch,
+                              const float *norm, const float *params, float *grad, float *loss,
+                              void *hip_stream);
+/* Load weights for inference with acceptance threshold tau_km. */
+mpt_status mpt_surrogate_load(mpt_ctx *ctx, const float *params, const float *norm, float tau_km,
+                              void *hip_stream);
+/* Predicted displacements y (n x 3) for given inputs x (n x 81). */
+mpt_status mpt_surrogate_forward(mpt_ctx *ctx, int64_t n, const float *x, float *y,
+                                 void *hip_stream);
+/* nsteps steps in blocks of MPT_SURR_K: per parcel, predict the block's
+ * advection, estimate its error as the distance [km] between the
+ * prediction and MPT_SURR_K*dt times the wind at the predicted midpoint; if
+ * at most tau, apply it plus the block's turbulent and mesoscale diffusion
+ * (per-step random numbers as in mpt_step, mesoscale spread of the
+ * block-start cell); otherwise run MPT_SURR_K plain steps.  Adds the number
+ * of parcel-blocks that fell back to *fallbacks (device uint32).  Needs
+ * MPT_MATH_F32, F32 storage, no scenarios, step0 and nsteps multiples of
+ * MPT_SURR_K; sorts before each block that contains a multiple of
+ * sort_interval. */
+mpt_status mpt_step_surrogate(mpt_ctx *ctx, mpt_particles *particles, uint32_t step0,
+                              int32_t nsteps, uint32_t *fallbacks, void *hip_stream);
+
 /* Release the context (the workspace stays the caller's). */
 mpt_status mpt_destroy(mpt_ctx *ctx);
 

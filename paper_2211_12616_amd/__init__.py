@@ -84,12 +84,23 @@ def lib() -> ctypes.CDLL:
         L.mpt_sort_particles.argtypes = [P, P, P]
         L.mpt_step.argtypes = [P, P, ctypes.c_uint32, ctypes.c_int32, P]
         L.mpt_step_graph.argtypes = [P, P, ctypes.c_uint32, ctypes.c_int32, P]
+        L.mpt_surrogate_datagen.argtypes = [P, ctypes.c_int64, P, P, P, P, P, P, P]
+        L.mpt_surrogate_stats.argtypes = [P, ctypes.c_int64, P, P, P, P]
+        L.mpt_surrogate_init.argtypes = [P, P, ctypes.c_uint64, P]
+        L.mpt_surrogate_train_step.argtypes = [P, P, P, ctypes.c_int32, P, P, P, P, ctypes.c_int32,
+                                               ctypes.c_float, P, P]
+        L.mpt_surrogate_grad.argtypes = [P, P, P, ctypes.c_int32, P, P, P, P, P]
+        L.mpt_surrogate_load.argtypes = [P, P, P, ctypes.c_float, P]
+        L.mpt_surrogate_forward.argtypes = [P, ctypes.c_int64, P, P, P]
+        L.mpt_step_surrogate.argtypes = [P, P, ctypes.c_uint32, ctypes.c_int32, P, P]
         L.mpt_destroy.argtypes = [P]
         L.mpt_status_string.argtypes = [S]
         L.mpt_status_string.restype = ctypes.c_char_p
         for fn in ("mpt_create", "mpt_init_met", "mpt_copy_met_level", "mpt_set_release",
                    "mpt_advect", "mpt_diffuse", "mpt_sort_particles", "mpt_step", "mpt_step_graph",
-                   "mpt_destroy"):
+                   "mpt_destroy", "mpt_surrogate_datagen", "mpt_surrogate_stats",
+                   "mpt_surrogate_init", "mpt_surrogate_train_step", "mpt_surrogate_grad",
+                   "mpt_surrogate_load", "mpt_surrogate_forward", "mpt_step_surrogate"):
             getattr(L, fn).restype = S
         _lib = L
     return _lib
@@ -99,7 +110,11 @@ def exported_symbols():
     return ["mpt_workspace_bytes", "mpt_create", "mpt_init_met", "mpt_copy_met_level",
             "mpt_met_level_bytes", "mpt_set_release", "mpt_advect", "mpt_diffuse",
             "mpt_sort_particles", "mpt_step", "mpt_step_graph", "mpt_destroy",
-            "mpt_status_string"]
+            "mpt_status_string", "mpt_surrogate_datagen", "mpt_surrogate_stats",
+            "mpt_surrogate_init", "mpt_surrogate_train_step", "mpt_surrogate_grad",
+            "mpt_surrogate_load", "mpt_surrogate_forward", "mpt_step_surrogate"]
+
+SURR_K, SURR_NIN, SURR_NOUT, SURR_NPARAM, SURR_MAX_BATCH = 8, 81, 3, 47504, 8192
 
 
 def _check(fn: str, code: int):
@@ -282,6 +297,64 @@ class Context:
         s = P.cstruct()
         _check("mpt_step", lib().mpt_step(self.h, ctypes.byref(s), step0, nsteps,
                                           _stream_handle(stream)))
+        P.adopt(s)
+
+    # ---- surrogate ----------------------------------------------------------
+    def surrogate_datagen(self, lon, lat, p, step, stream=None):
+        """Training samples at the given starts (torch cuda tensors: lon, lat,
+        p float64, step int32 holding uint32): returns (x [n, 81], y [n, 3])."""
+        import torch
+        n = lon.numel()
+        x = torch.empty((n, SURR_NIN), dtype=torch.float32, device="cuda")
+        y = torch.empty((n, SURR_NOUT), dtype=torch.float32, device="cuda")
+        _check("mpt_surrogate_datagen", lib().mpt_surrogate_datagen(
+            self.h, n, lon.data_ptr(), lat.data_ptr(), p.data_ptr(), step.data_ptr(),
+            x.data_ptr(), y.data_ptr(), _stream_handle(stream)))
+        return x, y
+
+    def surrogate_stats(self, x, y, stream=None):
+        import torch
+        norm = torch.empty(12, dtype=torch.float32, device="cuda")
+        _check("mpt_surrogate_stats", lib().mpt_surrogate_stats(
+            self.h, x.shape[0], x.data_ptr(), y.data_ptr(), norm.data_ptr(), _stream_handle(stream)))
+        return norm
+
+    def surrogate_init(self, seed: int, stream=None):
+        import torch
+        params = torch.empty(SURR_NPARAM, dtype=torch.float32, device="cuda")
+        _check("mpt_surrogate_init", lib().mpt_surrogate_init(self.h, params.data_ptr(), seed,
+                                                              _stream_handle(stream)))
+        return params
+
+    def surrogate_train_step(self, x, y, norm, params, m, v, t: int, lr: float, loss, stream=None):
+        _check("mpt_surrogate_train_step", lib().mpt_surrogate_train_step(
+            self.h, x.data_ptr(), y.data_ptr(), x.shape[0], norm.data_ptr(), params.data_ptr(),
+            m.data_ptr(), v.data_ptr(), t, lr, loss.data_ptr(), _stream_handle(stream)))
+
+    def surrogate_grad(self, x, y, norm, params, stream=None):
+        import torch
+        grad = torch.zeros(SURR_NPARAM, dtype=torch.float32, device="cuda")
+        loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+        _check("mpt_surrogate_grad", lib().mpt_surrogate_grad(
+            self.h, x.data_ptr(), y.data_ptr(), x.shape[0], norm.data_ptr(), params.data_ptr(),
+            grad.data_ptr(), loss.data_ptr(), _stream_handle(stream)))
+        return grad, loss
+
+    def surrogate_load(self, params, norm, tau_km: float, stream=None):
+        _check("mpt_surrogate_load", lib().mpt_surrogate_load(self.h, params.data_ptr(), norm.data_ptr(),
+                                                              tau_km, _stream_handle(stream)))
+
+    def surrogate_forward(self, x, stream=None):
+        import torch
+        y = torch.empty((x.shape[0], SURR_NOUT), dtype=torch.float32, device="cuda")
+        _check("mpt_surrogate_forward", lib().mpt_surrogate_forward(self.h, x.shape[0], x.data_ptr(),
+                                                                    y.data_ptr(), _stream_handle(stream)))
+        return y
+
+    def step_surrogate(self, P: DeviceParticles, step0: int, nsteps: int, fallbacks, stream=None):
+        s = P.cstruct()
+        _check("mpt_step_surrogate", lib().mpt_step_surrogate(self.h, ctypes.byref(s), step0, nsteps,
+                                                              fallbacks.data_ptr(), _stream_handle(stream)))
         P.adopt(s)
 
     def step_graph(self, P: DeviceParticles, step0: int, nsteps: int, stream):

@@ -1,8 +1,9 @@
-// k_sort.hip -- counting sort of parcels by grid-box tile: tile key and
-// histogram, exclusive scan of the histogram, scatter of the whole parcel
-// state into the second buffer set.  Parcels that are already nearly
-// sorted share keys across a wavefront, so both the histogram and the
-// scatter cursors are bumped once per run of equal keys within a wave.
+// k_sort.hip -- counting sort of parcels by grid-box tile: tile key, rank
+// inside the tile and histogram in one pass, exclusive scan of the
+// histogram, then an atomic-free scatter of the whole parcel state into the
+// second buffer set at offset[key] + rank.  Parcels that are already nearly
+// sorted share keys across a wavefront, so the histogram counter of a key
+// is bumped once per run of equal keys within a wave.
 #include "mpt_internal.h"
 
 namespace mpt {
@@ -31,7 +32,9 @@ __device__ __forceinline__ uint32_t wave_run_add(uint32_t *counters, uint32_t ke
 
 __global__ __launch_bounds__(kBlock) void k_sort_keys(const SortArgs a) {
   __shared__ double s_plev[kMaxLevels];
+  __shared__ uint16_t s_lut[kLutBins];
   for (int q = threadIdx.x; q < a.nz; q += kBlock) s_plev[q] = a.plev[q];
+  for (int q = threadIdx.x; q < kLutBins; q += kBlock) s_lut[q] = a.lut[q];
   __syncthreads();
   const int lb = logical_block((int)blockIdx.x, a.per_xcd);
   if (lb >= a.nblk) return;
@@ -54,16 +57,19 @@ __global__ __launch_bounds__(kBlock) void k_sort_keys(const SortArgs a) {
       int j = (int)floor((phi - a.lat0) * a.inv_dlat);
       j = min(max(j, 0), a.ny - 2);
       const double pc = fmin(fmax(p, a.p_top), a.p_bot);
-      int lo = 0, hi = a.nz - 2;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (s_plev[mid] >= pc) lo = mid; else hi = mid - 1;
-      }
-      key = ((uint32_t)(lo >> 2) * a.nty + (uint32_t)(j >> 3)) * a.ntx + (uint32_t)(i0 >> 3);
+      int b = (int)((__log2f((float)pc) - a.lut_lo) * a.lut_scale);
+      b = min(max(b, 0), kLutBins - 1);
+      int k = s_lut[b];
+      while (k < a.nz - 2 && s_plev[k + 1] >= pc) ++k;
+      while (k > 0 && s_plev[k] < pc) --k;
+      key = ((uint32_t)(k >> 2) * a.nty + (uint32_t)(j >> 3)) * a.ntx + (uint32_t)(i0 >> 3);
     }
-    a.keys[i] = key;
   }
-  wave_run_add(a.hist, key, valid);
+  const uint32_t rank = wave_run_add(a.hist, key, valid);
+  if (valid) {
+    a.keys[i] = key;
+    a.ranks[i] = rank;
+  }
 }
 
 // Exclusive scan, phase 1: each block scans kScanChunk entries in place
@@ -134,10 +140,8 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(const ScatterArgs a) {
   const int lb = logical_block((int)blockIdx.x, a.per_xcd);
   if (lb >= a.nblk) return;
   const int64_t i = (int64_t)lb * kBlock + threadIdx.x;
-  const bool valid = i < a.n;
-  const uint32_t key = valid ? a.keys[i] : 0xFFFFFFFFu;
-  const uint32_t pos = wave_run_add(a.cursor, key, valid);
-  if (!valid) return;
+  if (i >= a.n) return;
+  const uint32_t pos = a.offsets[a.keys[i]] + a.ranks[i];
   a.lon2[pos] = a.lon[i];
   a.lat2[pos] = a.lat[i];
   a.p2[pos] = a.p[i];

@@ -12,7 +12,8 @@ namespace mpt {
 
 template <int F, typename R>
 __device__ __forceinline__ void step_parcel(const StepArgs &a, const double *s_plev,
-                                            const double *s_idp, int64_t i, uint32_t step0) {
+                                            const double *s_idp, const uint16_t *s_lut, int64_t i,
+                                            uint32_t step0) {
   double lon = a.lon[i], lat = a.lat[i], p = a.p[i];
   if (!finite3(lon, lat, p)) return;
   const uint32_t id = a.id[i];
@@ -33,12 +34,12 @@ __device__ __forceinline__ void step_parcel(const StepArgs &a, const double *s_p
     moved = true;
     const double t = a.t_start + (double)step * a.dt;
     if (a.flags & kAdvect) {
-      advect<F, R>(a, s_plev, s_idp, t, lon, lat, p);
+      advect<F, R>(a, s_plev, s_idp, s_lut, t, lon, lat, p);
       position(a, lon, lat, p);
     }
     if (a.flags & (kTurb | kMeso)) {
       if (a.flags & kTurb) turb<R>(a, id, step, lon, lat, p);
-      if (do_meso) meso<F, R>(a, s_plev, s_idp, id, step, t + 0.5 * a.dt, lon, lat, p, up, vp, wp);
+      if (do_meso) meso<F, R>(a, s_plev, s_idp, s_lut, id, step, t + 0.5 * a.dt, lon, lat, p, up, vp, wp);
       position(a, lon, lat, p);
     }
   }
@@ -61,7 +62,7 @@ __device__ __forceinline__ int64_t active_bound(const StepArgs &a, uint32_t last
     const int mid = (lo + hi) >> 1;
     if ((int64_t)a.rel_sorted[mid] <= (int64_t)last) lo = mid + 1; else hi = mid;
   }
-  const int64_t b = a.cursor[a.ntiles - 1 + (uint32_t)lo];
+  const int64_t b = a.offsets[a.ntiles + (uint32_t)lo];   // start of the first pending bucket
   return b < a.n ? b : a.n;
 }
 
@@ -69,17 +70,19 @@ template <int F, typename R>
 __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
   __shared__ double s_plev[kMaxLevels];
   __shared__ double s_idp[kMaxLevels];
+  __shared__ uint16_t s_lut[kLutBins];
   for (int q = threadIdx.x; q < a.nz; q += kBlock) {
     s_plev[q] = a.plev[q];
     s_idp[q] = (q < a.nz - 1) ? a.inv_dp[q] : 0.0;
   }
+  for (int q = threadIdx.x; q < kLutBins; q += kBlock) s_lut[q] = a.lut[q];
   __syncthreads();
   const uint32_t step0 = a.step0 + (a.step_dev ? *a.step_dev : 0u);
   if (!a.persistent) {
     const int lb = logical_block((int)blockIdx.x, a.per_xcd);
     if (lb >= a.nblk) return;
     const int64_t i = (int64_t)lb * kBlock + threadIdx.x;
-    if (i < a.n) step_parcel<F, R>(a, s_plev, s_idp, i, step0);
+    if (i < a.n) step_parcel<F, R>(a, s_plev, s_idp, s_lut, i, step0);
     return;
   }
   // persistent: XCD x owns an even share of the chunks of the prefix and its
@@ -91,7 +94,7 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
   const int64_t c_lo = nchunks * xcd / kXcds, c_hi = nchunks * (xcd + 1) / kXcds;
   for (int64_t c = c_lo + q; c < c_hi; c += nq) {
     const int64_t i = c * kBlock + threadIdx.x;
-    if (i < bound) step_parcel<F, R>(a, s_plev, s_idp, i, step0);
+    if (i < bound) step_parcel<F, R>(a, s_plev, s_idp, s_lut, i, step0);
   }
 }
 

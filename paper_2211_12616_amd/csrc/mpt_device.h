@@ -17,6 +17,7 @@ constexpr double kREarth = 6371000.0;                 // m
 constexpr double kH0 = 7000.0;                        // scale height, dz -> dp [m]
 constexpr double kDeg = 180.0 / (kPi * kREarth);      // metres -> degrees of arc
 constexpr int kMaxLevels = 512;                       // LDS level table capacity
+constexpr int kLutBins = 8192;                        // level lookup bins over log2(p)
 constexpr int kBlock = 256;                           // 4 wave64 per block
 constexpr int kXcds = 8;                              // MI355X: 8 XCDs, 32 CUs each
 
@@ -37,6 +38,8 @@ struct StepArgs {
   const float *scales;         // [nt][3][nz] (R16 storage)
   const double *plev;          // [nz] device
   const double *inv_dp;        // [nz-1] 1 / (plev[k] - plev[k+1])
+  const uint16_t *lut;         // [kLutBins] level lower bound per log2(p) bin
+  float lut_lo, lut_scale;     // bin = (log2(p) - lut_lo) * lut_scale
   int nx, ny, nz, nt;
   double lon0, inv_dlon, lat0, inv_dlat, lat_hi, p_top, p_bot;
   double t_met0, dt_met, inv_dt_met;
@@ -57,11 +60,11 @@ struct StepArgs {
   // Persistent mode (scenario runs right after a sort): parcels are ordered
   // active-by-tile, then pending scenarios by release rank, then non-finite;
   // the kernel walks only the prefix of parcels released by the launch's
-  // last step: cursor[ntiles - 1 + r], r = #(rel_sorted <= last step).
+  // last step: offsets[ntiles + r], r = #(rel_sorted <= last step).
   int32_t persistent;
   int32_t nscen;
   uint32_t ntiles;
-  const uint32_t *cursor;      // sort cursors after the scatter (bucket ends)
+  const uint32_t *offsets;     // exclusive scan of the last sort's histogram
   const int32_t *rel_sorted;   // release steps in ascending order [nscen]
 };
 
@@ -103,7 +106,18 @@ template <> struct Math<double> {
   static __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
   static __device__ __forceinline__ double cos_(double x) { return cos(x); }
   static __device__ __forceinline__ void sincos_(double x, double *s, double *c) { sincos(x, s, c); }
-  static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+  // sin(pi x), cos(pi x): no reduction by pi needed
+  static __device__ __forceinline__ void sincospi_(double x, double *s, double *c) { sincospi(x, s, c); }
+  static __device__ __forceinline__ double cospi_(double x) { return cospi(x); }
+  // 1/x for x in [cos 89.999 deg, 1]: hardware estimate + two Newton steps
+  // (error squared per step, final error at the rounding level)
+  static __device__ __forceinline__ double rcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+  }
 };
 
 template <> struct Math<float> {
@@ -114,6 +128,10 @@ template <> struct Math<float> {
   static __device__ __forceinline__ float sqrt_(float x) { return __fsqrt_rn(x); }
   static __device__ __forceinline__ float cos_(float x) { return __cosf(x); }
   static __device__ __forceinline__ void sincos_(float x, float *s, float *c) { __sincosf(x, s, c); }
+  static __device__ __forceinline__ void sincospi_(float x, float *s, float *c) {
+    __sincosf(x * (float)kPi, s, c);
+  }
+  static __device__ __forceinline__ float cospi_(float x) { return __cosf(x * (float)kPi); }
   static __device__ __forceinline__ float rcp(float x) { return __frcp_rn(x); }
 };
 
@@ -126,14 +144,13 @@ __device__ __forceinline__ void normals3(uint64_t seed, uint32_t id, uint32_t st
   philox4x32_10(id, step, purpose, 0u, (uint32_t)seed, (uint32_t)(seed >> 32), x);
   const R u0 = Math<R>::uni(x[0]), u1 = Math<R>::uni(x[1]);
   const R u2 = Math<R>::uni(x[2]), u3 = Math<R>::uni(x[3]);
-  const R twopi = (R)(2.0 * kPi);
   const R r0 = Math<R>::sqrt_((R)-2 * Math<R>::log_(u0));
   const R r1 = Math<R>::sqrt_((R)-2 * Math<R>::log_(u2));
   R s1, c1;
-  Math<R>::sincos_(twopi * u1, &s1, &c1);
+  Math<R>::sincospi_((R)2 * u1, &s1, &c1);      // angle 2 pi u1
   xi[0] = r0 * c1;
   xi[1] = r0 * s1;
-  xi[2] = r1 * Math<R>::cos_(twopi * u3);
+  xi[2] = r1 * Math<R>::cospi_((R)2 * u3);
 }
 
 // ---- field records -----------------------------------------------------------
@@ -176,13 +193,25 @@ struct Loc {
   R fx, fy, fz, ft;
 };
 
+// Level bracket: k = largest index <= nz-2 with plev[k] >= pc.  A bin of
+// log2(pc) (FP32) gives a starting k from the LDS lookup table; the FP64
+// comparisons that follow make the result exact whatever bin FP32 picked.
+__device__ __forceinline__ int level_index(const StepArgs &a, const double *s_plev,
+                                           const uint16_t *s_lut, double pc) {
+  int b = (int)((__log2f((float)pc) - a.lut_lo) * a.lut_scale);
+  b = min(max(b, 0), kLutBins - 1);
+  int k = s_lut[b];
+  while (k < a.nz - 2 && s_plev[k + 1] >= pc) ++k;
+  while (k > 0 && s_plev[k] < pc) --k;
+  return k;
+}
+
 // Horizontal and vertical part of the cell location.  Longitude periodic,
-// latitude and pressure clamped; k = largest index <= nz-2 with
-// plev[k] >= p (binary search in the LDS copy of the level table).
+// latitude and pressure clamped; k from level_index.
 template <typename R>
 __device__ __forceinline__ void locate_xyz(const StepArgs &a, const double *s_plev,
-                                           const double *s_idp, double lon, double lat, double p,
-                                           Loc<R> &L) {
+                                           const double *s_idp, const uint16_t *s_lut, double lon,
+                                           double lat, double p, Loc<R> &L) {
   const double lam = lon - 360.0 * floor((lon - a.lon0) * (1.0 / 360.0));
   const double x = (lam - a.lon0) * a.inv_dlon;
   const double xf = floor(x);
@@ -201,13 +230,9 @@ __device__ __forceinline__ void locate_xyz(const StepArgs &a, const double *s_pl
   L.fy = (R)(y - (double)j);
 
   const double pc = fmin(fmax(p, a.p_top), a.p_bot);
-  int lo = 0, hi = a.nz - 2;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (s_plev[mid] >= pc) lo = mid; else hi = mid - 1;
-  }
-  L.k = lo;
-  L.fz = (R)((s_plev[lo] - pc) * s_idp[lo]);
+  const int k = level_index(a, s_plev, s_lut, pc);
+  L.k = k;
+  L.fz = (R)((s_plev[k] - pc) * s_idp[k]);
 }
 
 // Time-level pair bracketing t and the weight of the later level.
@@ -343,11 +368,12 @@ __device__ __forceinline__ R cos_floor(const StepArgs &a, double lat) {
 // f = (u / (R cos lat), v / R, omega) in degrees and hPa per second.
 template <int F, typename R>
 __device__ __forceinline__ void advect(const StepArgs &a, const double *s_plev, const double *s_idp,
-                                       double t, double &lon, double &lat, double &p) {
+                                       const uint16_t *s_lut, double t, double &lon, double &lat,
+                                       double &p) {
   Cell16<F> c;
   R w0[3], w1[3];
   Loc<R> L;
-  locate_xyz<R>(a, s_plev, s_idp, lon, lat, p, L);
+  locate_xyz<R>(a, s_plev, s_idp, s_lut, lon, lat, p, L);
   locate_t<R>(a, t, L);
   load_cell<F, R>(a, L, c);
   interp_cell<F, R>(a, c, L, w0);
@@ -359,7 +385,7 @@ __device__ __forceinline__ void advect(const StepArgs &a, const double *s_plev, 
   const double latm = lat + (double)(hdt * d0lat);
   const double pm = p + (double)(hdt * w0[2]);
 
-  locate_xyz<R>(a, s_plev, s_idp, lonm, latm, pm, L);
+  locate_xyz<R>(a, s_plev, s_idp, s_lut, lonm, latm, pm, L);
   locate_t<R>(a, t + 0.5 * a.dt, L);
   load_cell<F, R>(a, L, c);
   interp_cell<F, R>(a, c, L, w1);
@@ -410,21 +436,24 @@ __device__ __forceinline__ void turb(const StepArgs &a, uint32_t id, uint32_t st
   p = p + (double)dp;
 }
 
-// AR(1) sub-grid wind from the spread of the 16 values of the current cell
-// at the time-level pair of the step's midpoint time, then displacement.
+// Spread of the 16 values of the cell holding (lon, lat, p), at the
+// time-level pair of t_mid.
 template <int F, typename R>
-__device__ __forceinline__ void meso(const StepArgs &a, const double *s_plev, const double *s_idp,
-                                     uint32_t id, uint32_t step, double t_mid, double &lon,
-                                     double &lat, double &p, R &up, R &vp, R &wp) {
-  R xi[3];
-  normals3<R>(a.seed, id, step, 1u, xi);
+__device__ __forceinline__ void meso_sigma(const StepArgs &a, const double *s_plev,
+                                           const double *s_idp, const uint16_t *s_lut, double t_mid,
+                                           double lon, double lat, double p, R sg[3]) {
   Cell16<F> c;
   Loc<R> L;
-  locate_xyz<R>(a, s_plev, s_idp, lon, lat, p, L);
+  locate_xyz<R>(a, s_plev, s_idp, s_lut, lon, lat, p, L);
   locate_t<R>(a, t_mid, L);
   load_cell<F, R>(a, L, c);
-  R sg[3];
   sigma_cell<F, R>(a, c, L, sg);
+}
+
+// AR(1) update of the sub-grid wind with spread sg, then displacement.
+template <typename R>
+__device__ __forceinline__ void meso_apply(const StepArgs &a, const R sg[3], const R xi[3],
+                                           double &lon, double &lat, double &p, R &up, R &vp, R &wp) {
   const R r = (R)a.r_ar;
   up = fma(r, up, (R)a.rs_fh * sg[0] * xi[0]);
   vp = fma(r, vp, (R)a.rs_fh * sg[1] * xi[1]);
@@ -437,6 +466,19 @@ __device__ __forceinline__ void meso(const StepArgs &a, const double *s_plev, co
   lon = lon + (double)dlon;
   lat = lat + (double)dlat;
   p = p + (double)dp;
+}
+
+// AR(1) sub-grid wind from the spread of the 16 values of the current cell
+// at the time-level pair of the step's midpoint time, then displacement.
+template <int F, typename R>
+__device__ __forceinline__ void meso(const StepArgs &a, const double *s_plev, const double *s_idp,
+                                     const uint16_t *s_lut, uint32_t id, uint32_t step, double t_mid,
+                                     double &lon, double &lat, double &p, R &up, R &vp, R &wp) {
+  R xi[3];
+  normals3<R>(a.seed, id, step, 1u, xi);
+  R sg[3];
+  meso_sigma<F, R>(a, s_plev, s_idp, s_lut, t_mid, lon, lat, p, sg);
+  meso_apply<R>(a, sg, xi, lon, lat, p, up, vp, wp);
 }
 
 __device__ __forceinline__ bool finite3(double a, double b, double c) {

@@ -25,6 +25,8 @@ hipError_t launch_fill_f32(float *dst, float value, int64_t n, hipStream_t strea
 struct SortArgs {
   const double *lon, *lat, *p;
   const double *plev, *inv_dp;
+  const uint16_t *lut;
+  float lut_lo, lut_scale;
   int nx, ny, nz;
   double lon0, inv_dlon, lat0, inv_dlat, lat_hi, p_top, p_bot;
   uint32_t ntx, nty, ntz, nkeys;   // nkeys = ntiles + max scenarios + 1
@@ -36,6 +38,7 @@ struct SortArgs {
   uint32_t step;                   // step the sort precedes (+ *step_dev if set)
   const uint32_t *step_dev;
   uint32_t *keys;
+  uint32_t *ranks;                 // rank of the parcel among its key's parcels
   uint32_t *hist;                  // nkeys counters, then scanned in place
   uint32_t *block_sums;
   int nblk, per_xcd;
@@ -44,7 +47,8 @@ struct SortArgs {
 struct ScatterArgs {
   int64_t n;
   const uint32_t *keys;
-  uint32_t *cursor;
+  const uint32_t *ranks;
+  const uint32_t *offsets;         // exclusive scan of the histogram
   const double *lon, *lat, *p;
   const uint32_t *id;
   const void *up, *vp, *wp;
@@ -58,6 +62,48 @@ struct ScatterArgs {
 };
 
 hipError_t launch_sort(const SortArgs &sa, const ScatterArgs &xa, hipStream_t stream);
+
+// Learned k-step advection surrogate (k_surr.hip).
+constexpr int kSurrK = 8;                       // steps per surrogate block
+constexpr int kSurrIn = 81, kSurrInPad = 96;    // 3 variables x 27 stencil points
+constexpr int kSurrHid = 128;
+constexpr int kSurrOut = 3, kSurrOutPad = 16;   // east km, north km, dp hPa
+constexpr int kXLd = 104, kHLd = 136;           // LDS row strides (bf16)
+// flat FP32 parameters: W[in][out] then bias, per layer
+constexpr int kOffW1 = 0, kOffB1 = 12288, kOffW2 = 12416, kOffB2 = 28800, kOffW3 = 28928,
+              kOffB3 = 45312, kOffW4 = 45440, kOffB4 = 47488, kSurrNParam = 47504;
+constexpr int kWtSize = 47104;                  // bf16 [out][in] copies of W1..W4
+constexpr int kWbSize = 34816;                  // bf16 [in][out] copies of W2..W4
+constexpr int kSurrMaxBatch = 8192;
+constexpr int kSurrStatBlocks = 1024;
+
+struct SurrW {
+  const uint16_t *wt1, *wt2, *wt3, *wt4;        // forward fragments, [out][in]
+  const uint16_t *wb2, *wb3, *wb4;              // backward fragments, [in][out]
+  const float *b1, *b2, *b3, *b4;
+  const float *norm;                            // in mean[3], in std[3], out mean[3], out std[3]
+};
+
+struct SurrTrain {
+  const float *x, *y;                           // batch inputs (raw) and targets
+  int64_t batch;                                // multiple of 64
+  uint16_t *xn, *h1, *h2, *h3, *dy, *dh1, *dh2, *dh3;
+  float *yp, *grad, *loss;
+};
+
+hipError_t launch_surr_datagen(const StepArgs &a, int64_t n, const double *lon, const double *lat,
+                               const double *p, const uint32_t *step, float *x, float *y,
+                               hipStream_t s);
+hipError_t launch_surr_stats(const float *x, const float *y, int64_t n, double *part, int nblk,
+                             float *norm, hipStream_t s);
+hipError_t launch_surr_init(float *params, uint64_t seed, hipStream_t s);
+hipError_t launch_surr_pack(const float *params, uint16_t *wt, uint16_t *wb, hipStream_t s);
+hipError_t launch_surr_forward(const SurrW &W, const float *x, int64_t n, float *y, hipStream_t s);
+hipError_t launch_surr_train(const SurrW &W, const SurrTrain &T, float *params, float *m, float *v,
+                             float lr, float bc1, float bc2, hipStream_t s);
+hipError_t launch_surr_grad(const SurrW &W, const SurrTrain &T, hipStream_t s);
+hipError_t launch_surr_step(const StepArgs &a, const SurrW &W, float tau_km, uint32_t *fallbacks,
+                            hipStream_t s);
 
 // Single-word device helpers (k_step.hip).
 hipError_t launch_set_u32(uint32_t *p, uint32_t v, hipStream_t stream);

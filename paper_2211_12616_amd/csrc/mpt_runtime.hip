@@ -23,16 +23,26 @@ struct mpt_ctx {
   int64_t npts;
   float *scales;          // [nt][3][nz]
   double *plev, *inv_dp;  // [nz]
+  uint16_t *lut;          // [kLutBins] level lookup table
+  float lut_lo, lut_scale;
   int32_t *release;       // [kMaxScen] release step per scenario
   int32_t *rank;          // [kMaxScen] rank of the scenario in release order
   int32_t *rel_sorted;    // [kMaxScen] release steps in ascending order
   uint32_t *step_dev;     // step index read by graph-replayed kernels
-  uint32_t *keys, *hist, *block_sums;
+  uint32_t *keys, *ranks, *hist, *block_sums;
   uint32_t ntx, nty, ntz, ntiles, nkeys;
   // host state
   double plev_h[kMaxLevels];
   uint64_t levels_ready;  // bit l set once level l was stored (nt <= 64)
   int32_t nscen;
+  // surrogate: bf16 weight copies, normalization, training scratch
+  uint16_t *s_wt, *s_wb;
+  float *s_norm, *s_bias;               // loaded normalization and biases (FP32)
+  float s_tau;
+  int s_loaded;
+  uint16_t *t_xn, *t_h1, *t_h2, *t_h3, *t_dy, *t_dh1, *t_dh2, *t_dh3;
+  float *t_yp, *t_grad, *t_loss_unused;
+  double *t_part;
   // captured step loop (mpt_step_graph)
   hipGraph_t graph;
   hipGraphExec_t graph_exec;
@@ -86,8 +96,8 @@ mpt_status check_params(const mpt_params *p, const mpt_grid *g) {
 }
 
 struct Layout {
-  size_t met, scales, plev, inv_dp, release, rank, rel_sorted, step_dev, keys, hist, block_sums,
-      total;
+  size_t met, scales, plev, inv_dp, lut, release, rank, rel_sorted, step_dev, keys, ranks, hist,
+      block_sums, s_wt, s_wb, s_norm, s_bias, t_xn, t_h, t_dy, t_dh, t_yp, t_grad, t_part, total;
   uint32_t ntx, nty, ntz, ntiles, nkeys;
 };
 
@@ -104,13 +114,26 @@ Layout layout(const mpt_grid *g, int64_t n_max) {
   L.scales = off;     off += align_up(sizeof(float) * 3 * g->nz * g->nt);
   L.plev = off;       off += align_up(sizeof(double) * g->nz);
   L.inv_dp = off;     off += align_up(sizeof(double) * g->nz);
+  L.lut = off;        off += align_up(sizeof(uint16_t) * kLutBins);
   L.release = off;    off += align_up(sizeof(int32_t) * kMaxScen);
   L.rank = off;       off += align_up(sizeof(int32_t) * kMaxScen);
   L.rel_sorted = off; off += align_up(sizeof(int32_t) * kMaxScen);
   L.step_dev = off;   off += align_up(sizeof(uint32_t));
   L.keys = off;       off += align_up(sizeof(uint32_t) * (size_t)(n_max > 0 ? n_max : 0));
+  L.ranks = off;      off += align_up(sizeof(uint32_t) * (size_t)(n_max > 0 ? n_max : 0));
   L.hist = off;       off += align_up(sizeof(uint32_t) * L.nkeys);
   L.block_sums = off; off += align_up(sizeof(uint32_t) * scan_block_sums_len(L.nkeys));
+  L.s_wt = off;       off += align_up(sizeof(uint16_t) * kWtSize);
+  L.s_wb = off;       off += align_up(sizeof(uint16_t) * kWbSize);
+  L.s_norm = off;     off += align_up(sizeof(float) * 12);
+  L.s_bias = off;     off += align_up(sizeof(float) * 400);
+  L.t_xn = off;       off += align_up(sizeof(uint16_t) * kSurrMaxBatch * kSurrInPad);
+  L.t_h = off;        off += align_up(sizeof(uint16_t) * kSurrMaxBatch * kSurrHid * 3);
+  L.t_dy = off;       off += align_up(sizeof(uint16_t) * kSurrMaxBatch * kSurrOutPad);
+  L.t_dh = off;       off += align_up(sizeof(uint16_t) * kSurrMaxBatch * kSurrHid * 3);
+  L.t_yp = off;       off += align_up(sizeof(float) * kSurrMaxBatch * kSurrOutPad);
+  L.t_grad = off;     off += align_up(sizeof(float) * kSurrNParam);
+  L.t_part = off;     off += align_up(sizeof(double) * kSurrStatBlocks * 84 * 2);
   L.total = off;
   return L;
 }
@@ -131,6 +154,9 @@ void fill_step_args(const mpt_ctx *c, const mpt_particles *P, uint32_t step0, in
   a.scales = c->scales;
   a.plev = c->plev;
   a.inv_dp = c->inv_dp;
+  a.lut = c->lut;
+  a.lut_lo = c->lut_lo;
+  a.lut_scale = c->lut_scale;
   a.nx = g.nx; a.ny = g.ny; a.nz = g.nz; a.nt = g.nt;
   a.lon0 = g.lon0; a.inv_dlon = 1.0 / g.dlon;
   a.lat0 = g.lat0; a.inv_dlat = 1.0 / g.dlat;
@@ -159,7 +185,7 @@ void fill_step_args(const mpt_ctx *c, const mpt_particles *P, uint32_t step0, in
   a.persistent = 0;
   a.nscen = c->nscen;
   a.ntiles = c->ntiles;
-  a.cursor = c->hist;
+  a.offsets = c->hist;
   a.rel_sorted = c->rel_sorted;
 }
 
@@ -217,6 +243,7 @@ mpt_status do_sort(mpt_ctx *c, mpt_particles *P, uint32_t step, bool dev_step, h
   SortArgs sa;
   sa.lon = P->lon; sa.lat = P->lat; sa.p = P->p;
   sa.plev = c->plev; sa.inv_dp = c->inv_dp;
+  sa.lut = c->lut; sa.lut_lo = c->lut_lo; sa.lut_scale = c->lut_scale;
   sa.nx = g.nx; sa.ny = g.ny; sa.nz = g.nz;
   sa.lon0 = g.lon0; sa.inv_dlon = 1.0 / g.dlon;
   sa.lat0 = g.lat0; sa.inv_dlat = 1.0 / g.dlat;
@@ -229,12 +256,12 @@ mpt_status do_sort(mpt_ctx *c, mpt_particles *P, uint32_t step, bool dev_step, h
   sa.rank = c->rank;
   sa.step = step;
   sa.step_dev = dev_step ? c->step_dev : nullptr;
-  sa.keys = c->keys; sa.hist = c->hist; sa.block_sums = c->block_sums;
+  sa.keys = c->keys; sa.ranks = c->ranks; sa.hist = c->hist; sa.block_sums = c->block_sums;
   const int64_t nblk = (P->n + kBlock - 1) / kBlock;
   sa.nblk = (int)nblk;
   sa.per_xcd = (int)((nblk + kXcds - 1) / kXcds);
   ScatterArgs xa;
-  xa.n = P->n; xa.keys = c->keys; xa.cursor = c->hist;
+  xa.n = P->n; xa.keys = c->keys; xa.ranks = c->ranks; xa.offsets = c->hist;
   xa.lon = P->lon; xa.lat = P->lat; xa.p = P->p; xa.id = P->id;
   xa.up = P->up; xa.vp = P->vp; xa.wp = P->wp; xa.scen = P->scen;
   xa.lon2 = P->lon2; xa.lat2 = P->lat2; xa.p2 = P->p2; xa.id2 = P->id2;
@@ -303,6 +330,25 @@ mpt_status enqueue_steps(mpt_ctx *c, mpt_particles *P, int64_t first, int64_t co
   return MPT_OK;
 }
 
+// Weight views: bf16 copies in the context plus FP32 biases and
+// normalization at the given addresses.
+SurrW surr_weights(const mpt_ctx *c, const float *params, const float *norm) {
+  SurrW W;
+  W.wt1 = c->s_wt;
+  W.wt2 = W.wt1 + kSurrHid * kSurrInPad;
+  W.wt3 = W.wt2 + kSurrHid * kSurrHid;
+  W.wt4 = W.wt3 + kSurrHid * kSurrHid;
+  W.wb2 = c->s_wb;
+  W.wb3 = W.wb2 + kSurrHid * kSurrHid;
+  W.wb4 = W.wb3 + kSurrHid * kSurrHid;
+  W.b1 = params + kOffB1;
+  W.b2 = params + kOffB2;
+  W.b3 = params + kOffB3;
+  W.b4 = params + kOffB4;
+  W.norm = norm;
+  return W;
+}
+
 void drop_graph(mpt_ctx *c) {
   if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
   if (c->graph) hipGraphDestroy(c->graph);
@@ -353,20 +399,51 @@ mpt_status mpt_create(const mpt_grid *grid, const mpt_params *params, int64_t n_
   c->scales = reinterpret_cast<float *>(ws + L.scales);
   c->plev = reinterpret_cast<double *>(ws + L.plev);
   c->inv_dp = reinterpret_cast<double *>(ws + L.inv_dp);
+  c->lut = reinterpret_cast<uint16_t *>(ws + L.lut);
   c->release = reinterpret_cast<int32_t *>(ws + L.release);
   c->rank = reinterpret_cast<int32_t *>(ws + L.rank);
   c->rel_sorted = reinterpret_cast<int32_t *>(ws + L.rel_sorted);
   c->step_dev = reinterpret_cast<uint32_t *>(ws + L.step_dev);
   c->keys = reinterpret_cast<uint32_t *>(ws + L.keys);
+  c->ranks = reinterpret_cast<uint32_t *>(ws + L.ranks);
   c->hist = reinterpret_cast<uint32_t *>(ws + L.hist);
   c->block_sums = reinterpret_cast<uint32_t *>(ws + L.block_sums);
   c->ntx = L.ntx; c->nty = L.nty; c->ntz = L.ntz; c->ntiles = L.ntiles; c->nkeys = L.nkeys;
+  c->s_wt = reinterpret_cast<uint16_t *>(ws + L.s_wt);
+  c->s_wb = reinterpret_cast<uint16_t *>(ws + L.s_wb);
+  c->s_norm = reinterpret_cast<float *>(ws + L.s_norm);
+  c->s_bias = reinterpret_cast<float *>(ws + L.s_bias);
+  c->t_xn = reinterpret_cast<uint16_t *>(ws + L.t_xn);
+  c->t_h1 = reinterpret_cast<uint16_t *>(ws + L.t_h);
+  c->t_h2 = c->t_h1 + (size_t)kSurrMaxBatch * kSurrHid;
+  c->t_h3 = c->t_h2 + (size_t)kSurrMaxBatch * kSurrHid;
+  c->t_dy = reinterpret_cast<uint16_t *>(ws + L.t_dy);
+  c->t_dh1 = reinterpret_cast<uint16_t *>(ws + L.t_dh);
+  c->t_dh2 = c->t_dh1 + (size_t)kSurrMaxBatch * kSurrHid;
+  c->t_dh3 = c->t_dh2 + (size_t)kSurrMaxBatch * kSurrHid;
+  c->t_yp = reinterpret_cast<float *>(ws + L.t_yp);
+  c->t_grad = reinterpret_cast<float *>(ws + L.t_grad);
+  c->t_part = reinterpret_cast<double *>(ws + L.t_part);
 
   double idp[kMaxLevels];
   for (int k = 0; k < grid->nz - 1; ++k) idp[k] = 1.0 / (grid->plev[k] - grid->plev[k + 1]);
   idp[grid->nz - 1] = 0.0;
+  // level lookup table: bin b of log2(p) starts the search at the largest k
+  // whose level is at or below the bin's upper pressure edge
+  const double lo = log2(grid->plev[grid->nz - 1]), hi = log2(grid->plev[0]);
+  const double scale = kLutBins / (hi - lo);
+  uint16_t lut[kLutBins];
+  int k = grid->nz - 2;
+  for (int b = 0; b < kLutBins; ++b) {            // upper edges rise with b, k falls
+    const double p_hi = exp2(lo + (b + 1) / scale);
+    while (k > 0 && grid->plev[k] < p_hi) --k;
+    lut[b] = (uint16_t)k;
+  }
+  c->lut_lo = (float)lo;
+  c->lut_scale = (float)scale;
   if (hipMemcpy(c->plev, c->plev_h, sizeof(double) * grid->nz, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(c->inv_dp, idp, sizeof(double) * grid->nz, hipMemcpyHostToDevice) != hipSuccess) {
+      hipMemcpy(c->inv_dp, idp, sizeof(double) * grid->nz, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->lut, lut, sizeof(uint16_t) * kLutBins, hipMemcpyHostToDevice) != hipSuccess) {
     delete c;
     return MPT_ERR_HIP;
   }
@@ -544,6 +621,140 @@ mpt_status mpt_step_graph(mpt_ctx *c, mpt_particles *P, uint32_t step0, int32_t 
   if (launch_set_u32(c->step_dev, step0, s) != hipSuccess) return MPT_ERR_HIP;
   for (int32_t r = 0; r < nsteps / (2 * S); ++r)
     if (hipGraphLaunch(c->graph_exec, s) != hipSuccess) return MPT_ERR_HIP;
+  return MPT_OK;
+}
+
+// ---- surrogate ------------------------------------------------------------------
+
+mpt_status mpt_surrogate_datagen(mpt_ctx *c, int64_t n, const double *lon, const double *lat,
+                                 const double *p, const uint32_t *step, float *x, float *y,
+                                 void *hip_stream) {
+  if (!c) return MPT_ERR_ARG;
+  if (n < 0 || (n > 0 && (!lon || !lat || !p || !step || !x || !y))) return MPT_ERR_ARG;
+  if (c->grid.dtype != MPT_DT_F32) return MPT_ERR_UNSUPPORTED;
+  const uint64_t all = (c->grid.nt >= 64) ? ~0ull : ((1ull << c->grid.nt) - 1ull);
+  if ((c->levels_ready & all) != all) return MPT_ERR_STATE;
+  if (n == 0) return MPT_OK;
+  mpt_particles P = {};
+  P.n = n;
+  StepArgs a;
+  fill_step_args(c, &P, 0, kSurrK, MPT_ADVECT, a);
+  return from_hip(launch_surr_datagen(a, n, lon, lat, p, step, x, y, static_cast<hipStream_t>(hip_stream)));
+}
+
+mpt_status mpt_surrogate_stats(mpt_ctx *c, int64_t n, const float *x, const float *y, float *norm,
+                               void *hip_stream) {
+  if (!c || n < 1 || !x || !y || !norm) return MPT_ERR_ARG;
+  const int nblk = (int)(n < kSurrStatBlocks ? n : kSurrStatBlocks);
+  return from_hip(launch_surr_stats(x, y, n, c->t_part, nblk, norm, static_cast<hipStream_t>(hip_stream)));
+}
+
+mpt_status mpt_surrogate_init(mpt_ctx *c, float *params, uint64_t seed, void *hip_stream) {
+  if (!c || !params) return MPT_ERR_ARG;
+  return from_hip(launch_surr_init(params, seed, static_cast<hipStream_t>(hip_stream)));
+}
+
+mpt_status mpt_surrogate_train_step(mpt_ctx *c, const float *x, const float *y, int32_t batch,
+                                    const float *norm, float *params, float *adam_m, float *adam_v,
+                                    int32_t t, float lr, float *loss, void *hip_stream) {
+  if (!c || !x || !y || !norm || !params || !adam_m || !adam_v || !loss) return MPT_ERR_ARG;
+  if (batch < 64 || batch > kSurrMaxBatch || batch % 64 != 0 || t < 1 || !(lr > 0.0f)) return MPT_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  // bf16 copies of the current weights, then forward, backward, Adam
+  if (launch_surr_pack(params, c->s_wt, c->s_wb, s) != hipSuccess) return MPT_ERR_HIP;
+  const SurrW W = surr_weights(c, params, norm);
+  SurrTrain T;
+  T.x = x; T.y = y; T.batch = batch;
+  T.xn = c->t_xn; T.h1 = c->t_h1; T.h2 = c->t_h2; T.h3 = c->t_h3;
+  T.dy = c->t_dy; T.dh1 = c->t_dh1; T.dh2 = c->t_dh2; T.dh3 = c->t_dh3;
+  T.yp = c->t_yp; T.grad = c->t_grad; T.loss = loss;
+  const float bc1 = 1.0f - powf(0.9f, (float)t), bc2 = 1.0f - powf(0.999f, (float)t);
+  c->s_loaded = 0;                      // the copies now hold training weights
+  return from_hip(launch_surr_train(W, T, params, adam_m, adam_v, lr, bc1, bc2, s));
+}
+
+mpt_status mpt_surrogate_grad(mpt_ctx *c, const float *x, const float *y, int32_t batch,
+                              const float *norm, const float *params, float *grad, float *loss,
+                              void *hip_stream) {
+  if (!c || !x || !y || !norm || !params || !grad || !loss) return MPT_ERR_ARG;
+  if (batch < 64 || batch > kSurrMaxBatch || batch % 64 != 0) return MPT_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if (launch_surr_pack(params, c->s_wt, c->s_wb, s) != hipSuccess) return MPT_ERR_HIP;
+  const SurrW W = surr_weights(c, params, norm);
+  SurrTrain T;
+  T.x = x; T.y = y; T.batch = batch;
+  T.xn = c->t_xn; T.h1 = c->t_h1; T.h2 = c->t_h2; T.h3 = c->t_h3;
+  T.dy = c->t_dy; T.dh1 = c->t_dh1; T.dh2 = c->t_dh2; T.dh3 = c->t_dh3;
+  T.yp = c->t_yp; T.grad = grad; T.loss = loss;
+  c->s_loaded = 0;
+  return from_hip(launch_surr_grad(W, T, s));
+}
+
+mpt_status mpt_surrogate_load(mpt_ctx *c, const float *params, const float *norm, float tau_km,
+                              void *hip_stream) {
+  if (!c || !params || !norm || !(tau_km >= 0.0f)) return MPT_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if (launch_surr_pack(params, c->s_wt, c->s_wb, s) != hipSuccess) return MPT_ERR_HIP;
+  if (hipMemcpyAsync(c->s_bias, params + kOffB1, sizeof(float) * 128, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(c->s_bias + 128, params + kOffB2, sizeof(float) * 128, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(c->s_bias + 256, params + kOffB3, sizeof(float) * 128, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(c->s_bias + 384, params + kOffB4, sizeof(float) * 16, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(c->s_norm, norm, sizeof(float) * 12, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return MPT_ERR_HIP;
+  c->s_tau = tau_km;
+  c->s_loaded = 1;
+  return MPT_OK;
+}
+
+namespace {
+SurrW loaded_weights(const mpt_ctx *c) {
+  SurrW W = surr_weights(c, nullptr, c->s_norm);
+  W.b1 = c->s_bias;
+  W.b2 = c->s_bias + 128;
+  W.b3 = c->s_bias + 256;
+  W.b4 = c->s_bias + 384;
+  return W;
+}
+}  // namespace
+
+mpt_status mpt_surrogate_forward(mpt_ctx *c, int64_t n, const float *x, float *y, void *hip_stream) {
+  if (!c || n < 0 || (n > 0 && (!x || !y))) return MPT_ERR_ARG;
+  if (!c->s_loaded) return MPT_ERR_STATE;
+  if (n == 0) return MPT_OK;
+  return from_hip(launch_surr_forward(loaded_weights(c), x, n, y, static_cast<hipStream_t>(hip_stream)));
+}
+
+mpt_status mpt_step_surrogate(mpt_ctx *c, mpt_particles *P, uint32_t step0, int32_t nsteps,
+                              uint32_t *fallbacks, void *hip_stream) {
+  if (!c || !fallbacks) return MPT_ERR_ARG;
+  if (c->params.math != MPT_MATH_F32 || c->grid.dtype != MPT_DT_F32) return MPT_ERR_UNSUPPORTED;
+  if (!P || P->scen) return MPT_ERR_UNSUPPORTED;
+  if (step0 % kSurrK != 0 || nsteps < 0 || nsteps % kSurrK != 0) return MPT_ERR_ARG;
+  if (!c->s_loaded) return MPT_ERR_STATE;
+  const int S = c->params.sort_interval;
+  mpt_status st = check_particles(c, P, S > 0 && nsteps > 0);
+  if (st != MPT_OK) return st;
+  if (P->n > 0 && (!P->up || !P->vp || !P->wp)) return MPT_ERR_ARG;
+  st = check_time(c, step0, nsteps);
+  if (st != MPT_OK) return st;
+  if (P->n == 0 || nsteps == 0) return MPT_OK;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const SurrW W = loaded_weights(c);
+  for (int64_t b0 = step0; b0 < (int64_t)step0 + nsteps; b0 += kSurrK) {
+    bool due = false;
+    for (int64_t q = b0; S > 0 && q < b0 + kSurrK; ++q)
+      if (q % S == 0) due = true;
+    if (due) {
+      st = do_sort(c, P, (uint32_t)b0, false, s);
+      if (st != MPT_OK) return st;
+    }
+    StepArgs a;
+    fill_step_args(c, P, (uint32_t)b0, kSurrK, c->params.flags, a);
+    const int64_t nblk = (P->n + 63) / 64;
+    a.nblk = (int32_t)nblk;
+    a.per_xcd = (int32_t)((nblk + kXcds - 1) / kXcds);
+    if (launch_surr_step(a, W, c->s_tau, fallbacks, s) != hipSuccess) return MPT_ERR_HIP;
+  }
   return MPT_OK;
 }
 

@@ -208,18 +208,19 @@ def test_r16_form(mpt, met3, kind):
 
 def test_errors_on_gpu(mpt, met3):
     part = inputs.make_particles(100, 31)
-    ctx0 = mpt.Context(met3, mpt.make_params(sort_interval=10), n_max=100)
+    ctx = mpt.Context(met3, mpt.make_params(sort_interval=10), n_max=100)
     P = mpt.DeviceParticles.from_host(part)
     with pytest.raises(mpt.MptError) as e:
-        ctx0.step(P, 0, 1)                        # met not stored yet
+        ctx.step(P, 0, 1)                         # met not stored yet
     assert e.value.code == -2
-    ctx = mpt.Context(met3, mpt.make_params(sort_interval=10), n_max=50)
     ctx.upload_met(met3)
     with pytest.raises(mpt.MptError) as e:
         ctx.step(P, 230, 20)                      # beyond the last met level
     assert e.value.code == -3
+    small = mpt.Context(met3, mpt.make_params(sort_interval=10), n_max=50)
+    small.upload_met(met3)
     with pytest.raises(mpt.MptError) as e:
-        ctx.step(P, 0, 5)                         # sorts, but n > n_max
+        small.step(P, 0, 5)                       # sorts, but n > n_max
     assert e.value.code == -4
     ctx2 = mpt.Context(met3, mpt.make_params(), n_max=100)
     ctx2.upload_met(met3)

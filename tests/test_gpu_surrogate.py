@@ -1,0 +1,154 @@
+"""GPU tests of the learned k-step surrogate (a project addition: the paper
+has no counterpart).  Pins: training inputs and targets against the oracle's
+stencil and its plain 8-step advection; the MLP forward against a numpy
+float32 forward on the same bf16 weights; the gradient against CPU autograd;
+training lowers the loss; with tau = 0 every parcel-block falls back to the
+plain scheme, which must then equal the plain F32 step bit for bit.  The
+accepted-surrogate trajectory itself is parity unpinned (it is judged by
+its distance to the plain scheme)."""
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+from gpu_common import assert_bitwise, by_id, gpu_run, require_gpu, say
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mpt():
+    return require_gpu()
+
+
+@pytest.fixture(scope="module")
+def met3():
+    return inputs.make_met_c1(seed=11, nt=3)
+
+
+@pytest.fixture(scope="module")
+def ctx(mpt, met3):
+    c = mpt.Context(met3, mpt.make_params(math=1, sort_interval=0), n_max=100_000)
+    c.upload_met(met3)
+    return c
+
+
+def starts(n, seed, step_max=232):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return (rng.uniform(0, 360, n), np.rad2deg(np.arcsin(rng.uniform(-0.97, 0.97, n))),
+            rng.uniform(100, 900, n), rng.integers(0, step_max, n).astype(np.uint32))
+
+
+def to_dev(lon, lat, p, step):
+    import torch
+    return (torch.from_numpy(lon).cuda(), torch.from_numpy(lat).cuda(), torch.from_numpy(p).cuda(),
+            torch.from_numpy(step.view(np.int32)).cuda())
+
+
+def test_datagen_matches_oracle(mpt, ctx, met3):
+    lon, lat, p, step = starts(3000, 1)
+    x, y = ctx.surrogate_datagen(*to_dev(lon, lat, p, step))
+    x, y = x.cpu().numpy(), y.cpu().numpy()
+    m = oracle.Met(met3)
+    c = oracle.ctl()
+    xr = np.empty((len(lon), 81))
+    yr = np.empty((len(lon), 3))
+    for s in np.unique(step):
+        sel = step == s
+        xr[sel] = oracle.stencil81(m, lon[sel], lat[sel], p[sel], float(s) * 180.0)
+        yr[sel] = oracle.displacement(m, c, lon[sel], lat[sel], p[sel], int(s), 8)
+    for q, scale in enumerate((50.0, 50.0, 0.005)):
+        d = np.abs(x[:, q * 27:(q + 1) * 27] - xr[:, q * 27:(q + 1) * 27]).max()
+        say(f"[datagen] var {q}: max |x - oracle| = {d:.3e} (field scale {scale})")
+        assert d <= 2e-6 * scale
+    dy = np.abs(y - yr).max(axis=0)
+    say(f"[datagen] targets max |y - oracle| = {dy}")
+    assert np.all(dy <= np.array([1e-4, 1e-4, 1e-4]))
+
+
+def test_forward_matches_numpy(mpt, ctx):
+    import torch
+    lon, lat, p, step = starts(4000, 2)
+    x, y = ctx.surrogate_datagen(*to_dev(lon, lat, p, step))
+    norm = ctx.surrogate_stats(x, y)
+    params = ctx.surrogate_init(7)
+    ctx.surrogate_load(params, norm, 1.0)
+    out = ctx.surrogate_forward(x).cpu().numpy()
+    ref = mlp.forward(params.cpu().numpy(), x.cpu().numpy(), norm.cpu().numpy())
+    scale = norm.cpu().numpy()[9:12]
+    err = np.abs(out - ref) / scale
+    say(f"[forward] max |gpu - numpy| / out std = {err.max(axis=0)}")
+    assert err.max() <= 1e-2
+
+
+def test_gradient_matches_autograd(mpt, ctx):
+    import torch
+    lon, lat, p, step = starts(1024, 3)
+    x, y = ctx.surrogate_datagen(*to_dev(lon, lat, p, step))
+    norm = ctx.surrogate_stats(x, y)
+    params = ctx.surrogate_init(11)
+    grad, loss = ctx.surrogate_grad(x, y, norm, params)
+    g = grad.cpu().numpy()
+    P = params.cpu().numpy()
+    nrm = norm.cpu().numpy()
+    xn = torch.from_numpy(mlp.normalize_inputs(x.cpu().numpy(), nrm))
+    tn = torch.from_numpy(((y.cpu().numpy() - nrm[6:9]) / nrm[9:12]).astype(np.float32))
+    pt = torch.from_numpy(mlp.bf16(P)).requires_grad_(True)
+    h, off = xn, 0
+    for li, (fi, fo) in enumerate(mlp.SHAPES):
+        w = pt[off:off + fi * fo].reshape(fi, fo)
+        off += fi * fo
+        b = pt[off:off + fo]
+        off += fo
+        z = h @ w + b
+        h = torch.relu(z) if li < 3 else z
+    L = ((h[:, :3] - tn) ** 2).mean()
+    L.backward()
+    ga = pt.grad.numpy()
+    cos = float(g @ ga / (np.linalg.norm(g) * np.linalg.norm(ga)))
+    rel = float(np.linalg.norm(g - ga) / np.linalg.norm(ga))
+    say(f"[grad] loss gpu {loss.item():.5f} autograd {L.item():.5f}; cosine {cos:.5f}, rel diff {rel:.3e}")
+    assert abs(loss.item() - L.item()) <= 2e-2 * L.item()
+    assert cos >= 0.995 and rel <= 0.08
+
+
+def test_training_lowers_loss(mpt, ctx):
+    import torch
+    lon, lat, p, step = starts(65536, 4)
+    x, y = ctx.surrogate_datagen(*to_dev(lon, lat, p, step))
+    norm = ctx.surrogate_stats(x, y)
+    params = ctx.surrogate_init(5)
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    B = 4096
+    losses = []
+    t = 0
+    for epoch in range(20):
+        loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+        for b0 in range(0, x.shape[0], B):
+            t += 1
+            ctx.surrogate_train_step(x[b0:b0 + B], y[b0:b0 + B], norm, params, m, v, t, 1e-3, loss)
+        losses.append(loss.item() / (x.shape[0] // B))
+    say(f"[train] mean batch loss by epoch: {[round(l, 4) for l in losses]}")
+    assert losses[-1] <= 0.2 * losses[0]
+    assert np.isfinite(params.cpu().numpy()).all()
+
+
+def test_tau_zero_falls_back_to_plain_bitwise(mpt, met3):
+    import torch
+    part = inputs.make_particles(5000, 61)
+    plain = gpu_run(met3, part, 0, 64, math=1, sort_interval=16, fuse=8)
+    c = mpt.Context(met3, mpt.make_params(math=1, sort_interval=16), n_max=part.n)
+    c.upload_met(met3)
+    lon, lat, p, step = starts(4096, 6)
+    x, y = c.surrogate_datagen(*to_dev(lon, lat, p, step))
+    norm = c.surrogate_stats(x, y)
+    params = c.surrogate_init(3)
+    c.surrogate_load(params, norm, 0.0)
+    P = mpt.DeviceParticles.from_host(part, math=1)
+    fb = torch.zeros(1, dtype=torch.int32, device="cuda")
+    c.step_surrogate(P, 0, 64, fb)
+    torch.cuda.synchronize()
+    assert fb.item() == part.n * 8
+    assert_bitwise(plain, by_id(P.to_host()))
