@@ -53,7 +53,177 @@ def parse():
                     help="target wall time of the CPU-oracle sample (0 = skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
+    ap.add_argument("--scenarios", action="store_true",
+                    help="also run the batched release workload (16 scenarios, 480 steps)")
+    ap.add_argument("--surrogate", action="store_true",
+                    help="also train and run the learned 8-step surrogate (480 steps)")
+    ap.add_argument("--surr-train", type=float, default=5e7, help="surrogate training segments")
+    ap.add_argument("--surr-epochs", type=int, default=2)
+    ap.add_argument("--surr-bound-km", type=float, default=1.0,
+                    help="p99 bound on the accepted 8-step advection error used to set tau")
     return ap.parse_args()
+
+
+def run_scenarios(met, mpt, inputs, torch, nsteps=480):
+    """Batched releases: 16 scenarios of 1e4..2e7 parcels (log-uniform), each
+    a point or column release at a random place and step, FP32 fields,
+    advection + diffusion for 480 steps through the graph-replayed loop."""
+    sc = inputs.make_scenarios(seed=24)
+    part, scen = inputs.make_scenario_particles(sc, seed=24)
+    n = part.n
+    ctx = mpt.Context(met, mpt.make_params(math=1, sort_interval=10, fuse=10), n_max=n)
+    ctx.upload_met(met)
+    ctx.set_release(sc.release_step)
+    P = mpt.DeviceParticles.from_host(part, math=1, scen=scen)
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(s):
+        ctx.step_graph(P, 0, nsteps, s)
+    s.synchronize()
+    elapsed = time.perf_counter() - t0
+    active = int(np.sum(sc.sizes * np.maximum(0, nsteps - np.minimum(sc.release_step, nsteps))))
+    lon = P.lon.cpu().numpy()
+    return {"workload": "16 release scenarios (1e4..2e7 parcels, log-uniform), 0.3deg grid, "
+                        "480 steps, FP32, graph-replayed loop, persistent launches",
+            "n_particles": int(n), "steps": nsteps, "active_particle_steps": active,
+            "active_particle_steps_per_s": active / elapsed, "seconds": elapsed,
+            "finite": bool(np.isfinite(lon).all())}
+
+
+def run_surrogate(met, mpt, inputs, torch, args, nsteps=480):
+    """Learned 8-step surrogate: train on plain-scheme segments, set tau on
+    held-out parcels, then run 1e8 parcels for 480 steps and compare with the
+    plain FP32 run (time and distance)."""
+    K = mpt.SURR_K
+    rng = np.random.Generator(np.random.PCG64(25))
+    ntr = int(args.surr_train)
+    ctx = mpt.Context(met, mpt.make_params(math=1, sort_interval=0, fuse=10), n_max=200_000)
+    ctx.upload_met(met)
+    steps_max = nsteps - K
+    xs, ys = [], []
+    t0 = time.perf_counter()
+    chunk = 5_000_000
+    for c0 in range(0, ntr, chunk):
+        m = min(chunk, ntr - c0)
+        lon = torch.from_numpy(rng.uniform(0, 360, m)).cuda()
+        lat = torch.from_numpy(np.rad2deg(np.arcsin(rng.uniform(-0.985, 0.985, m)))).cuda()
+        p = torch.from_numpy(rng.uniform(100, 900, m)).cuda()
+        st = torch.from_numpy((rng.integers(0, steps_max // K + 1, m) * K).astype(np.int32)).cuda()
+        x, y = ctx.surrogate_datagen(lon, lat, p, st)
+        xs.append(x)
+        ys.append(y)
+    x = torch.cat(xs)
+    y = torch.cat(ys)
+    del xs, ys
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    norm = ctx.surrogate_stats(x, y)
+    params = ctx.surrogate_init(26)
+    mom = torch.zeros_like(params)
+    var = torch.zeros_like(params)
+    B = 4096
+    t = 0
+    losses = []
+    t0 = time.perf_counter()
+    for ep in range(args.surr_epochs):
+        loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+        nb = 0
+        for b0 in range(0, ntr - B + 1, B):
+            t += 1
+            nb += 1
+            ctx.surrogate_train_step(x[b0:b0 + B], y[b0:b0 + B], norm, params, mom, var, t, 1e-3, loss)
+        losses.append(loss.item() / nb)
+        log(f"surrogate epoch {ep}: mean batch loss {losses[-1]:.5f}")
+    t_train = time.perf_counter() - t0
+    del x, y
+    torch.cuda.empty_cache()
+
+    # tau: held-out parcels, advection only, one block from several starts
+    ncal = 200_000
+    cal = inputs.make_particles(ncal, 27)
+    ctxc = mpt.Context(met, mpt.make_params(math=1, sort_interval=0, flags=mpt.ADVECT), n_max=ncal)
+    ctxc.upload_met(met)
+    ctxc.surrogate_load(params, norm, float("inf"))
+    errs, trues = [], []
+    for s0 in (0, 120, 240, 360):
+        A = mpt.DeviceParticles.from_host(cal, math=1, pingpong=False)
+        Bp = mpt.DeviceParticles.from_host(cal, math=1, pingpong=False)
+        fb = torch.zeros(1, dtype=torch.int32, device="cuda")
+        e = torch.empty(ncal, dtype=torch.float32, device="cuda")
+        ctxc.step_surrogate(A, s0, K, fb, e)
+        ctxc.step(Bp, s0, K)
+        torch.cuda.synchronize()
+        a, bq = A.to_host(), Bp.to_host()
+        d = _chord_km(a.lon, a.lat, bq.lon, bq.lat)
+        errs.append(e.cpu().numpy())
+        trues.append(d)
+    est = np.concatenate(errs)
+    true = np.concatenate(trues)
+    order = np.argsort(est)
+    tau = 0.0
+    lo = 0
+    for q in np.linspace(0.05, 1.0, 96):
+        k = int(q * len(order))
+        if k < 100:
+            continue
+        if np.percentile(true[order[:k]], 99) <= args.surr_bound_km:
+            tau = float(est[order[k - 1]])
+            lo = k
+    accepted_frac_cal = lo / len(order)
+    log(f"surrogate tau = {tau:.4f} km (accepts {accepted_frac_cal:.3f} of held-out blocks)")
+
+    # production run vs plain, 1e8 parcels (the benchmark's parcels), all modules
+    n = int(args.n)
+    part = inputs.make_particles(n, 23)
+    ctxs = mpt.Context(met, mpt.make_params(math=1, sort_interval=16, fuse=8), n_max=n)
+    ctxs.upload_met(met)
+    ctxs.surrogate_load(params, norm, tau)
+    S = mpt.DeviceParticles.from_host(part, math=1)
+    fb = torch.zeros(1, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctxs.step_surrogate(S, 0, nsteps, fb)
+    torch.cuda.synchronize()
+    t_surr = time.perf_counter() - t0
+    hs = S.to_host()
+    del S
+    torch.cuda.empty_cache()
+    ctxp = mpt.Context(met, mpt.make_params(math=1, sort_interval=16, fuse=8), n_max=n)
+    ctxp.upload_met(met)
+    Pp = mpt.DeviceParticles.from_host(part, math=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctxp.step(Pp, 0, nsteps)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    hp = Pp.to_host()
+    del Pp
+    torch.cuda.empty_cache()
+    oa, ob = np.argsort(hs.id), np.argsort(hp.id)
+    d = _chord_km(hs.lon[oa], hs.lat[oa], hp.lon[ob], hp.lat[ob])
+    blocks = n * (nsteps // K)
+    return {"workload": "learned 8-step surrogate, 1e8 parcels, 0.3deg grid, 480 steps, FP32 fields, "
+                        "advect+turb+meso; fallback to plain midpoint",
+            "train_segments": ntr, "epochs": args.surr_epochs, "loss_by_epoch": losses,
+            "datagen_s": t_data, "train_s": t_train, "tau_km": tau,
+            "accept_bound_p99_km": args.surr_bound_km, "heldout_accept_frac": accepted_frac_cal,
+            "fallback_rate": fb.item() / blocks,
+            "surrogate_particle_steps_per_s": n * nsteps / t_surr,
+            "plain_f32_particle_steps_per_s": n * nsteps / t_plain,
+            "speedup_vs_plain_f32": t_plain / t_surr,
+            "error_vs_plain_km": {"p50": float(np.percentile(d, 50)), "p99": float(np.percentile(d, 99)),
+                                  "max": float(d.max())}}
+
+
+def _chord_km(lon1, lat1, lon2, lat2):
+    r = np.pi / 180.0
+
+    def xyz(lo, la):
+        return np.stack([np.cos(la * r) * np.cos(lo * r), np.cos(la * r) * np.sin(lo * r), np.sin(la * r)])
+
+    c = np.linalg.norm(xyz(lon1, lat1) - xyz(lon2, lat2), axis=0)
+    return 2.0 * np.arcsin(np.minimum(c / 2.0, 1.0)) * 6371.0
 
 
 def unique_points_per_step(P, met, torch):
@@ -101,6 +271,8 @@ def main():
     dt = 180.0
     total = W + K
     nt = int(math.ceil(total * dt / inputs.DT_MET)) + 1
+    if args.scenarios or args.surrogate:
+        nt = max(nt, int(math.ceil(480 * dt / inputs.DT_MET)) + 1)
     t0 = time.time()
     log(f"generating fields {args.nx}x{args.ny}x{args.nz}, nt={nt}")
     met = inputs.make_met_c2(seed=12, nt=nt, nx=args.nx, ny=args.ny, nz=args.nz)
@@ -226,6 +398,17 @@ def main():
                                 "cores": nthreads, "kind": "oracle",
                                 "sample": f"ids 0..{m_cpu - 1} of the same workload, steps 0..{steps_cpu - 1} "
                                           f"(all modules, FP64), {tcpu:.1f} s wall"}
+    extras = {}
+    if args.scenarios:
+        log("scenario workload")
+        extras["scenarios"] = run_scenarios(met, mpt, inputs, torch)
+        torch.cuda.empty_cache()
+    if args.surrogate:
+        log("surrogate workload")
+        extras["surrogate"] = run_surrogate(met, mpt, inputs, torch, args)
+        torch.cuda.empty_cache()
+    if extras:
+        line["extras"] = extras
     if args.copy_probe:
         a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
         b = torch.empty_like(a)

@@ -92,7 +92,7 @@ def lib() -> ctypes.CDLL:
         L.mpt_surrogate_grad.argtypes = [P, P, P, ctypes.c_int32, P, P, P, P, P]
         L.mpt_surrogate_load.argtypes = [P, P, P, ctypes.c_float, P]
         L.mpt_surrogate_forward.argtypes = [P, ctypes.c_int64, P, P, P]
-        L.mpt_step_surrogate.argtypes = [P, P, ctypes.c_uint32, ctypes.c_int32, P, P]
+        L.mpt_step_surrogate.argtypes = [P, P, ctypes.c_uint32, ctypes.c_int32, P, P, P]
         L.mpt_destroy.argtypes = [P]
         L.mpt_status_string.argtypes = [S]
         L.mpt_status_string.restype = ctypes.c_char_p
@@ -351,10 +351,12 @@ class Context:
                                                                     y.data_ptr(), _stream_handle(stream)))
         return y
 
-    def step_surrogate(self, P: DeviceParticles, step0: int, nsteps: int, fallbacks, stream=None):
+    def step_surrogate(self, P: DeviceParticles, step0: int, nsteps: int, fallbacks, err=None,
+                       stream=None):
         s = P.cstruct()
-        _check("mpt_step_surrogate", lib().mpt_step_surrogate(self.h, ctypes.byref(s), step0, nsteps,
-                                                              fallbacks.data_ptr(), _stream_handle(stream)))
+        _check("mpt_step_surrogate", lib().mpt_step_surrogate(
+            self.h, ctypes.byref(s), step0, nsteps, fallbacks.data_ptr(),
+            err.data_ptr() if err is not None else None, _stream_handle(stream)))
         P.adopt(s)
 
     def step_graph(self, P: DeviceParticles, step0: int, nsteps: int, stream):

@@ -493,7 +493,7 @@ __global__ void k_surr_adam(float *params, const float *grad, float *m, float *v
 // block's turbulent and mesoscale diffusion with the block-start spread) or
 // kSurrK plain steps.
 __global__ __launch_bounds__(64) void k_surr_step(const StepArgs a, const SurrW W, float tau_km,
-                                                  uint32_t *fallbacks) {
+                                                  uint32_t *fallbacks, float *err_out) {
   __shared__ __attribute__((aligned(16))) uint16_t xs[64 * kXLd];
   __shared__ __attribute__((aligned(16))) uint16_t ha[16 * kHLd], hb[16 * kHLd];
   __shared__ float ys[64][4];
@@ -544,6 +544,7 @@ __global__ __launch_bounds__(64) void k_surr_step(const StepArgs a, const SurrW 
   const float span = (float)(kSurrK * a.dt) * 1e-3f;
   const float ee = de - span * wm[0], en = dn - span * wm[1];
   const float err = sqrtf(ee * ee + en * en);
+  if (err_out) err_out[i] = err;
   const uint32_t id = a.id[i];
   float up = static_cast<const float *>(a.up)[i];
   float vp = static_cast<const float *>(a.vp)[i];
@@ -639,9 +640,9 @@ hipError_t launch_surr_grad(const SurrW &W, const SurrTrain &T, hipStream_t s) {
 }
 
 hipError_t launch_surr_step(const StepArgs &a, const SurrW &W, float tau_km, uint32_t *fallbacks,
-                            hipStream_t s) {
+                            float *err_out, hipStream_t s) {
   hipLaunchKernelGGL(k_surr_step, dim3((unsigned)(a.per_xcd * kXcds)), dim3(64), 0, s, a, W, tau_km,
-                     fallbacks);
+                     fallbacks, err_out);
   return hipGetLastError();
 }
 

@@ -725,10 +725,11 @@ mpt_status mpt_surrogate_forward(mpt_ctx *c, int64_t n, const float *x, float *y
 }
 
 mpt_status mpt_step_surrogate(mpt_ctx *c, mpt_particles *P, uint32_t step0, int32_t nsteps,
-                              uint32_t *fallbacks, void *hip_stream) {
+                              uint32_t *fallbacks, float *err_out, void *hip_stream) {
   if (!c || !fallbacks) return MPT_ERR_ARG;
   if (c->params.math != MPT_MATH_F32 || c->grid.dtype != MPT_DT_F32) return MPT_ERR_UNSUPPORTED;
   if (!P || P->scen) return MPT_ERR_UNSUPPORTED;
+  if (err_out && c->params.sort_interval > 0 && nsteps > 0) return MPT_ERR_ARG;  // fixed order needed
   if (step0 % kSurrK != 0 || nsteps < 0 || nsteps % kSurrK != 0) return MPT_ERR_ARG;
   if (!c->s_loaded) return MPT_ERR_STATE;
   const int S = c->params.sort_interval;
@@ -753,7 +754,7 @@ mpt_status mpt_step_surrogate(mpt_ctx *c, mpt_particles *P, uint32_t step0, int3
     const int64_t nblk = (P->n + 63) / 64;
     a.nblk = (int32_t)nblk;
     a.per_xcd = (int32_t)((nblk + kXcds - 1) / kXcds);
-    if (launch_surr_step(a, W, c->s_tau, fallbacks, s) != hipSuccess) return MPT_ERR_HIP;
+    if (launch_surr_step(a, W, c->s_tau, fallbacks, err_out, s) != hipSuccess) return MPT_ERR_HIP;
   }
   return MPT_OK;
 }
