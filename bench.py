@@ -27,6 +27,17 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
+# Per-unit figures of the step kernel, from rocprofv3 --pmc runs of this
+# workload (profiles/k_step_1e8_0p3deg.md): FP64 FLOP per parcel-step =
+# 64 x SQ_INSTS_VALU_FLOPS_FP64 per launch / parcel-steps per launch (F64 form);
+# FP32 likewise from SQ_INSTS_VALU_FLOPS_FP32 (F32 form).  HBM bytes per
+# 10-step launch of 1e8 parcels = 2 x FETCH_SIZE + WRITE_SIZE (KiB x 1024; a
+# 1 GiB copy reads FETCH_SIZE = 512 MiB and WRITE_SIZE = 1 GiB).
+FP64_FLOP_PER_PS = 1429.0
+FP32_FLOP_PER_PS = 656.0
+TRAFFIC_BYTES_PER_LAUNCH = {"f64": 2 * 3.685e6 * 1024 + 4.688e6 * 1024,
+                            "f32": 2 * 3.088e6 * 1024 + 3.516e6 * 1024}
 METRIC = "particle-steps/s (advect+diffuse, 1e8 particles, 0.3° grid); surrogate vs plain"
 FORMS = {"f64": (0, 0), "f32": (1, 0), "bf16": (1, 1), "f16": (1, 2)}   # (math, dtype)
 
@@ -341,12 +352,18 @@ def main():
     state_b = 100 if math_ == 0 else 76
     rec_b = 12 if dtype == 0 else 6
     field_b = main_r["unique_pts"] * 2 * rec_b / n
-    # dominant kernel: the fused step kernel; algorithmic bytes per launch =
-    # N * (state read+write once per launch + field bytes per step * steps)
-    launch_bytes = [n * (state_b + field_b * k) for k in main_r["step_steps"]]
     durations = main_r["step_ms"]
     avg_ms = float(np.mean(durations))
-    achieved_gbs = float(np.mean([b / (d * 1e-3) / 1e9 for b, d in zip(launch_bytes, durations)]))
+    # the dominant kernel is bound by its vector ALU (FP64 for the F64 form):
+    # algorithmic FLOP per launch = FLOP per parcel-step x parcel-steps
+    flop_ps = FP64_FLOP_PER_PS if math_ == 0 else FP32_FLOP_PER_PS
+    peak = FP64_PEAK_TFLOPS if math_ == 0 else FP32_PEAK_TFLOPS
+    achieved_tf = float(np.mean([flop_ps * n * k / (d * 1e-3) / 1e12
+                                 for k, d in zip(main_r["step_steps"], durations)]))
+    hbm_gbs = float(np.mean([n * (state_b + field_b * k) / (d * 1e-3) / 1e9
+                             for k, d in zip(main_r["step_steps"], durations)]))
+    traffic = TRAFFIC_BYTES_PER_LAUNCH.get(args.form) if (n == 100_000_000 and args.fuse == 10
+                                                          and args.nz == 137) else None
     value = n * K / main_r["elapsed"]
     line = {
         "metric": METRIC,
@@ -366,11 +383,14 @@ def main():
                    "n_particles": n, "grid": f"{args.nx}x{args.ny}x{args.nz}",
                    "form": args.form.upper(), "sort_interval": args.sort_interval,
                    "fuse": args.fuse, "met_levels": nt},
-        "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": None,
+        "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": peak,
+                     "unit": "TFLOP/s", "frac": achieved_tf / peak, "traffic": traffic,
                      "kernel": "k_step", "avg_launch_ms": avg_ms,
-                     "algorithmic_bytes_per_particle_step": state_b / args.fuse + field_b,
-                     "field_bytes_per_particle_step": field_b},
+                     "flop_per_particle_step": flop_ps,
+                     "steps_per_launch": args.fuse,
+                     "hbm_algorithmic_GBps": hbm_gbs,
+                     "hbm_frac": hbm_gbs / HBM_PEAK_GBS,
+                     "algorithmic_bytes_per_particle_step": state_b / args.fuse + field_b},
         "sort_ms_avg": float(np.mean(main_r["sort_ms"])) if main_r["sort_ms"] else None,
         "forms": {f: {"particle_steps_per_s": n * K / r["elapsed"],
                       "step_kernel_ms_avg": float(np.mean(r["step_ms"])),

@@ -78,6 +78,14 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
   for (int q = threadIdx.x; q < kLutBins; q += kBlock) s_lut[q] = a.lut[q];
   __syncthreads();
   const uint32_t step0 = a.step0 + (a.step_dev ? *a.step_dev : 0u);
+  if (a.index) {                         // grid-stride over a list of parcel indices
+    const int64_t cnt = *a.index_count;
+    for (int64_t c = blockIdx.x; c * kBlock < cnt; c += gridDim.x) {
+      const int64_t j = c * kBlock + threadIdx.x;
+      if (j < cnt) step_parcel<F, R>(a, s_plev, s_idp, s_lut, (int64_t)a.index[j], step0);
+    }
+    return;
+  }
   if (!a.persistent) {
     const int lb = logical_block((int)blockIdx.x, a.per_xcd);
     if (lb >= a.nblk) return;

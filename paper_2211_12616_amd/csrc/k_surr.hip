@@ -493,7 +493,8 @@ __global__ void k_surr_adam(float *params, const float *grad, float *m, float *v
 // block's turbulent and mesoscale diffusion with the block-start spread) or
 // kSurrK plain steps.
 __global__ __launch_bounds__(64) void k_surr_step(const StepArgs a, const SurrW W, float tau_km,
-                                                  uint32_t *fallbacks, float *err_out) {
+                                                  uint32_t *fallbacks, float *err_out,
+                                                  uint32_t *fb_list, uint32_t *fb_count) {
   __shared__ __attribute__((aligned(16))) uint16_t xs[64 * kXLd];
   __shared__ __attribute__((aligned(16))) uint16_t ha[16 * kHLd], hb[16 * kHLd];
   __shared__ float ys[64][4];
@@ -551,33 +552,35 @@ __global__ __launch_bounds__(64) void k_surr_step(const StepArgs a, const SurrW 
   float wp = static_cast<const float *>(a.wp)[i];
   const bool meso_on = (a.flags & kMeso) != 0;
   const bool accept = err <= tau_km && isfinite(err);
-  if (accept) {
-    float sg[3] = {0.f, 0.f, 0.f};
-    if (meso_on) meso_sigma<kF32, float>(a, a.plev, a.inv_dp, a.lut, t0 + 0.5 * a.dt, lon, lat, p, sg);
-    lon = lon + (double)(de * 1000.0f * kdeg / c0);
-    lat = lat + (double)(dn * 1000.0f * kdeg);
-    p = p + (double)dpp;
+  // parcels that fall back keep their state here and are queued for the
+  // plain step kernel (a wave-aggregated append to the list)
+  const uint64_t fb = __ballot(!accept);
+  if (fb) {
+    const int leader = __ffsll((long long)fb) - 1;
+    uint32_t base = 0;
+    if (l == leader) {
+      base = atomicAdd(fb_count, (uint32_t)__popcll(fb));
+      atomicAdd(fallbacks, (uint32_t)__popcll(fb));
+    }
+    base = __shfl(base, leader);
+    if (!accept) fb_list[base + __popcll(fb & ((1ull << l) - 1ull))] = (uint32_t)i;
+  }
+  if (!accept) return;
+  float sg[3] = {0.f, 0.f, 0.f};
+  if (meso_on) meso_sigma<kF32, float>(a, a.plev, a.inv_dp, a.lut, t0 + 0.5 * a.dt, lon, lat, p, sg);
+  lon = lon + (double)(de * 1000.0f * kdeg / c0);
+  lat = lat + (double)(dn * 1000.0f * kdeg);
+  p = p + (double)dpp;
+  position(a, lon, lat, p);
+  for (int s = 0; s < kSurrK; ++s) {
+    const uint32_t step = a.step0 + (uint32_t)s;
+    if (a.flags & kTurb) turb<float>(a, id, step, lon, lat, p);
+    if (meso_on) {
+      float xi[3];
+      normals3<float>(a.seed, id, step, 1u, xi);
+      meso_apply<float>(a, sg, xi, lon, lat, p, up, vp, wp);
+    }
     position(a, lon, lat, p);
-    for (int s = 0; s < kSurrK; ++s) {
-      const uint32_t step = a.step0 + (uint32_t)s;
-      if (a.flags & kTurb) turb<float>(a, id, step, lon, lat, p);
-      if (meso_on) {
-        float xi[3];
-        normals3<float>(a.seed, id, step, 1u, xi);
-        meso_apply<float>(a, sg, xi, lon, lat, p, up, vp, wp);
-      }
-      position(a, lon, lat, p);
-    }
-  } else {
-    for (int s = 0; s < kSurrK; ++s) {
-      const uint32_t step = a.step0 + (uint32_t)s;
-      const double t = a.t_start + (double)step * a.dt;
-      advect<kF32, float>(a, a.plev, a.inv_dp, a.lut, t, lon, lat, p);
-      position(a, lon, lat, p);
-      if (a.flags & kTurb) turb<float>(a, id, step, lon, lat, p);
-      if (meso_on) meso<kF32, float>(a, a.plev, a.inv_dp, a.lut, id, step, t + 0.5 * a.dt, lon, lat, p, up, vp, wp);
-      position(a, lon, lat, p);
-    }
   }
   a.lon[i] = lon;
   a.lat[i] = lat;
@@ -585,8 +588,6 @@ __global__ __launch_bounds__(64) void k_surr_step(const StepArgs a, const SurrW 
   static_cast<float *>(a.up)[i] = up;
   static_cast<float *>(a.vp)[i] = vp;
   static_cast<float *>(a.wp)[i] = wp;
-  const uint64_t fb = __ballot(!accept);
-  if (l == __ffsll((long long)__ballot(1)) - 1 && fb) atomicAdd(fallbacks, (uint32_t)__popcll(fb));
 }
 
 // ---- launchers ------------------------------------------------------------------------
@@ -640,9 +641,9 @@ hipError_t launch_surr_grad(const SurrW &W, const SurrTrain &T, hipStream_t s) {
 }
 
 hipError_t launch_surr_step(const StepArgs &a, const SurrW &W, float tau_km, uint32_t *fallbacks,
-                            float *err_out, hipStream_t s) {
+                            float *err_out, uint32_t *fb_list, uint32_t *fb_count, hipStream_t s) {
   hipLaunchKernelGGL(k_surr_step, dim3((unsigned)(a.per_xcd * kXcds)), dim3(64), 0, s, a, W, tau_km,
-                     fallbacks, err_out);
+                     fallbacks, err_out, fb_list, fb_count);
   return hipGetLastError();
 }
 

@@ -66,6 +66,9 @@ struct StepArgs {
   uint32_t ntiles;
   const uint32_t *offsets;     // exclusive scan of the last sort's histogram
   const int32_t *rel_sorted;   // release steps in ascending order [nscen]
+  // Index-list mode: advance only parcels index[0 .. *index_count).
+  const uint32_t *index;
+  const uint32_t *index_count;
 };
 
 // Map the hardware block index to a logical block so that each XCD walks a

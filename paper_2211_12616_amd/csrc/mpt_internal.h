@@ -103,7 +103,7 @@ hipError_t launch_surr_train(const SurrW &W, const SurrTrain &T, float *params, 
                              float lr, float bc1, float bc2, hipStream_t s);
 hipError_t launch_surr_grad(const SurrW &W, const SurrTrain &T, hipStream_t s);
 hipError_t launch_surr_step(const StepArgs &a, const SurrW &W, float tau_km, uint32_t *fallbacks,
-                            float *err_out, hipStream_t s);
+                            float *err_out, uint32_t *fb_list, uint32_t *fb_count, hipStream_t s);
 
 // Single-word device helpers (k_step.hip).
 hipError_t launch_set_u32(uint32_t *p, uint32_t v, hipStream_t stream);

@@ -29,6 +29,7 @@ struct mpt_ctx {
   int32_t *rank;          // [kMaxScen] rank of the scenario in release order
   int32_t *rel_sorted;    // [kMaxScen] release steps in ascending order
   uint32_t *step_dev;     // step index read by graph-replayed kernels
+  uint32_t *fb_count;     // surrogate fallback list length
   uint32_t *keys, *ranks, *hist, *block_sums;
   uint32_t ntx, nty, ntz, ntiles, nkeys;
   // host state
@@ -118,7 +119,7 @@ Layout layout(const mpt_grid *g, int64_t n_max) {
   L.release = off;    off += align_up(sizeof(int32_t) * kMaxScen);
   L.rank = off;       off += align_up(sizeof(int32_t) * kMaxScen);
   L.rel_sorted = off; off += align_up(sizeof(int32_t) * kMaxScen);
-  L.step_dev = off;   off += align_up(sizeof(uint32_t));
+  L.step_dev = off;   off += align_up(sizeof(uint32_t) * 2);
   L.keys = off;       off += align_up(sizeof(uint32_t) * (size_t)(n_max > 0 ? n_max : 0));
   L.ranks = off;      off += align_up(sizeof(uint32_t) * (size_t)(n_max > 0 ? n_max : 0));
   L.hist = off;       off += align_up(sizeof(uint32_t) * L.nkeys);
@@ -187,6 +188,8 @@ void fill_step_args(const mpt_ctx *c, const mpt_particles *P, uint32_t step0, in
   a.ntiles = c->ntiles;
   a.offsets = c->hist;
   a.rel_sorted = c->rel_sorted;
+  a.index = nullptr;
+  a.index_count = nullptr;
 }
 
 mpt_status check_particles(const mpt_ctx *c, const mpt_particles *P, bool need_pingpong) {
@@ -404,6 +407,7 @@ mpt_status mpt_create(const mpt_grid *grid, const mpt_params *params, int64_t n_
   c->rank = reinterpret_cast<int32_t *>(ws + L.rank);
   c->rel_sorted = reinterpret_cast<int32_t *>(ws + L.rel_sorted);
   c->step_dev = reinterpret_cast<uint32_t *>(ws + L.step_dev);
+  c->fb_count = c->step_dev + 1;
   c->keys = reinterpret_cast<uint32_t *>(ws + L.keys);
   c->ranks = reinterpret_cast<uint32_t *>(ws + L.ranks);
   c->hist = reinterpret_cast<uint32_t *>(ws + L.hist);
@@ -740,6 +744,7 @@ mpt_status mpt_step_surrogate(mpt_ctx *c, mpt_particles *P, uint32_t step0, int3
   if (st != MPT_OK) return st;
   if (P->n == 0 || nsteps == 0) return MPT_OK;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if (P->n > c->n_max) return MPT_ERR_WORKSPACE;      // the fallback list lives in the key buffer
   const SurrW W = loaded_weights(c);
   for (int64_t b0 = step0; b0 < (int64_t)step0 + nsteps; b0 += kSurrK) {
     bool due = false;
@@ -754,7 +759,17 @@ mpt_status mpt_step_surrogate(mpt_ctx *c, mpt_particles *P, uint32_t step0, int3
     const int64_t nblk = (P->n + 63) / 64;
     a.nblk = (int32_t)nblk;
     a.per_xcd = (int32_t)((nblk + kXcds - 1) / kXcds);
-    if (launch_surr_step(a, W, c->s_tau, fallbacks, err_out, s) != hipSuccess) return MPT_ERR_HIP;
+    if (launch_set_u32(c->fb_count, 0u, s) != hipSuccess ||
+        launch_surr_step(a, W, c->s_tau, fallbacks, err_out, c->keys, c->fb_count, s) != hipSuccess)
+      return MPT_ERR_HIP;
+    // parcels that fell back: kSurrK plain steps, walking the list
+    StepArgs f;
+    fill_step_args(c, P, (uint32_t)b0, kSurrK, c->params.flags, f);
+    f.index = c->keys;
+    f.index_count = c->fb_count;
+    f.nblk = kPersistentBlocks;
+    f.persistent = 1;
+    if (launch_step(c->grid.dtype, 0, f, s) != hipSuccess) return MPT_ERR_HIP;
   }
   return MPT_OK;
 }
