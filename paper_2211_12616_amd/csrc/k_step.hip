@@ -66,8 +66,17 @@ __device__ __forceinline__ int64_t active_bound(const StepArgs &a, uint32_t last
   return b < a.n ? b : a.n;
 }
 
+// Minimum waves per SIMD the compiler must allow (register budget) for the
+// FP64 and FP32 step kernels.
+#ifndef MPT_WAVES_F64
+#define MPT_WAVES_F64 3
+#endif
+#ifndef MPT_WAVES_F32
+#define MPT_WAVES_F32 4
+#endif
+
 template <int F, typename R>
-__global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
+__device__ __forceinline__ void step_body(const StepArgs &a) {
   __shared__ double s_plev[kMaxLevels];
   __shared__ double s_idp[kMaxLevels];
   __shared__ uint16_t s_lut[kLutBins];
@@ -106,17 +115,28 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
   }
 }
 
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MPT_WAVES_F64)))
+void k_step_f64(const StepArgs a) {
+  step_body<kF32, double>(a);
+}
+
+template <int F>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MPT_WAVES_F32)))
+void k_step_f32(const StepArgs a) {
+  step_body<F, float>(a);
+}
+
 hipError_t launch_step(int field, int math_f64, const StepArgs &args, hipStream_t stream) {
   const dim3 grid((unsigned)(args.persistent ? args.nblk : args.per_xcd * kXcds)), block(kBlock);
   if (math_f64) {
     if (field != kF32) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_step<kF32, double>), grid, block, 0, stream, args);
+    hipLaunchKernelGGL(k_step_f64, grid, block, 0, stream, args);
   } else if (field == kF32) {
-    hipLaunchKernelGGL((k_step<kF32, float>), grid, block, 0, stream, args);
+    hipLaunchKernelGGL((k_step_f32<kF32>), grid, block, 0, stream, args);
   } else if (field == kBF16) {
-    hipLaunchKernelGGL((k_step<kBF16, float>), grid, block, 0, stream, args);
+    hipLaunchKernelGGL((k_step_f32<kBF16>), grid, block, 0, stream, args);
   } else {
-    hipLaunchKernelGGL((k_step<kF16, float>), grid, block, 0, stream, args);
+    hipLaunchKernelGGL((k_step_f32<kF16>), grid, block, 0, stream, args);
   }
   return hipGetLastError();
 }

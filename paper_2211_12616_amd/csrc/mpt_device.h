@@ -359,9 +359,26 @@ __device__ __forceinline__ void sigma_cell(const StepArgs &a, const Cell16<F> &c
   }
 }
 
+// cos(lat) floored at cos(89.999 deg).  FP64: cos of the angle.  FP32: the
+// value must keep its relative accuracy near the poles, where 1/cos(lat)
+// scales the longitude increments and a cosine of an FP32 angle has an
+// absolute error: within 0.5 rad of a pole it is the sine of the
+// co-latitude (formed in FP64) by its Taylor series to x^7 (relative error
+// below 1e-9), elsewhere (cos >= 0.48) the hardware cosine.
 template <typename R>
 __device__ __forceinline__ R cos_floor(const StepArgs &a, double lat) {
-  const R c = Math<R>::cos_((R)(lat * (kPi / 180.0)));
+  R c;
+  if constexpr (sizeof(R) == 8) {
+    c = Math<R>::cos_((R)(lat * (kPi / 180.0)));
+  } else {
+    const float x = (float)((90.0 - fabs(lat)) * (kPi / 180.0));
+    if (x < 0.5f) {
+      const float x2 = x * x;
+      c = (R)(x * (1.0f - x2 * (1.0f / 6.0f) * (1.0f - x2 * (1.0f / 20.0f) * (1.0f - x2 * (1.0f / 42.0f)))));
+    } else {
+      c = (R)__cosf((float)(lat * (kPi / 180.0)));
+    }
+  }
   return c > (R)a.cos_cap ? c : (R)a.cos_cap;
 }
 

@@ -128,3 +128,35 @@ def test_null_context_calls():
     assert L.mpt_destroy(None) == -1
     assert L.mpt_met_level_bytes(None) == 0
     assert L.mpt_status_string(-3) == b"step outside the resident met time levels"
+
+
+def test_null_context_newer_entry_points():
+    L = mpt.lib()
+    s = mpt.ParticlesC(n=0)
+    assert L.mpt_step_graph(None, ctypes.byref(s), 0, 20, None) == -1
+    assert L.mpt_surrogate_datagen(None, 1, None, None, None, None, None, None, None) == -1
+    assert L.mpt_surrogate_stats(None, 1, None, None, None, None) == -1
+    assert L.mpt_surrogate_init(None, None, 0, None) == -1
+    assert L.mpt_surrogate_train_step(None, None, None, 64, None, None, None, None, 1, 1e-3, None,
+                                      None) == -1
+    assert L.mpt_surrogate_grad(None, None, None, 64, None, None, None, None, None) == -1
+    assert L.mpt_surrogate_load(None, None, None, 1.0, None) == -1
+    assert L.mpt_surrogate_forward(None, 1, None, None, None) == -1
+    assert L.mpt_step_surrogate(None, ctypes.byref(s), 0, 8, None, None, None) == -1
+
+
+def test_surrogate_constants_match_header():
+    txt = open(os.path.join(ROOT, "include", "mpt.h")).read()
+    for name, val in (("MPT_SURR_K", mpt.SURR_K), ("MPT_SURR_NIN", mpt.SURR_NIN),
+                      ("MPT_SURR_NOUT", mpt.SURR_NOUT), ("MPT_SURR_NPARAM", mpt.SURR_NPARAM),
+                      ("MPT_SURR_MAX_BATCH", mpt.SURR_MAX_BATCH)):
+        m = re.search(name + r"\s*=\s*(\d+)", txt)
+        assert m and int(m.group(1)) == val, name
+    # the flat parameter layout: per layer W[in][out] + bias with padded shapes
+    from oracle import mlp
+    assert sum(fi * fo + fo for fi, fo in mlp.SHAPES) == mpt.SURR_NPARAM
+
+
+def test_workspace_includes_surrogate_scratch():
+    g, plev, p = grid_params(dtype=mpt.DT_F32, math=mpt.MATH_F32)
+    assert ws_bytes(g, p, 0) > 16 * 1024 * 1024
