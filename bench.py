@@ -35,9 +35,9 @@ FP32_PEAK_TFLOPS = 157.3
 # 10-step launch of 1e8 parcels = 2 x FETCH_SIZE + WRITE_SIZE (KiB x 1024; a
 # 1 GiB copy reads FETCH_SIZE = 512 MiB and WRITE_SIZE = 1 GiB).
 FP64_FLOP_PER_PS = 1429.0
-FP32_FLOP_PER_PS = 656.0
-TRAFFIC_BYTES_PER_LAUNCH = {"f64": 2 * 3.685e6 * 1024 + 4.688e6 * 1024,
-                            "f32": 2 * 3.088e6 * 1024 + 3.516e6 * 1024}
+FP32_FLOP_PER_PS = 669.0
+TRAFFIC_BYTES_PER_LAUNCH = {"f64": 2 * 3.689e6 * 1024 + 4.949e6 * 1024,
+                            "f32": 2 * 3.087e6 * 1024 + 3.516e6 * 1024}
 METRIC = "particle-steps/s (advect+diffuse, 1e8 particles, 0.3° grid); surrogate vs plain"
 FORMS = {"f64": (0, 0), "f32": (1, 0), "bf16": (1, 1), "f16": (1, 2)}   # (math, dtype)
 

@@ -2,9 +2,12 @@
 // turbulent and mesoscale diffusion, position) for one or more steps per
 // launch, one parcel per thread, state held in registers across steps.
 //
-// Two launch shapes: one block per 256 parcels (XCD-aware order), or a
-// persistent grid that walks 256-parcel chunks of the active prefix of a
-// scenario run, whose length it reads from device memory.
+// Three launch shapes, each compiled as its own kernel so that each gets its
+// own register allocation (sharing one body spills the launch arguments to
+// VGPR lanes): one block per 256 parcels (XCD-aware order); a persistent grid
+// that walks 256-parcel chunks of the active prefix of a scenario run, whose
+// length it reads from device memory; a grid-stride walk over a device list
+// of parcel indices, whose length it reads from device memory.
 #include "mpt_device.h"
 #include "mpt_internal.h"
 
@@ -75,7 +78,9 @@ __device__ __forceinline__ int64_t active_bound(const StepArgs &a, uint32_t last
 #define MPT_WAVES_F32 4
 #endif
 
-template <int F, typename R>
+enum : int { kModeBlock = 0, kModePersistent = 1, kModeIndex = 2 };
+
+template <int M, int F, typename R>
 __device__ __forceinline__ void step_body(const StepArgs &a) {
   __shared__ double s_plev[kMaxLevels];
   __shared__ double s_idp[kMaxLevels];
@@ -87,58 +92,66 @@ __device__ __forceinline__ void step_body(const StepArgs &a) {
   for (int q = threadIdx.x; q < kLutBins; q += kBlock) s_lut[q] = a.lut[q];
   __syncthreads();
   const uint32_t step0 = a.step0 + (a.step_dev ? *a.step_dev : 0u);
-  if (a.index) {                         // grid-stride over a list of parcel indices
+  if constexpr (M == kModeIndex) {       // grid-stride over a list of parcel indices
     const int64_t cnt = *a.index_count;
     for (int64_t c = blockIdx.x; c * kBlock < cnt; c += gridDim.x) {
       const int64_t j = c * kBlock + threadIdx.x;
       if (j < cnt) step_parcel<F, R>(a, s_plev, s_idp, s_lut, (int64_t)a.index[j], step0);
     }
-    return;
-  }
-  if (!a.persistent) {
+  } else if constexpr (M == kModeBlock) {
     const int lb = logical_block((int)blockIdx.x, a.per_xcd);
     if (lb >= a.nblk) return;
     const int64_t i = (int64_t)lb * kBlock + threadIdx.x;
     if (i < a.n) step_parcel<F, R>(a, s_plev, s_idp, s_lut, i, step0);
-    return;
-  }
-  // persistent: XCD x owns an even share of the chunks of the prefix and its
-  // blocks stride through that share
-  const int64_t bound = active_bound(a, step0 + (uint32_t)(a.nsteps - 1));
-  const int64_t nchunks = (bound + kBlock - 1) / kBlock;
-  const int xcd = (int)blockIdx.x % kXcds;
-  const int q = (int)blockIdx.x / kXcds, nq = (int)gridDim.x / kXcds;
-  const int64_t c_lo = nchunks * xcd / kXcds, c_hi = nchunks * (xcd + 1) / kXcds;
-  for (int64_t c = c_lo + q; c < c_hi; c += nq) {
-    const int64_t i = c * kBlock + threadIdx.x;
-    if (i < bound) step_parcel<F, R>(a, s_plev, s_idp, s_lut, i, step0);
+  } else {
+    // persistent: XCD x owns an even share of the chunks of the prefix and
+    // its blocks stride through that share
+    const int64_t bound = active_bound(a, step0 + (uint32_t)(a.nsteps - 1));
+    const int64_t nchunks = (bound + kBlock - 1) / kBlock;
+    const int xcd = (int)blockIdx.x % kXcds;
+    const int q = (int)blockIdx.x / kXcds, nq = (int)gridDim.x / kXcds;
+    const int64_t c_lo = nchunks * xcd / kXcds, c_hi = nchunks * (xcd + 1) / kXcds;
+    for (int64_t c = c_lo + q; c < c_hi; c += nq) {
+      const int64_t i = c * kBlock + threadIdx.x;
+      if (i < bound) step_parcel<F, R>(a, s_plev, s_idp, s_lut, i, step0);
+    }
   }
 }
 
+template <int M>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MPT_WAVES_F64)))
 void k_step_f64(const StepArgs a) {
-  step_body<kF32, double>(a);
+  step_body<M, kF32, double>(a);
 }
 
-template <int F>
+template <int M, int F>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MPT_WAVES_F32)))
 void k_step_f32(const StepArgs a) {
-  step_body<F, float>(a);
+  step_body<M, F, float>(a);
+}
+
+template <int M>
+static hipError_t launch_mode(int field, int math_f64, const StepArgs &args, dim3 grid,
+                              hipStream_t stream) {
+  const dim3 block(kBlock);
+  if (math_f64) {
+    if (field != kF32) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_step_f64<M>, grid, block, 0, stream, args);
+  } else if (field == kF32) {
+    hipLaunchKernelGGL((k_step_f32<M, kF32>), grid, block, 0, stream, args);
+  } else if (field == kBF16) {
+    hipLaunchKernelGGL((k_step_f32<M, kBF16>), grid, block, 0, stream, args);
+  } else {
+    hipLaunchKernelGGL((k_step_f32<M, kF16>), grid, block, 0, stream, args);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_step(int field, int math_f64, const StepArgs &args, hipStream_t stream) {
-  const dim3 grid((unsigned)(args.persistent ? args.nblk : args.per_xcd * kXcds)), block(kBlock);
-  if (math_f64) {
-    if (field != kF32) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_step_f64, grid, block, 0, stream, args);
-  } else if (field == kF32) {
-    hipLaunchKernelGGL((k_step_f32<kF32>), grid, block, 0, stream, args);
-  } else if (field == kBF16) {
-    hipLaunchKernelGGL((k_step_f32<kBF16>), grid, block, 0, stream, args);
-  } else {
-    hipLaunchKernelGGL((k_step_f32<kF16>), grid, block, 0, stream, args);
-  }
-  return hipGetLastError();
+  const dim3 grid((unsigned)(args.persistent ? args.nblk : args.per_xcd * kXcds));
+  if (args.index) return launch_mode<kModeIndex>(field, math_f64, args, grid, stream);
+  if (args.persistent) return launch_mode<kModePersistent>(field, math_f64, args, grid, stream);
+  return launch_mode<kModeBlock>(field, math_f64, args, grid, stream);
 }
 
 __global__ void k_add_u32(uint32_t *p, uint32_t v) { *p += v; }

@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "mpt_math.h"
+
 namespace mpt {
 
 // ---- constants of the method ------------------------------------------------
@@ -105,13 +107,18 @@ template <> struct Math<double> {
   static __device__ __forceinline__ double uni(uint32_t x) {
     return ((double)(x >> 8) + 0.5) * (1.0 / 16777216.0);
   }
-  static __device__ __forceinline__ double log_(double x) { return log(x); }
+  // ln of a uniform in (0, 1): always a positive normal number
+  static __device__ __forceinline__ double log_(double x) { return m64::ln_pos(x); }
   static __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
-  static __device__ __forceinline__ double cos_(double x) { return cos(x); }
-  static __device__ __forceinline__ void sincos_(double x, double *s, double *c) { sincos(x, s, c); }
-  // sin(pi x), cos(pi x): no reduction by pi needed
-  static __device__ __forceinline__ void sincospi_(double x, double *s, double *c) { sincospi(x, s, c); }
-  static __device__ __forceinline__ double cospi_(double x) { return cospi(x); }
+  // sin(pi x), cos(pi x) for x in [0, 2] (twice a uniform)
+  static __device__ __forceinline__ void sincospi_(double x, double *s, double *c) {
+    m64::sincospi_02(x, s, c);
+  }
+  static __device__ __forceinline__ double cospi_(double x) {
+    double s, c;
+    m64::sincospi_02(x, &s, &c);
+    return c;
+  }
   // 1/x for x in [cos 89.999 deg, 1]: hardware estimate + two Newton steps
   // (error squared per step, final error at the rounding level)
   static __device__ __forceinline__ double rcp(double x) {
@@ -129,8 +136,6 @@ template <> struct Math<float> {
   }
   static __device__ __forceinline__ float log_(float x) { return __logf(x); }
   static __device__ __forceinline__ float sqrt_(float x) { return __fsqrt_rn(x); }
-  static __device__ __forceinline__ float cos_(float x) { return __cosf(x); }
-  static __device__ __forceinline__ void sincos_(float x, float *s, float *c) { __sincosf(x, s, c); }
   static __device__ __forceinline__ void sincospi_(float x, float *s, float *c) {
     __sincosf(x * (float)kPi, s, c);
   }
@@ -359,17 +364,17 @@ __device__ __forceinline__ void sigma_cell(const StepArgs &a, const Cell16<F> &c
   }
 }
 
-// cos(lat) floored at cos(89.999 deg).  FP64: cos of the angle.  FP32: the
-// value must keep its relative accuracy near the poles, where 1/cos(lat)
-// scales the longitude increments and a cosine of an FP32 angle has an
-// absolute error: within 0.5 rad of a pole it is the sine of the
-// co-latitude (formed in FP64) by its Taylor series to x^7 (relative error
-// below 1e-9), elsewhere (cos >= 0.48) the hardware cosine.
+// cos(lat) floored at cos(89.999 deg).  The value must keep its relative
+// accuracy near the poles, where 1/cos(lat) scales the longitude increments
+// and a cosine of a rounded angle has an absolute error.  FP64: the sine of
+// the co-latitude by its series to x^21.  FP32: within 0.5 rad of a pole the
+// sine of the co-latitude (formed in FP64) by its series to x^7 (relative
+// error below 1e-9), elsewhere (cos >= 0.48) the hardware cosine.
 template <typename R>
 __device__ __forceinline__ R cos_floor(const StepArgs &a, double lat) {
   R c;
   if constexpr (sizeof(R) == 8) {
-    c = Math<R>::cos_((R)(lat * (kPi / 180.0)));
+    c = m64::cos_lat_deg(lat);
   } else {
     const float x = (float)((90.0 - fabs(lat)) * (kPi / 180.0));
     if (x < 0.5f) {
