@@ -263,12 +263,23 @@ struct Cell16 {
   typename Rec<F>::T r[2][2][2][2];   // [dl][dk][dj][di]
 };
 
+// Two consecutive 8-byte records read by one 16-byte load.
+struct __attribute__((aligned(8))) RecPair8 {
+  ushort4 a, b;
+};
+
+// 16-byte records: one load per corner.  8-byte records: the two corners of
+// a row are consecutive in memory except across the periodic seam, so one
+// 16-byte load fetches both (half the gather instructions); a parcel on the
+// seam (i0 = nx - 1, i1 = 0) loads the pair ending at i0 and record 0.
 template <int F, typename R>
 __device__ __forceinline__ void load_cell(const StepArgs &a, const Loc<R> &L, Cell16<F> &c) {
   using T = typename Rec<F>::T;
   const T *base = reinterpret_cast<const T *>(a.met);
   const int nxy = a.nx * a.ny;
   const int r0 = L.k * nxy + L.j * a.nx;
+  const bool seam = L.i1 < L.i0;
+  const int ip = seam ? L.i0 - 1 : L.i0;
 #pragma unroll
   for (int dl = 0; dl < 2; ++dl) {
     const T *lev = base + (int64_t)(L.l + dl) * a.level_elems;
@@ -277,8 +288,18 @@ __device__ __forceinline__ void load_cell(const StepArgs &a, const Loc<R> &L, Ce
 #pragma unroll
       for (int dj = 0; dj < 2; ++dj) {
         const T *row = lev + r0 + dk * nxy + dj * a.nx;
-        c.r[dl][dk][dj][0] = row[L.i0];
-        c.r[dl][dk][dj][1] = row[L.i1];
+        if constexpr (F == kF32) {
+          c.r[dl][dk][dj][0] = row[L.i0];
+          c.r[dl][dk][dj][1] = row[L.i1];
+        } else {
+          const RecPair8 q = *reinterpret_cast<const RecPair8 *>(row + ip);
+          c.r[dl][dk][dj][0] = q.a;
+          c.r[dl][dk][dj][1] = q.b;
+          if (seam) {
+            c.r[dl][dk][dj][0] = q.b;
+            c.r[dl][dk][dj][1] = row[0];
+          }
+        }
       }
   }
 }
