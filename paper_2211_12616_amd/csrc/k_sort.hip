@@ -160,6 +160,14 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(const ScatterArgs a) {
 
 size_t scan_block_sums_len(uint32_t nkeys) { return (nkeys + kScanChunk - 1) / kScanChunk; }
 
+hipError_t launch_scan_u32(uint32_t *data, uint32_t n, uint32_t *block_sums, hipStream_t stream) {
+  const uint32_t nb = (uint32_t)scan_block_sums_len(n);
+  hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(256), 0, stream, data, n, block_sums);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(256), 0, stream, block_sums, nb);
+  hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(256), 0, stream, data, n, block_sums);
+  return hipGetLastError();
+}
+
 hipError_t launch_sort(const SortArgs &sa, const ScatterArgs &xa, hipStream_t stream) {
   const uint32_t nb = (uint32_t)scan_block_sums_len(sa.nkeys);
   unsigned fill_grid = (sa.nkeys + 255) / 256;

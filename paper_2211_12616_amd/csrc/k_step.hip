@@ -6,8 +6,9 @@
 // own register allocation (sharing one body spills the launch arguments to
 // VGPR lanes): one block per 256 parcels (XCD-aware order); a persistent grid
 // that walks 256-parcel chunks of the active prefix of a scenario run, whose
-// length it reads from device memory; a grid-stride walk over a device list
-// of parcel indices, whose length it reads from device memory.
+// length it reads from device memory; the same walk over a device list of
+// parcel indices in increasing order, whose length it reads from device
+// memory.
 #include "mpt_device.h"
 #include "mpt_internal.h"
 
@@ -92,9 +93,16 @@ __device__ __forceinline__ void step_body(const StepArgs &a) {
   for (int q = threadIdx.x; q < kLutBins; q += kBlock) s_lut[q] = a.lut[q];
   __syncthreads();
   const uint32_t step0 = a.step0 + (a.step_dev ? *a.step_dev : 0u);
-  if constexpr (M == kModeIndex) {       // grid-stride over a list of parcel indices
+  if constexpr (M == kModeIndex) {
+    // a list of parcel indices in increasing order: XCD x owns an even share
+    // of its 256-entry chunks (a region of the sorted parcels) and its
+    // blocks stride through that share
     const int64_t cnt = *a.index_count;
-    for (int64_t c = blockIdx.x; c * kBlock < cnt; c += gridDim.x) {
+    const int64_t nchunks = (cnt + kBlock - 1) / kBlock;
+    const int xcd = (int)blockIdx.x % kXcds;
+    const int q = (int)blockIdx.x / kXcds, nq = (int)gridDim.x / kXcds;
+    const int64_t c_lo = nchunks * xcd / kXcds, c_hi = nchunks * (xcd + 1) / kXcds;
+    for (int64_t c = c_lo + q; c < c_hi; c += nq) {
       const int64_t j = c * kBlock + threadIdx.x;
       if (j < cnt) step_parcel<F, R>(a, s_plev, s_idp, s_lut, (int64_t)a.index[j], step0);
     }

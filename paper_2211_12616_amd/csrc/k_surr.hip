@@ -7,10 +7,10 @@
 // and the step kernel falls back to 8 plain steps wherever a one-step
 // midpoint consistency estimate of the prediction's error exceeds tau.
 //
-// Wave-level MLP: a wave runs 16-row tiles through the network; the A
-// operand (activations) comes from LDS, the B operand (weights, [out][in]
-// bf16, 16-byte fragments) from global memory, where the 94 KB of weights
-// stay cache resident.
+// Inference (k_surr_mlp) is a persistent kernel, one block per CU, that
+// stages the 94 KB of bf16 weights in LDS once and keeps the activations in
+// registers (transposed products, below).  Training runs 16-row tiles with
+// the activations in LDS and the weights read from global memory.
 #include "mpt_device.h"
 #include "mpt_internal.h"
 
@@ -102,8 +102,9 @@ __device__ __forceinline__ f32x4 mlp16(const uint16_t *xs, int ldx, const SurrW 
 // {-1, 0, 1} (lon, lat, level): quadrilinear interpolation of the shifted
 // cell with the parcel's own weights, columns periodic, rows / levels
 // clamped to valid cells.  Evaluated over the 4 x 4 x 4 points x 2 time
-// levels around the cell; sink(idx, value), idx = var*27 + (c+1)*9 +
-// (b+1)*3 + (a+1).
+// levels around the cell.  The values of one level shift c come out
+// together, in ascending c: sink(c + 1, g) with g[(b+1)*9 + (a+1)*3 + var];
+// the input index of a value is var*27 + (c+1)*9 + (b+1)*3 + (a+1).
 template <class Sink>
 __device__ __forceinline__ void stencil81(const StepArgs &a, const Loc<float> &L, Sink sink) {
   const float4 *base = reinterpret_cast<const float4 *>(a.met);
@@ -159,14 +160,16 @@ __device__ __forceinline__ void stencil81(const StepArgs &a, const Loc<float> &L
     if (qk > 0) {
 #pragma unroll
       for (int sc = 0; sc < 3; ++sc)
-        if (pc[sc] + 1 == qk)
+        if (pc[sc] + 1 == qk) {
+          float g[27];
 #pragma unroll
           for (int sb = 0; sb < 3; ++sb)
 #pragma unroll
             for (int s = 0; s < 3; ++s)
 #pragma unroll
-              for (int q = 0; q < 3; ++q)
-                sink(q * 27 + sc * 9 + sb * 3 + s, lerp(zprev[sb][s][q], zcur[sb][s][q], L.fz));
+              for (int q = 0; q < 3; ++q) g[sb * 9 + s * 3 + q] = lerp(zprev[sb][s][q], zcur[sb][s][q], L.fz);
+          sink(sc, g);
+        }
     }
 #pragma unroll
     for (int sb = 0; sb < 3; ++sb)
@@ -194,7 +197,10 @@ __global__ __launch_bounds__(256) void k_surr_datagen(const StepArgs a, int64_t 
   Loc<float> L;
   surr_locate(a, lo, la, pp, t0, L);
   float *xr = x + i * kSurrIn;
-  stencil81(a, L, [&](int idx, float v) { xr[idx] = v; });
+  stencil81(a, L, [&](int sc, const float (&g)[27]) {
+#pragma unroll
+    for (int j = 0; j < 27; ++j) xr[(j % 3) * 27 + sc * 9 + j / 3] = g[j];
+  });
   double X = lo, Y = la, Z = pp;
   for (int q = 0; q < kSurrK; ++q) {
     advect<kF32, double>(a, a.plev, a.inv_dp, a.lut, t0 + (double)q * a.dt, X, Y, Z);
@@ -312,32 +318,186 @@ __global__ void k_surr_pack(const float *params, uint16_t *wt, uint16_t *wb) {
   }
 }
 
-// ---- inference on given inputs (tests, calibration) ------------------------------
-// One wave per 64 rows: raw inputs -> normalized bf16 tile -> MLP -> outputs
-// de-normalized to (east km, north km, dp hPa).
-__global__ __launch_bounds__(64) void k_surr_forward(const SurrW W, const float *x, int64_t n,
-                                                     float *y) {
-  __shared__ __attribute__((aligned(16))) uint16_t xs[64 * kXLd];
-  __shared__ __attribute__((aligned(16))) uint16_t ha[16 * kHLd], hb[16 * kHLd];
-  __shared__ float ys[64][4];
-  const int l = threadIdx.x;
-  const int64_t r0 = (int64_t)blockIdx.x * 64, i = r0 + l;
-  for (int c = 0; c < kXLd; ++c) {
-    float v = 0.0f;
-    if (i < n && c < kSurrIn) v = (x[i * kSurrIn + c] - W.norm[c / 27]) / W.norm[3 + c / 27];
-    xs[l * kXLd + c] = f2bf(v);
-  }
-  __syncthreads();
-  for (int t = 0; t < 4; ++t) {
-    const f32x4 o = mlp16(xs + t * 16 * kXLd, kXLd, W, ha, hb, nullptr, nullptr, nullptr, 0, 0);
-    const int row = l & 15, kq = l >> 4;
-    if (row < kSurrOut)
+// ---- inference: persistent MLP with the weights in LDS --------------------------------
+// Each layer computes H^T = W^T X^T: the weights are the A operand (rows =
+// output units) and 16 parcels are the columns of B, so the accumulator
+// tiles of one layer (lane l: units 4*(l/16)+i of parcel l%16) are already
+// the B fragments of the next once the K order of the next layer's weights
+// is permuted to match: slot (kt, g, j) of a 32-wide K tile holds unit
+// 32 kt + 4 g + j for j < 4 and 32 kt + 16 + 4 g + j - 4 for j >= 4.
+// Activations never leave registers; every weight fragment read from LDS
+// serves the 4 parcel tiles of a wave.
+constexpr int kMlpThreads = 256;
+constexpr int kMlpBlocks = 256;                               // one per CU
+
+typedef __attribute__((__vector_size__(8 * sizeof(float)))) float f32x8;
+
+__device__ __forceinline__ float relu_bits(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
+
+// relu, then bf16 (round to nearest even) of 4 + 4 accumulator values
+__device__ __forceinline__ bf16x8 pack_relu(const f32x4 &a, const f32x4 &b) {
+  const f32x8 v = {relu_bits(a[0]), relu_bits(a[1]), relu_bits(a[2]), relu_bits(a[3]),
+                   relu_bits(b[0]), relu_bits(b[1]), relu_bits(b[2]), relu_bits(b[3])};
+  return __builtin_convertvector(v, bf16x8);
+}
+
+// One hidden layer over the wave's 4 parcel tiles: in[t][kt] (KT K tiles)
+// -> out[t][p], p = the next layer's K tile (m-tiles 2p and 2p + 1).
+template <int KT>
+__device__ __forceinline__ void mlp_layer(const uint16_t *sw, int ld, const float *sbias,
+                                          const bf16x8 (&in)[4][KT], bf16x8 (&out)[4][4]) {
+  const int l = threadIdx.x & 63, col = l & 15, g = l >> 4;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) ys[t * 16 + kq * 4 + q][row] = o[q];
-    __syncthreads();
+  for (int p = 0; p < 4; ++p) {
+    f32x4 acc[2][4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int mt = 2 * p + h;
+      const f32x4 b = *reinterpret_cast<const f32x4 *>(sbias + 16 * mt + 4 * g);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc[h][t] = b;
+#pragma unroll
+      for (int kt = 0; kt < KT; ++kt) {
+        const bf16x8 a = frag8(sw + (16 * mt + col) * ld + 32 * kt + 8 * g);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[h][t] = mfma(a, in[t][kt], acc[h][t]);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) out[t][p] = pack_relu(acc[0][t], acc[1][t]);
   }
-  if (i < n)
-    for (int q = 0; q < kSurrOut; ++q) y[i * kSurrOut + q] = W.norm[6 + q] + W.norm[9 + q] * ys[l][q];
+}
+
+// Stencil rows in the MLP's input order: K tile c (32 wide) holds the 27
+// values of level shift c - 1 as (b, a, var) with var fastest, then 5 zeros
+// (input index of slot j < 27: (j % 3) * 27 + c * 9 + j / 3).  The
+// layer-1 weights are permuted to this order when they are staged.
+__device__ __forceinline__ void pack_ktile(const float (&g)[27], const float (&inv)[3], const float *norm,
+                                           bf16x8 (&dst)[4]) {
+#pragma unroll
+  for (int c8 = 0; c8 < 4; ++c8) {
+    f32x8 v;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int q = 8 * c8 + j;
+      v[j] = q < 27 ? (g[q] - norm[q % 3]) * inv[q % 3] : 0.0f;
+    }
+    dst[c8] = __builtin_convertvector(v, bf16x8);
+  }
+}
+
+__device__ __forceinline__ void store_ktile(const float (&g)[27], const float (&inv)[3],
+                                            const float *norm, uint16_t *dst) {
+  bf16x8 t[4];
+  pack_ktile(g, inv, norm, t);
+#pragma unroll
+  for (int c8 = 0; c8 < 4; ++c8) *reinterpret_cast<bf16x8 *>(dst + 8 * c8) = t[c8];
+}
+
+// The inference LDS image of the forward weights wt: layer 1 with K in the
+// stencil rows' order (slot 32 c + j < 32 c + 27 of row m holds input
+// (j % 3) * 27 + c * 9 + j / 3), layers 2..4 with K in the order of the
+// accumulator tiles of the layer before (slot 32 kt + 8 g + j holds unit
+// 32 kt + 4 g + j for j < 4, 32 kt + 16 + 4 g + j - 4 for j >= 4); rows
+// padded by 8 zeros against LDS bank conflicts.
+__global__ void k_surr_pack_inf(const uint16_t *wt, uint16_t *wi) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= kWiSize) return;
+  uint16_t v = 0;
+  if (e < kSurrHid * kW1Ld) {
+    const int m = e / kW1Ld, k = e % kW1Ld, c = k >> 5, j = k & 31;
+    if (k < kSurrInPad && j < 27) v = wt[m * kSurrInPad + (j % 3) * 27 + c * 9 + j / 3];
+  } else {
+    const int e2 = e - kSurrHid * kW1Ld;
+    const int layer = e2 / (kSurrHid * kWLd);             // 0, 1: W2, W3; 2: W4
+    const int m = (e2 % (kSurrHid * kWLd)) / kWLd, k = e2 % kWLd;
+    const uint16_t *src = wt + kSurrHid * kSurrInPad + layer * kSurrHid * kSurrHid;
+    if (k < kSurrHid) {
+      const int kt = k >> 5, g = (k >> 3) & 3, j = k & 7;
+      v = src[m * kSurrHid + 32 * kt + (j < 4 ? 4 * g + j : 16 + 4 * g + j - 4)];
+    }
+  }
+  wi[e] = v;
+}
+
+// Persistent over groups of 64 parcels: X rows (bf16, normalized, 96 wide)
+// -> Y[row * ldy + q] = de-normalized (east km, north km, dp hPa).
+__global__ __launch_bounds__(kMlpThreads) void k_surr_mlp(const SurrW W, const uint16_t *X, int64_t n,
+                                                          float *Y, int ldy) {
+  __shared__ __attribute__((aligned(16))) uint16_t sw[kWiSize];
+  __shared__ __attribute__((aligned(16))) float sb[3 * kSurrHid + kSurrOutPad + 12];
+  uint16_t *sw1 = sw, *sw2 = sw1 + kSurrHid * kW1Ld, *sw3 = sw2 + kSurrHid * kWLd, *sw4 = sw3 + kSurrHid * kWLd;
+  const int tid = threadIdx.x;
+  for (int q = tid; q < kWiSize / 8; q += kMlpThreads)
+    reinterpret_cast<uint4 *>(sw)[q] = reinterpret_cast<const uint4 *>(W.wi)[q];
+  for (int q = tid; q < kSurrHid; q += kMlpThreads) {
+    sb[q] = W.b1[q];
+    sb[kSurrHid + q] = W.b2[q];
+    sb[2 * kSurrHid + q] = W.b3[q];
+  }
+  if (tid < kSurrOutPad) sb[3 * kSurrHid + tid] = W.b4[tid];
+  if (tid < 12) sb[3 * kSurrHid + kSurrOutPad + tid] = W.norm[tid];
+  __syncthreads();
+  const float *nm = sb + 3 * kSurrHid + kSurrOutPad;
+  const int l = tid & 63, col = l & 15, g = l >> 4;
+  constexpr int kWaves = kMlpThreads / 64;
+  const int64_t ngroups = (n + 63) / 64;
+  for (int64_t grp = (int64_t)blockIdx.x * kWaves + (tid >> 6); grp < ngroups;
+       grp += (int64_t)gridDim.x * kWaves) {
+    // keeps the weight fragment reads inside the loop (hoisted, the 92
+    // fragments would need 368 registers)
+    asm volatile("" ::: "memory");
+    bf16x8 x[4][kSurrInPad / 32];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int64_t row = grp * 64 + 16 * t + col;
+#pragma unroll
+      for (int kt = 0; kt < kSurrInPad / 32; ++kt)
+        x[t][kt] = row < n ? frag8(X + row * kSurrInPad + 32 * kt + 8 * g) : frag8_zero();
+    }
+    bf16x8 h1[4][4], h2[4][4];
+    mlp_layer<kSurrInPad / 32>(sw1, kW1Ld, sb, x, h1);
+    mlp_layer<4>(sw2, kWLd, sb + kSurrHid, h1, h2);
+    mlp_layer<4>(sw3, kWLd, sb + 2 * kSurrHid, h2, h1);
+    f32x4 o[4];
+    const f32x4 b4 = *reinterpret_cast<const f32x4 *>(sb + 3 * kSurrHid + 4 * g);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) o[t] = b4;
+#pragma unroll
+    for (int kt = 0; kt < 4; ++kt) {
+      const bf16x8 a = frag8(sw4 + col * kWLd + 32 * kt + 8 * g);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) o[t] = mfma(a, h1[t][kt], o[t]);
+    }
+    if (g == 0) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int64_t row = grp * 64 + 16 * t + col;
+        if (row < n)
+#pragma unroll
+          for (int q = 0; q < kSurrOut; ++q) Y[row * ldy + q] = nm[6 + q] + nm[9 + q] * o[t][q];
+      }
+    }
+  }
+}
+
+// Raw inputs (FP32, 81 per row, input index order) -> normalized bf16 rows
+// of 96 in the MLP's input order (see store_ktile).
+__global__ __launch_bounds__(256) void k_surr_xnorm(const SurrW W, const float *x, int64_t n,
+                                                    uint16_t *X) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float inv[3];
+#pragma unroll
+  for (int v = 0; v < 3; ++v) inv[v] = 1.0f / W.norm[3 + v];
+  const float *xr = x + i * kSurrIn;
+#pragma unroll
+  for (int sc = 0; sc < 3; ++sc) {
+    float g[27];
+#pragma unroll
+    for (int j = 0; j < 27; ++j) g[j] = xr[(j % 3) * 27 + sc * 9 + j / 3];
+    store_ktile(g, inv, W.norm, X + i * kSurrInPad + 32 * sc);
+  }
 }
 
 // ---- training ---------------------------------------------------------------------
@@ -348,9 +508,12 @@ __global__ __launch_bounds__(64) void k_surr_train_fwd(const SurrW W, const Surr
   __shared__ __attribute__((aligned(16))) uint16_t ha[16 * kHLd], hb[16 * kHLd];
   const int l = threadIdx.x;
   const int64_t r0 = (int64_t)blockIdx.x * 64, i = r0 + l;
+  float inv[3];
+#pragma unroll
+  for (int v = 0; v < 3; ++v) inv[v] = 1.0f / W.norm[3 + v];
   for (int c = 0; c < kXLd; ++c) {
     float v = 0.0f;
-    if (c < kSurrIn) v = (T.x[i * kSurrIn + c] - W.norm[c / 27]) / W.norm[3 + c / 27];
+    if (c < kSurrIn) v = (T.x[i * kSurrIn + c] - W.norm[c / 27]) * inv[c / 27];
     const uint16_t q = f2bf(v);
     xs[l * kXLd + c] = q;
     if (c < kSurrInPad) T.xn[i * kSurrInPad + c] = q;
@@ -488,22 +651,75 @@ __global__ void k_surr_adam(float *params, const float *grad, float *m, float *v
 }
 
 // ---- surrogate stepping -------------------------------------------------------------
-// One wave per 64 parcels, one block of kSurrK steps from step0:
-// stencil -> MLP -> consistency estimate -> accept (displacement plus the
-// block's turbulent and mesoscale diffusion with the block-start spread) or
-// kSurrK plain steps.
-__global__ __launch_bounds__(64) void k_surr_step(const StepArgs a, const SurrW W, float tau_km,
-                                                  uint32_t *fallbacks, float *err_out,
-                                                  uint32_t *fb_list, uint32_t *fb_count) {
-  __shared__ __attribute__((aligned(16))) uint16_t xs[64 * kXLd];
-  __shared__ __attribute__((aligned(16))) uint16_t ha[16 * kHLd], hb[16 * kHLd];
-  __shared__ float ys[64][4];
-  const int l = threadIdx.x;
+// A block of kSurrK steps runs over chunks of parcels in three passes:
+// stencil rows (k_surr_x), MLP (k_surr_mlp), then the consistency estimate
+// and either acceptance (displacement plus the block's turbulent and
+// mesoscale diffusion with the block-start spread) or a place in the list
+// of parcels that take kSurrK plain steps (k_surr_apply).
+
+// Stencil inputs of parcels i0 .. i0 + cnt - 1 at the block's start time,
+// normalized, as bf16 rows of 96 in the MLP's input order; a parcel with a
+// non-finite position gets a zero row.  Rows are staged in LDS (stores
+// between the gathers would hold up the waits for them, as the memory
+// counter covers both) and the block's 256 consecutive rows leave in one
+// coalesced copy.
+constexpr int kRowLd = kSurrInPad / 8 + 1;      // 16-byte units per staged row (padded)
+
+__global__ __launch_bounds__(256) void k_surr_x(const StepArgs a, const SurrW W, int64_t i0, int64_t cnt,
+                                                uint16_t *X) {
+  __shared__ bf16x8 srow[256 * kRowLd];
+  const int lb = logical_block((int)blockIdx.x, a.per_xcd);
+  if (lb >= a.nblk) return;                       // uniform over the block
+  const int64_t r0 = (int64_t)lb * 256;
+  const int64_t r = r0 + threadIdx.x;
+  bf16x8 *mine = srow + threadIdx.x * kRowLd;
+  bool valid = false;
+  double lon = 0.0, lat = 0.0, p = 0.0;
+  if (r < cnt) {
+    lon = a.lon[i0 + r];
+    lat = a.lat[i0 + r];
+    p = a.p[i0 + r];
+    valid = finite3(lon, lat, p);
+  }
+  if (valid) {
+    float inv[3];
+#pragma unroll
+    for (int v = 0; v < 3; ++v) inv[v] = 1.0f / W.norm[3 + v];
+    Loc<float> L;
+    surr_locate(a, lon, lat, p, a.t_start + (double)a.step0 * a.dt, L);
+    stencil81(a, L, [&](int sc, const float (&g)[27]) {
+      bf16x8 t[4];
+      pack_ktile(g, inv, W.norm, t);
+#pragma unroll
+      for (int c8 = 0; c8 < 4; ++c8) mine[4 * sc + c8] = t[c8];
+    });
+  } else {
+#pragma unroll
+    for (int c = 0; c < kSurrInPad / 8; ++c) mine[c] = frag8_zero();
+  }
+  __syncthreads();
+  const int64_t rows = cnt - r0 < 256 ? cnt - r0 : 256;
+  for (int q = threadIdx.x; q < rows * (kSurrInPad / 8); q += 256) {
+    const int row = q / (kSurrInPad / 8), c = q % (kSurrInPad / 8);
+    *reinterpret_cast<bf16x8 *>(X + (r0 + row) * kSurrInPad + 8 * c) = srow[row * kRowLd + c];
+  }
+}
+
+// Consistency estimate, then acceptance or fallback, for parcels
+// i0 .. i0 + cnt - 1 with predictions Y (4 floats per row).  Every wave
+// records the ballot of its parcels that fall back in fb_mask[i / 64]
+// (i0 is a multiple of 64), from which an ordered list is built.
+__global__ __launch_bounds__(256) void k_surr_apply(const StepArgs a, float tau_km, const float *Y,
+                                                    int64_t i0, int64_t cnt, uint32_t *fallbacks,
+                                                    float *err_out, uint64_t *fb_mask) {
   const int lb = logical_block((int)blockIdx.x, a.per_xcd);
   if (lb >= a.nblk) return;
-  const int64_t i = (int64_t)lb * 64 + l;
-  const bool in_range = i < a.n;
-  double lon = 0.0, lat = 0.0, p = 500.0;
+  const int64_t r = (int64_t)lb * 256 + threadIdx.x;
+  const int l = threadIdx.x & 63;
+  if (r - l >= cnt) return;                          // the whole wave is past the chunk
+  const int64_t i = i0 + r;
+  const bool in_range = r < cnt;
+  double lon = 0.0, lat = 0.0, p = 0.0;
   if (in_range) {
     lon = a.lon[i];
     lat = a.lat[i];
@@ -511,61 +727,44 @@ __global__ __launch_bounds__(64) void k_surr_step(const StepArgs a, const SurrW 
   }
   const bool valid = in_range && finite3(lon, lat, p);
   const double t0 = a.t_start + (double)a.step0 * a.dt;
-  Loc<float> L;
-  surr_locate(a, valid ? lon : 0.0, valid ? lat : 0.0, valid ? p : 500.0, t0, L);
-  stencil81(a, L, [&](int idx, float v) {
-    xs[l * kXLd + idx] = f2bf((v - W.norm[idx / 27]) / W.norm[3 + idx / 27]);
-  });
-  for (int c = kSurrIn; c < kXLd; ++c) xs[l * kXLd + c] = 0;
-  __syncthreads();
-  for (int t = 0; t < 4; ++t) {
-    const f32x4 o = mlp16(xs + t * 16 * kXLd, kXLd, W, ha, hb, nullptr, nullptr, nullptr, 0, 0);
-    const int row = l & 15, kq = l >> 4;
-    if (row < kSurrOut)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) ys[t * 16 + kq * 4 + q][row] = o[q];
-    __syncthreads();
-  }
-  if (!valid) return;
-  const float de = W.norm[6] + W.norm[9] * ys[l][0];
-  const float dn = W.norm[7] + W.norm[10] * ys[l][1];
-  const float dpp = W.norm[8] + W.norm[11] * ys[l][2];
-  // consistency estimate: kSurrK dt times the wind at the predicted midpoint
-  const float c0 = cos_floor<float>(a, lat);
   const float kdeg = (float)kDeg;
-  const double lonm = lon + (double)(0.5f * de * 1000.0f * kdeg / c0);
-  const double latm = lat + (double)(0.5f * dn * 1000.0f * kdeg);
-  const double pm = p + (double)(0.5f * dpp);
-  Cell16<kF32> cell;
-  Loc<float> Lm;
-  surr_locate(a, lonm, latm, pm, t0 + 0.5 * kSurrK * a.dt, Lm);
-  load_cell<kF32, float>(a, Lm, cell);
-  float wm[3];
-  interp_cell<kF32, float>(a, cell, Lm, wm);
-  const float span = (float)(kSurrK * a.dt) * 1e-3f;
-  const float ee = de - span * wm[0], en = dn - span * wm[1];
-  const float err = sqrtf(ee * ee + en * en);
-  if (err_out) err_out[i] = err;
+  float de = 0.f, dn = 0.f, dpp = 0.f, c0 = 1.f;
+  bool accept = false;
+  if (valid) {
+    const float4 yv = *reinterpret_cast<const float4 *>(Y + r * 4);
+    de = yv.x;
+    dn = yv.y;
+    dpp = yv.z;
+    // consistency estimate: kSurrK dt times the wind at the predicted midpoint
+    c0 = cos_floor<float>(a, lat);
+    const double lonm = lon + (double)(0.5f * de * 1000.0f * kdeg / c0);
+    const double latm = lat + (double)(0.5f * dn * 1000.0f * kdeg);
+    const double pm = p + (double)(0.5f * dpp);
+    Cell16<kF32> cell;
+    Loc<float> Lm;
+    surr_locate(a, lonm, latm, pm, t0 + 0.5 * kSurrK * a.dt, Lm);
+    load_cell<kF32, float>(a, Lm, cell);
+    float wm[3];
+    interp_cell<kF32, float>(a, cell, Lm, wm);
+    const float span = (float)(kSurrK * a.dt) * 1e-3f;
+    const float ee = de - span * wm[0], en = dn - span * wm[1];
+    const float err = sqrtf(ee * ee + en * en);
+    if (err_out) err_out[i] = err;
+    accept = err <= tau_km && isfinite(err);
+  }
+  // parcels that fall back keep their state here; the plain step kernel
+  // takes them from the ordered list
+  const uint64_t fb = __ballot(valid && !accept);
+  if (l == 0) {
+    fb_mask[i / 64] = fb;
+    if (fb) atomicAdd(fallbacks, (uint32_t)__popcll(fb));
+  }
+  if (!valid || !accept) return;
   const uint32_t id = a.id[i];
   float up = static_cast<const float *>(a.up)[i];
   float vp = static_cast<const float *>(a.vp)[i];
   float wp = static_cast<const float *>(a.wp)[i];
   const bool meso_on = (a.flags & kMeso) != 0;
-  const bool accept = err <= tau_km && isfinite(err);
-  // parcels that fall back keep their state here and are queued for the
-  // plain step kernel (a wave-aggregated append to the list)
-  const uint64_t fb = __ballot(!accept);
-  if (fb) {
-    const int leader = __ffsll((long long)fb) - 1;
-    uint32_t base = 0;
-    if (l == leader) {
-      base = atomicAdd(fb_count, (uint32_t)__popcll(fb));
-      atomicAdd(fallbacks, (uint32_t)__popcll(fb));
-    }
-    base = __shfl(base, leader);
-    if (!accept) fb_list[base + __popcll(fb & ((1ull << l) - 1ull))] = (uint32_t)i;
-  }
-  if (!accept) return;
   float sg[3] = {0.f, 0.f, 0.f};
   if (meso_on) meso_sigma<kF32, float>(a, a.plev, a.inv_dp, a.lut, t0 + 0.5 * a.dt, lon, lat, p, sg);
   lon = lon + (double)(de * 1000.0f * kdeg / c0);
@@ -588,6 +787,24 @@ __global__ __launch_bounds__(64) void k_surr_step(const StepArgs a, const SurrW 
   static_cast<float *>(a.up)[i] = up;
   static_cast<float *>(a.vp)[i] = vp;
   static_cast<float *>(a.wp)[i] = wp;
+}
+
+// off[w] = number of set bits of fb_mask[w] for w < nw, off[nw] = 0.
+__global__ void k_fb_counts(const uint64_t *fb_mask, int64_t nw, uint32_t *off) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w < nw) off[w] = (uint32_t)__popcll(fb_mask[w]);
+  else if (w == nw) off[w] = 0u;
+}
+
+// After the exclusive scan of the counts: wave w's parcels that fall back
+// go to list[off[w] ...] in increasing index order.
+__global__ __launch_bounds__(256) void k_fb_expand(const uint64_t *fb_mask, int64_t nw, const uint32_t *off,
+                                                   uint32_t *list) {
+  const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (w >= nw) return;
+  const int l = threadIdx.x & 63;
+  const uint64_t m = fb_mask[w];
+  if ((m >> l) & 1ull) list[off[w] + __popcll(m & ((1ull << l) - 1ull))] = (uint32_t)(w * 64 + l);
 }
 
 // ---- launchers ------------------------------------------------------------------------
@@ -616,8 +833,63 @@ hipError_t launch_surr_pack(const float *params, uint16_t *wt, uint16_t *wb, hip
   return hipGetLastError();
 }
 
-hipError_t launch_surr_forward(const SurrW &W, const float *x, int64_t n, float *y, hipStream_t s) {
-  hipLaunchKernelGGL(k_surr_forward, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, W, x, n, y);
+hipError_t launch_surr_pack_inf(const uint16_t *wt, uint16_t *wi, hipStream_t s) {
+  hipLaunchKernelGGL(k_surr_pack_inf, dim3((kWiSize + 255) / 256), dim3(256), 0, s, wt, wi);
+  return hipGetLastError();
+}
+
+hipError_t launch_surr_forward(const SurrW &W, const float *x, int64_t n, uint16_t *X, float *y,
+                               int64_t chunk, hipStream_t s) {
+  for (int64_t i0 = 0; i0 < n; i0 += chunk) {
+    const int64_t cnt = n - i0 < chunk ? n - i0 : chunk;
+    hipLaunchKernelGGL(k_surr_xnorm, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, W,
+                       x + i0 * kSurrIn, cnt, X);
+    const hipError_t e = launch_surr_mlp(W, X, cnt, y + i0 * kSurrOut, kSurrOut, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_surr_mlp(const SurrW &W, const uint16_t *X, int64_t n, float *Y, int ldy, hipStream_t s) {
+  const int64_t groups = (n + 63) / 64;
+  const int64_t want = (groups + kMlpThreads / 64 - 1) / (kMlpThreads / 64);
+  const unsigned nb = (unsigned)(want < kMlpBlocks ? want : kMlpBlocks);
+  hipLaunchKernelGGL(k_surr_mlp, dim3(nb), dim3(kMlpThreads), 0, s, W, X, n, Y, ldy);
+  return hipGetLastError();
+}
+
+// Per-chunk launch shape of the one-parcel-per-thread passes.
+static StepArgs chunk_args(const StepArgs &a, int64_t cnt) {
+  StepArgs c = a;
+  const int64_t nblk = (cnt + 255) / 256;
+  c.nblk = (int32_t)nblk;
+  c.per_xcd = (int32_t)((nblk + kXcds - 1) / kXcds);
+  return c;
+}
+
+hipError_t launch_surr_x(const StepArgs &a, const SurrW &W, int64_t i0, int64_t cnt, uint16_t *X,
+                         hipStream_t s) {
+  const StepArgs c = chunk_args(a, cnt);
+  hipLaunchKernelGGL(k_surr_x, dim3((unsigned)(c.per_xcd * kXcds)), dim3(256), 0, s, c, W, i0, cnt, X);
+  return hipGetLastError();
+}
+
+hipError_t launch_surr_apply(const StepArgs &a, float tau_km, const float *Y, int64_t i0, int64_t cnt,
+                             uint32_t *fallbacks, float *err_out, uint64_t *fb_mask, hipStream_t s) {
+  const StepArgs c = chunk_args(a, cnt);
+  hipLaunchKernelGGL(k_surr_apply, dim3((unsigned)(c.per_xcd * kXcds)), dim3(256), 0, s, c, tau_km, Y, i0,
+                     cnt, fallbacks, err_out, fb_mask);
+  return hipGetLastError();
+}
+
+hipError_t launch_surr_fblist(const uint64_t *fb_mask, int64_t n, uint32_t *off, uint32_t *sums,
+                              uint32_t *list, hipStream_t s) {
+  const int64_t nw = (n + 63) / 64;
+  hipLaunchKernelGGL(k_fb_counts, dim3((unsigned)((nw + 1 + 255) / 256)), dim3(256), 0, s, fb_mask, nw, off);
+  const hipError_t e = launch_scan_u32(off, (uint32_t)(nw + 1), sums, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fb_expand, dim3((unsigned)((nw * 64 + 255) / 256)), dim3(256), 0, s, fb_mask, nw, off,
+                     list);
   return hipGetLastError();
 }
 
@@ -637,13 +909,6 @@ hipError_t launch_surr_grad(const SurrW &W, const SurrTrain &T, hipStream_t s) {
   hipLaunchKernelGGL(k_surr_train_fwd, dim3(nb), dim3(64), 0, s, W, T);
   hipLaunchKernelGGL(k_surr_train_bwd, dim3(nb), dim3(64), 0, s, W, T);
   hipLaunchKernelGGL(k_surr_wgrad, dim3(48 + 64 + 64 + 8 + 7), dim3(64), 0, s, T, T.grad);
-  return hipGetLastError();
-}
-
-hipError_t launch_surr_step(const StepArgs &a, const SurrW &W, float tau_km, uint32_t *fallbacks,
-                            float *err_out, uint32_t *fb_list, uint32_t *fb_count, hipStream_t s) {
-  hipLaunchKernelGGL(k_surr_step, dim3((unsigned)(a.per_xcd * kXcds)), dim3(64), 0, s, a, W, tau_km,
-                     fallbacks, err_out, fb_list, fb_count);
   return hipGetLastError();
 }
 

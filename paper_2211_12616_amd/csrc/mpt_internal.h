@@ -74,14 +74,20 @@ constexpr int kOffW1 = 0, kOffB1 = 12288, kOffW2 = 12416, kOffB2 = 28800, kOffW3
               kOffB3 = 45312, kOffW4 = 45440, kOffB4 = 47488, kSurrNParam = 47504;
 constexpr int kWtSize = 47104;                  // bf16 [out][in] copies of W1..W4
 constexpr int kWbSize = 34816;                  // bf16 [in][out] copies of W2..W4
+// inference LDS image: W1..W4 as [out][in] rows padded by 8, K permuted to
+// the order the MLP kernel feeds them
+constexpr int kW1Ld = kSurrInPad + 8, kWLd = kSurrHid + 8;
+constexpr int kWiSize = kSurrHid * kW1Ld + 2 * kSurrHid * kWLd + kSurrOutPad * kWLd;
 constexpr int kSurrMaxBatch = 8192;
 constexpr int kSurrStatBlocks = 1024;
+constexpr int64_t kSurrChunk = 1 << 20;          // parcels per stencil / MLP / apply pass
 
 struct SurrW {
   const uint16_t *wt1, *wt2, *wt3, *wt4;        // forward fragments, [out][in]
   const uint16_t *wb2, *wb3, *wb4;              // backward fragments, [in][out]
   const float *b1, *b2, *b3, *b4;
   const float *norm;                            // in mean[3], in std[3], out mean[3], out std[3]
+  const uint16_t *wi;                           // inference LDS image (loaded weights only)
 };
 
 struct SurrTrain {
@@ -98,16 +104,35 @@ hipError_t launch_surr_stats(const float *x, const float *y, int64_t n, double *
                              float *norm, hipStream_t s);
 hipError_t launch_surr_init(float *params, uint64_t seed, hipStream_t s);
 hipError_t launch_surr_pack(const float *params, uint16_t *wt, uint16_t *wb, hipStream_t s);
-hipError_t launch_surr_forward(const SurrW &W, const float *x, int64_t n, float *y, hipStream_t s);
+hipError_t launch_surr_pack_inf(const uint16_t *wt, uint16_t *wi, hipStream_t s);
+// raw inputs -> outputs, in chunks of at most `chunk` rows through X (bf16 [chunk][96])
+hipError_t launch_surr_forward(const SurrW &W, const float *x, int64_t n, uint16_t *X, float *y,
+                               int64_t chunk, hipStream_t s);
+// normalized bf16 rows X [n][96] -> Y[row * ldy + 0..2]
+hipError_t launch_surr_mlp(const SurrW &W, const uint16_t *X, int64_t n, float *Y, int ldy, hipStream_t s);
+// stencil rows of parcels i0 .. i0 + cnt - 1 at step a.step0
+hipError_t launch_surr_x(const StepArgs &a, const SurrW &W, int64_t i0, int64_t cnt, uint16_t *X,
+                         hipStream_t s);
+// consistency estimate and acceptance for parcels i0 .. i0 + cnt - 1 (i0 a
+// multiple of 64); fb_mask[i / 64] gets the wave's ballot of parcels that
+// fall back
+hipError_t launch_surr_apply(const StepArgs &a, float tau_km, const float *Y, int64_t i0, int64_t cnt,
+                             uint32_t *fallbacks, float *err_out, uint64_t *fb_mask, hipStream_t s);
+// ordered fallback list: list[0 .. off[nw]) = indices of the set bits of
+// fb_mask[0 .. nw), nw = ceil(n / 64), in increasing order; off holds nw + 1
+// entries and sums scan_block_sums_len(nw + 1)
+hipError_t launch_surr_fblist(const uint64_t *fb_mask, int64_t n, uint32_t *off, uint32_t *sums,
+                              uint32_t *list, hipStream_t s);
 hipError_t launch_surr_train(const SurrW &W, const SurrTrain &T, float *params, float *m, float *v,
                              float lr, float bc1, float bc2, hipStream_t s);
 hipError_t launch_surr_grad(const SurrW &W, const SurrTrain &T, hipStream_t s);
-hipError_t launch_surr_step(const StepArgs &a, const SurrW &W, float tau_km, uint32_t *fallbacks,
-                            float *err_out, uint32_t *fb_list, uint32_t *fb_count, hipStream_t s);
 
 // Single-word device helpers (k_step.hip).
 hipError_t launch_set_u32(uint32_t *p, uint32_t v, hipStream_t stream);
 hipError_t launch_add_u32(uint32_t *p, uint32_t v, hipStream_t stream);
 size_t scan_block_sums_len(uint32_t nkeys);
+// exclusive prefix sum of data[0 .. n) in place; block_sums holds
+// scan_block_sums_len(n) entries (k_sort.hip)
+hipError_t launch_scan_u32(uint32_t *data, uint32_t n, uint32_t *block_sums, hipStream_t stream);
 
 }  // namespace mpt

@@ -29,7 +29,6 @@ struct mpt_ctx {
   int32_t *rank;          // [kMaxScen] rank of the scenario in release order
   int32_t *rel_sorted;    // [kMaxScen] release steps in ascending order
   uint32_t *step_dev;     // step index read by graph-replayed kernels
-  uint32_t *fb_count;     // surrogate fallback list length
   uint32_t *keys, *ranks, *hist, *block_sums;
   uint32_t ntx, nty, ntz, ntiles, nkeys;
   // host state
@@ -37,8 +36,13 @@ struct mpt_ctx {
   uint64_t levels_ready;  // bit l set once level l was stored (nt <= 64)
   int32_t nscen;
   // surrogate: bf16 weight copies, normalization, training scratch
-  uint16_t *s_wt, *s_wb;
+  uint16_t *s_wt, *s_wb, *s_wi;
   float *s_norm, *s_bias;               // loaded normalization and biases (FP32)
+  uint16_t *s_x;                        // stencil rows of one chunk (bf16 [s_chunk][96])
+  float *s_y;                           // predictions of one chunk ([s_chunk][4])
+  int64_t s_chunk;
+  uint64_t *fb_mask;                    // per wave of 64 parcels: ballot of surrogate fallbacks
+  uint32_t *fb_off, *fb_sums;           // its prefix sums (+ total) and scan scratch
   float s_tau;
   int s_loaded;
   uint16_t *t_xn, *t_h1, *t_h2, *t_h3, *t_dy, *t_dh1, *t_dh2, *t_dh3;
@@ -98,9 +102,17 @@ mpt_status check_params(const mpt_params *p, const mpt_grid *g) {
 
 struct Layout {
   size_t met, scales, plev, inv_dp, lut, release, rank, rel_sorted, step_dev, keys, ranks, hist,
-      block_sums, s_wt, s_wb, s_norm, s_bias, t_xn, t_h, t_dy, t_dh, t_yp, t_grad, t_part, total;
+      block_sums, s_wt, s_wb, s_wi, s_norm, s_bias, s_x, s_y, fb_mask, fb_off, fb_sums, t_xn, t_h, t_dy, t_dh, t_yp, t_grad, t_part, total;
   uint32_t ntx, nty, ntz, ntiles, nkeys;
+  int64_t s_chunk;
 };
+
+// Rows per pass of the surrogate's stencil / MLP / apply kernels.
+int64_t surr_chunk(int64_t n_max) {
+  int64_t c = n_max > kSurrMaxBatch ? n_max : kSurrMaxBatch;
+  c = (c + 63) / 64 * 64;
+  return c < kSurrChunk ? c : kSurrChunk;
+}
 
 Layout layout(const mpt_grid *g, int64_t n_max) {
   Layout L;
@@ -126,8 +138,16 @@ Layout layout(const mpt_grid *g, int64_t n_max) {
   L.block_sums = off; off += align_up(sizeof(uint32_t) * scan_block_sums_len(L.nkeys));
   L.s_wt = off;       off += align_up(sizeof(uint16_t) * kWtSize);
   L.s_wb = off;       off += align_up(sizeof(uint16_t) * kWbSize);
+  L.s_wi = off;       off += align_up(sizeof(uint16_t) * kWiSize);
   L.s_norm = off;     off += align_up(sizeof(float) * 12);
   L.s_bias = off;     off += align_up(sizeof(float) * 400);
+  L.s_chunk = surr_chunk(n_max);
+  L.s_x = off;        off += align_up(sizeof(uint16_t) * (size_t)L.s_chunk * kSurrInPad);
+  L.s_y = off;        off += align_up(sizeof(float) * (size_t)L.s_chunk * 4);
+  const size_t nw = (size_t)((n_max > 0 ? n_max : 0) + 63) / 64;
+  L.fb_mask = off;    off += align_up(sizeof(uint64_t) * nw);
+  L.fb_off = off;     off += align_up(sizeof(uint32_t) * (nw + 1));
+  L.fb_sums = off;    off += align_up(sizeof(uint32_t) * scan_block_sums_len((uint32_t)(nw + 1)));
   L.t_xn = off;       off += align_up(sizeof(uint16_t) * kSurrMaxBatch * kSurrInPad);
   L.t_h = off;        off += align_up(sizeof(uint16_t) * kSurrMaxBatch * kSurrHid * 3);
   L.t_dy = off;       off += align_up(sizeof(uint16_t) * kSurrMaxBatch * kSurrOutPad);
@@ -349,6 +369,7 @@ SurrW surr_weights(const mpt_ctx *c, const float *params, const float *norm) {
   W.b3 = params + kOffB3;
   W.b4 = params + kOffB4;
   W.norm = norm;
+  W.wi = c->s_wi;
   return W;
 }
 
@@ -407,7 +428,6 @@ mpt_status mpt_create(const mpt_grid *grid, const mpt_params *params, int64_t n_
   c->rank = reinterpret_cast<int32_t *>(ws + L.rank);
   c->rel_sorted = reinterpret_cast<int32_t *>(ws + L.rel_sorted);
   c->step_dev = reinterpret_cast<uint32_t *>(ws + L.step_dev);
-  c->fb_count = c->step_dev + 1;
   c->keys = reinterpret_cast<uint32_t *>(ws + L.keys);
   c->ranks = reinterpret_cast<uint32_t *>(ws + L.ranks);
   c->hist = reinterpret_cast<uint32_t *>(ws + L.hist);
@@ -415,8 +435,15 @@ mpt_status mpt_create(const mpt_grid *grid, const mpt_params *params, int64_t n_
   c->ntx = L.ntx; c->nty = L.nty; c->ntz = L.ntz; c->ntiles = L.ntiles; c->nkeys = L.nkeys;
   c->s_wt = reinterpret_cast<uint16_t *>(ws + L.s_wt);
   c->s_wb = reinterpret_cast<uint16_t *>(ws + L.s_wb);
+  c->s_wi = reinterpret_cast<uint16_t *>(ws + L.s_wi);
   c->s_norm = reinterpret_cast<float *>(ws + L.s_norm);
   c->s_bias = reinterpret_cast<float *>(ws + L.s_bias);
+  c->s_x = reinterpret_cast<uint16_t *>(ws + L.s_x);
+  c->s_y = reinterpret_cast<float *>(ws + L.s_y);
+  c->s_chunk = L.s_chunk;
+  c->fb_mask = reinterpret_cast<uint64_t *>(ws + L.fb_mask);
+  c->fb_off = reinterpret_cast<uint32_t *>(ws + L.fb_off);
+  c->fb_sums = reinterpret_cast<uint32_t *>(ws + L.fb_sums);
   c->t_xn = reinterpret_cast<uint16_t *>(ws + L.t_xn);
   c->t_h1 = reinterpret_cast<uint16_t *>(ws + L.t_h);
   c->t_h2 = c->t_h1 + (size_t)kSurrMaxBatch * kSurrHid;
@@ -698,7 +725,9 @@ mpt_status mpt_surrogate_load(mpt_ctx *c, const float *params, const float *norm
                               void *hip_stream) {
   if (!c || !params || !norm || !(tau_km >= 0.0f)) return MPT_ERR_ARG;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  if (launch_surr_pack(params, c->s_wt, c->s_wb, s) != hipSuccess) return MPT_ERR_HIP;
+  if (launch_surr_pack(params, c->s_wt, c->s_wb, s) != hipSuccess ||
+      launch_surr_pack_inf(c->s_wt, c->s_wi, s) != hipSuccess)
+    return MPT_ERR_HIP;
   if (hipMemcpyAsync(c->s_bias, params + kOffB1, sizeof(float) * 128, hipMemcpyDeviceToDevice, s) != hipSuccess ||
       hipMemcpyAsync(c->s_bias + 128, params + kOffB2, sizeof(float) * 128, hipMemcpyDeviceToDevice, s) != hipSuccess ||
       hipMemcpyAsync(c->s_bias + 256, params + kOffB3, sizeof(float) * 128, hipMemcpyDeviceToDevice, s) != hipSuccess ||
@@ -717,6 +746,7 @@ SurrW loaded_weights(const mpt_ctx *c) {
   W.b2 = c->s_bias + 128;
   W.b3 = c->s_bias + 256;
   W.b4 = c->s_bias + 384;
+  W.wi = c->s_wi;
   return W;
 }
 }  // namespace
@@ -725,7 +755,8 @@ mpt_status mpt_surrogate_forward(mpt_ctx *c, int64_t n, const float *x, float *y
   if (!c || n < 0 || (n > 0 && (!x || !y))) return MPT_ERR_ARG;
   if (!c->s_loaded) return MPT_ERR_STATE;
   if (n == 0) return MPT_OK;
-  return from_hip(launch_surr_forward(loaded_weights(c), x, n, y, static_cast<hipStream_t>(hip_stream)));
+  return from_hip(launch_surr_forward(loaded_weights(c), x, n, c->s_x, y, c->s_chunk,
+                                     static_cast<hipStream_t>(hip_stream)));
 }
 
 mpt_status mpt_step_surrogate(mpt_ctx *c, mpt_particles *P, uint32_t step0, int32_t nsteps,
@@ -756,17 +787,20 @@ mpt_status mpt_step_surrogate(mpt_ctx *c, mpt_particles *P, uint32_t step0, int3
     }
     StepArgs a;
     fill_step_args(c, P, (uint32_t)b0, kSurrK, c->params.flags, a);
-    const int64_t nblk = (P->n + 63) / 64;
-    a.nblk = (int32_t)nblk;
-    a.per_xcd = (int32_t)((nblk + kXcds - 1) / kXcds);
-    if (launch_set_u32(c->fb_count, 0u, s) != hipSuccess ||
-        launch_surr_step(a, W, c->s_tau, fallbacks, err_out, c->keys, c->fb_count, s) != hipSuccess)
+    for (int64_t i0 = 0; i0 < P->n; i0 += c->s_chunk) {
+      const int64_t cnt = P->n - i0 < c->s_chunk ? P->n - i0 : c->s_chunk;
+      if (launch_surr_x(a, W, i0, cnt, c->s_x, s) != hipSuccess ||
+          launch_surr_mlp(W, c->s_x, cnt, c->s_y, 4, s) != hipSuccess ||
+          launch_surr_apply(a, c->s_tau, c->s_y, i0, cnt, fallbacks, err_out, c->fb_mask, s) != hipSuccess)
+        return MPT_ERR_HIP;
+    }
+    if (launch_surr_fblist(c->fb_mask, P->n, c->fb_off, c->fb_sums, c->keys, s) != hipSuccess)
       return MPT_ERR_HIP;
     // parcels that fell back: kSurrK plain steps, walking the list
     StepArgs f;
     fill_step_args(c, P, (uint32_t)b0, kSurrK, c->params.flags, f);
     f.index = c->keys;
-    f.index_count = c->fb_count;
+    f.index_count = c->fb_off + (P->n + 63) / 64;
     f.nblk = kPersistentBlocks;
     f.persistent = 1;
     if (launch_step(c->grid.dtype, 0, f, s) != hipSuccess) return MPT_ERR_HIP;

@@ -152,3 +152,54 @@ def test_tau_zero_falls_back_to_plain_bitwise(mpt, met3):
     torch.cuda.synchronize()
     assert fb.item() == part.n * 8
     assert_bitwise(plain, by_id(P.to_host()))
+
+
+@pytest.mark.parametrize("n", [20_011, (1 << 20) + 777])
+def test_accepted_block_moves_by_the_forward_of_the_stencil(mpt, met3, n):
+    """Advection only, tau = inf: every parcel-block is accepted and moves by
+    the MLP's displacement for the oracle's stencil at its start (forward
+    pass pinned above), followed by the position fix.  n crosses the
+    1 Mi-parcel pass size (the workspace of a context this large holds one
+    pass) with a ragged tail."""
+    import torch
+    say(f"[accepted] n = {n}")
+    part = inputs.make_particles(n, 62)
+    c = mpt.Context(met3, mpt.make_params(math=1, sort_interval=0, flags=mpt.ADVECT), n_max=n)
+    c.upload_met(met3)
+    lon, lat, p, step = starts(8192, 8)
+    x, y = c.surrogate_datagen(*to_dev(lon, lat, p, step))
+    norm = c.surrogate_stats(x, y)
+    params = c.surrogate_init(9)
+    c.surrogate_load(params, norm, float("inf"))
+    P = mpt.DeviceParticles.from_host(part, math=1, pingpong=False)
+    fb = torch.zeros(1, dtype=torch.int32, device="cuda")
+    err = torch.empty(n, dtype=torch.float32, device="cuda")
+    step0 = 16
+    c.step_surrogate(P, step0, 8, fb, err)
+    torch.cuda.synchronize()
+    g = P.to_host()
+    assert fb.item() == 0
+    assert np.isfinite(err.cpu().numpy()).all()
+    m = oracle.Met(met3)
+    xr = oracle.stencil81(m, part.lon, part.lat, part.p, step0 * 180.0)
+    d = c.surrogate_forward(torch.from_numpy(xr.astype(np.float32)).cuda()).cpu().numpy().astype(np.float64)
+    kdeg = 180.0 / (np.pi * 6371e3)
+    c0 = np.maximum(np.cos(np.deg2rad(part.lat)), np.cos(np.deg2rad(89.999)))
+    elon, elat, ep = oracle.position(m, part.lon + d[:, 0] * 1e3 * kdeg / c0, part.lat + d[:, 1] * 1e3 * kdeg,
+                                     part.p + d[:, 2])
+    km = oracle.chord_deg(g.lon, g.lat, elon, elat) * np.pi * 6371.0 / 180.0
+    sd = norm.cpu().numpy()[9:12]
+    say(f"[accepted] max position difference {km.max():.3e} km (out std {sd[0]:.2f}, {sd[1]:.2f} km), "
+        f"max |dp| {np.abs(g.p - ep).max():.3e} hPa (out std {sd[2]:.2f})")
+    # Exact up to rounding except where an input lies within rounding of a
+    # bf16 midpoint (GPU FP32 stencil vs oracle FP64 stencil): a wrong row,
+    # feature order or chunk offset moves every parcel of its pass, so the
+    # bulk of each pass is held tight and the rare flips loosely.
+    dp = np.abs(g.p - ep)
+    for lo in range(0, n, 1 << 20):
+        seg = slice(lo, min(n, lo + (1 << 20)))
+        assert np.median(km[seg]) <= 1e-4
+        assert np.percentile(km[seg], 99) <= 1e-3 * max(sd[0], sd[1])
+        assert np.percentile(dp[seg], 99) <= 1e-3 * sd[2]
+    assert km.max() <= 5e-2 * max(sd[0], sd[1])
+    assert dp.max() <= 5e-2 * sd[2]
