@@ -105,10 +105,14 @@ __device__ __forceinline__ f32x4 mlp16(const uint16_t *xs, int ldx, const SurrW 
 // levels around the cell.  The values of one level shift c come out
 // together, in ascending c: sink(c + 1, g) with g[(b+1)*9 + (a+1)*3 + var];
 // the input index of a value is var*27 + (c+1)*9 + (b+1)*3 + (a+1).
-template <class Sink>
-__device__ __forceinline__ void stencil81(const StepArgs &a, const Loc<float> &L, Sink sink) {
+// kTime: the values are interpolated between the time-level pair of L;
+// otherwise f0 is the field already interpolated to the parcel's time (one
+// load per point instead of two, the same values: k_surr_tfield applies the
+// same interpolation).
+template <bool kTime, class Sink>
+__device__ __forceinline__ void stencil81(const StepArgs &a, const Loc<float> &L, const float4 *f0, Sink sink) {
   const float4 *base = reinterpret_cast<const float4 *>(a.met);
-  const float4 *lev0 = base + (int64_t)L.l * a.level_elems;
+  const float4 *lev0 = kTime ? base + (int64_t)L.l * a.level_elems : f0;
   const float4 *lev1 = lev0 + a.level_elems;
   int ic[4], jr[4], kr[4], pb[3], pc[3];
 #pragma unroll
@@ -134,10 +138,17 @@ __device__ __forceinline__ void stencil81(const StepArgs &a, const Loc<float> &L
       float v[4][3];
 #pragma unroll
       for (int qi = 0; qi < 4; ++qi) {
-        const float4 r0 = lev0[r + ic[qi]], r1 = lev1[r + ic[qi]];
-        v[qi][0] = lerp(r0.x, r1.x, L.ft);
-        v[qi][1] = lerp(r0.y, r1.y, L.ft);
-        v[qi][2] = lerp(r0.z, r1.z, L.ft);
+        const float4 r0 = lev0[r + ic[qi]];
+        if constexpr (kTime) {
+          const float4 r1 = lev1[r + ic[qi]];
+          v[qi][0] = lerp(r0.x, r1.x, L.ft);
+          v[qi][1] = lerp(r0.y, r1.y, L.ft);
+          v[qi][2] = lerp(r0.z, r1.z, L.ft);
+        } else {
+          v[qi][0] = r0.x;
+          v[qi][1] = r0.y;
+          v[qi][2] = r0.z;
+        }
       }
 #pragma unroll
       for (int s = 0; s < 3; ++s)
@@ -197,7 +208,7 @@ __global__ __launch_bounds__(256) void k_surr_datagen(const StepArgs a, int64_t 
   Loc<float> L;
   surr_locate(a, lo, la, pp, t0, L);
   float *xr = x + i * kSurrIn;
-  stencil81(a, L, [&](int sc, const float (&g)[27]) {
+  stencil81<true>(a, L, nullptr, [&](int sc, const float (&g)[27]) {
 #pragma unroll
     for (int j = 0; j < 27; ++j) xr[(j % 3) * 27 + sc * 9 + j / 3] = g[j];
   });
@@ -654,8 +665,22 @@ __global__ void k_surr_adam(float *params, const float *grad, float *m, float *v
 // A block of kSurrK steps runs over chunks of parcels in three passes:
 // stencil rows (k_surr_x), MLP (k_surr_mlp), then the consistency estimate
 // and either acceptance (displacement plus the block's turbulent and
-// mesoscale diffusion with the block-start spread) or a place in the list
-// of parcels that take kSurrK plain steps (k_surr_apply).
+// mesoscale diffusion, drawn at once with the block-start spread) or a place
+// in the list of parcels that take kSurrK plain steps (k_surr_apply).
+
+// The FP32 field at time t (all points): F = lerp(level l, level l + 1, ft)
+// per component with the (l, ft) a parcel at time t computes.
+__global__ __launch_bounds__(256) void k_surr_tfield(const StepArgs a, double t, float4 *F) {
+  Loc<float> L;
+  locate_t<float>(a, t, L);
+  const float4 *lev0 = reinterpret_cast<const float4 *>(a.met) + (int64_t)L.l * a.level_elems;
+  const float4 *lev1 = lev0 + a.level_elems;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < a.level_elems;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const float4 r0 = lev0[q], r1 = lev1[q];
+    F[q] = make_float4(lerp(r0.x, r1.x, L.ft), lerp(r0.y, r1.y, L.ft), lerp(r0.z, r1.z, L.ft), 0.0f);
+  }
+}
 
 // Stencil inputs of parcels i0 .. i0 + cnt - 1 at the block's start time,
 // normalized, as bf16 rows of 96 in the MLP's input order; a parcel with a
@@ -665,8 +690,8 @@ __global__ void k_surr_adam(float *params, const float *grad, float *m, float *v
 // coalesced copy.
 constexpr int kRowLd = kSurrInPad / 8 + 1;      // 16-byte units per staged row (padded)
 
-__global__ __launch_bounds__(256) void k_surr_x(const StepArgs a, const SurrW W, int64_t i0, int64_t cnt,
-                                                uint16_t *X) {
+__global__ __launch_bounds__(256) void k_surr_x(const StepArgs a, const SurrW W, const float4 *F,
+                                                int64_t i0, int64_t cnt, uint16_t *X) {
   __shared__ bf16x8 srow[256 * kRowLd];
   const int lb = logical_block((int)blockIdx.x, a.per_xcd);
   if (lb >= a.nblk) return;                       // uniform over the block
@@ -687,7 +712,7 @@ __global__ __launch_bounds__(256) void k_surr_x(const StepArgs a, const SurrW W,
     for (int v = 0; v < 3; ++v) inv[v] = 1.0f / W.norm[3 + v];
     Loc<float> L;
     surr_locate(a, lon, lat, p, a.t_start + (double)a.step0 * a.dt, L);
-    stencil81(a, L, [&](int sc, const float (&g)[27]) {
+    stencil81<false>(a, L, F, [&](int sc, const float (&g)[27]) {
       bf16x8 t[4];
       pack_ktile(g, inv, W.norm, t);
 #pragma unroll
@@ -705,8 +730,9 @@ __global__ __launch_bounds__(256) void k_surr_x(const StepArgs a, const SurrW W,
   }
 }
 
-// Consistency estimate, then acceptance or fallback, for parcels
-// i0 .. i0 + cnt - 1 with predictions Y (4 floats per row).  Every wave
+// Consistency estimate, then acceptance (displacement, then the block's
+// diffusion) or fallback, for parcels i0 .. i0 + cnt - 1 with predictions Y
+// (4 floats per row).  Every wave
 // records the ballot of its parcels that fall back in fb_mask[i / 64]
 // (i0 is a multiple of 64), from which an ordered list is built.
 __global__ __launch_bounds__(256) void k_surr_apply(const StepArgs a, float tau_km, const float *Y,
@@ -771,14 +797,36 @@ __global__ __launch_bounds__(256) void k_surr_apply(const StepArgs a, float tau_
   lat = lat + (double)(dn * 1000.0f * kdeg);
   p = p + (double)dpp;
   position(a, lon, lat, p);
-  for (int s = 0; s < kSurrK; ++s) {
-    const uint32_t step = a.step0 + (uint32_t)s;
-    if (a.flags & kTurb) turb<float>(a, id, step, lon, lat, p);
-    if (meso_on) {
+  // the block's turbulent and mesoscale diffusion, drawn at once from its
+  // distribution with the spread held at its block-start value (normals
+  // of purposes 2, 3, 4 at the block's first step)
+  if (a.flags & (kTurb | kMeso)) {
+    float ex = 0.f, ny = 0.f, dz = 0.f, dpm = 0.f;     // m east, m north, m up; hPa
+    if (a.flags & kTurb) {
       float xi[3];
-      normals3<float>(a.seed, id, step, 1u, xi);
-      meso_apply<float>(a, sg, xi, lon, lat, p, up, vp, wp);
+      normals3<float>(a.seed, id, a.step0, 2u, xi);
+      ex = (float)a.agg_sh * xi[0];
+      ny = (float)a.agg_sh * xi[1];
+      dz = (float)a.agg_sz * xi[2];
     }
+    if (meso_on) {
+      float n1[3], n2[3];
+      normals3<float>(a.seed, id, a.step0, 3u, n1);
+      normals3<float>(a.seed, id, a.step0, 4u, n2);
+      const float A = (float)a.agg_a, rk = (float)a.agg_rk, fdt = (float)a.dt;
+      const float l11 = (float)a.agg_l11, l21 = (float)a.agg_l21, l22 = (float)a.agg_l22;
+      const float cu = (float)a.rs_fh * sg[0], cv = (float)a.rs_fh * sg[1], cw = (float)a.rs_fv * sg[2];
+      ex += fdt * (A * up + cu * l11 * n1[0]);
+      ny += fdt * (A * vp + cv * l11 * n1[1]);
+      dpm = fdt * (A * wp + cw * l11 * n1[2]);
+      up = rk * up + cu * (l21 * n1[0] + l22 * n2[0]);
+      vp = rk * vp + cv * (l21 * n1[1] + l22 * n2[1]);
+      wp = rk * wp + cw * (l21 * n1[2] + l22 * n2[2]);
+    }
+    const float c1 = cos_floor<float>(a, lat);
+    lon = lon + (double)(ex * kdeg / c1);
+    lat = lat + (double)(ny * kdeg);
+    p = p + (double)(-dz * (float)p * (float)(1.0 / kH0) + dpm);
     position(a, lon, lat, p);
   }
   a.lon[i] = lon;
@@ -867,10 +915,15 @@ static StepArgs chunk_args(const StepArgs &a, int64_t cnt) {
   return c;
 }
 
-hipError_t launch_surr_x(const StepArgs &a, const SurrW &W, int64_t i0, int64_t cnt, uint16_t *X,
-                         hipStream_t s) {
+hipError_t launch_surr_tfield(const StepArgs &a, double t, float4 *F, hipStream_t s) {
+  hipLaunchKernelGGL(k_surr_tfield, dim3(4096), dim3(256), 0, s, a, t, F);
+  return hipGetLastError();
+}
+
+hipError_t launch_surr_x(const StepArgs &a, const SurrW &W, const float4 *F, int64_t i0, int64_t cnt,
+                         uint16_t *X, hipStream_t s) {
   const StepArgs c = chunk_args(a, cnt);
-  hipLaunchKernelGGL(k_surr_x, dim3((unsigned)(c.per_xcd * kXcds)), dim3(256), 0, s, c, W, i0, cnt, X);
+  hipLaunchKernelGGL(k_surr_x, dim3((unsigned)(c.per_xcd * kXcds)), dim3(256), 0, s, c, W, F, i0, cnt, X);
   return hipGetLastError();
 }
 

@@ -71,6 +71,11 @@ struct StepArgs {
   // Index-list mode: advance only parcels index[0 .. *index_count).
   const uint32_t *index;
   const uint32_t *index_count;
+  // Diffusion of a k-step surrogate block drawn at once (spread frozen):
+  // turbulence sqrt(k) sig_h, sqrt(k) sig_z; AR(1) sums A = r + ... + r^k,
+  // r^k, and the Cholesky factor (l11, l21, l22) of the covariance of
+  // (sum_j B_j xi_j, sum_j r^(k-1-j) xi_j), B_j = 1 + r + ... + r^(k-1-j).
+  double agg_sh, agg_sz, agg_a, agg_rk, agg_l11, agg_l21, agg_l22;
 };
 
 // Map the hardware block index to a logical block so that each XCD walks a

@@ -110,9 +110,12 @@ hipError_t launch_surr_forward(const SurrW &W, const float *x, int64_t n, uint16
                                int64_t chunk, hipStream_t s);
 // normalized bf16 rows X [n][96] -> Y[row * ldy + 0..2]
 hipError_t launch_surr_mlp(const SurrW &W, const uint16_t *X, int64_t n, float *Y, int ldy, hipStream_t s);
-// stencil rows of parcels i0 .. i0 + cnt - 1 at step a.step0
-hipError_t launch_surr_x(const StepArgs &a, const SurrW &W, int64_t i0, int64_t cnt, uint16_t *X,
-                         hipStream_t s);
+// FP32 field interpolated to time t ([level_elems] float4)
+hipError_t launch_surr_tfield(const StepArgs &a, double t, float4 *F, hipStream_t s);
+// stencil rows of parcels i0 .. i0 + cnt - 1 at step a.step0 from the field
+// F at that step's time
+hipError_t launch_surr_x(const StepArgs &a, const SurrW &W, const float4 *F, int64_t i0, int64_t cnt,
+                         uint16_t *X, hipStream_t s);
 // consistency estimate and acceptance for parcels i0 .. i0 + cnt - 1 (i0 a
 // multiple of 64); fb_mask[i / 64] gets the wave's ballot of parcels that
 // fall back

@@ -41,6 +41,7 @@ struct mpt_ctx {
   uint16_t *s_x;                        // stencil rows of one chunk (bf16 [s_chunk][96])
   float *s_y;                           // predictions of one chunk ([s_chunk][4])
   int64_t s_chunk;
+  float4 *s_f;                          // FP32 field at a surrogate block's start time
   uint64_t *fb_mask;                    // per wave of 64 parcels: ballot of surrogate fallbacks
   uint32_t *fb_off, *fb_sums;           // its prefix sums (+ total) and scan scratch
   float s_tau;
@@ -102,7 +103,7 @@ mpt_status check_params(const mpt_params *p, const mpt_grid *g) {
 
 struct Layout {
   size_t met, scales, plev, inv_dp, lut, release, rank, rel_sorted, step_dev, keys, ranks, hist,
-      block_sums, s_wt, s_wb, s_wi, s_norm, s_bias, s_x, s_y, fb_mask, fb_off, fb_sums, t_xn, t_h, t_dy, t_dh, t_yp, t_grad, t_part, total;
+      block_sums, s_wt, s_wb, s_wi, s_norm, s_bias, s_x, s_y, s_f, fb_mask, fb_off, fb_sums, t_xn, t_h, t_dy, t_dh, t_yp, t_grad, t_part, total;
   uint32_t ntx, nty, ntz, ntiles, nkeys;
   int64_t s_chunk;
 };
@@ -144,6 +145,7 @@ Layout layout(const mpt_grid *g, int64_t n_max) {
   L.s_chunk = surr_chunk(n_max);
   L.s_x = off;        off += align_up(sizeof(uint16_t) * (size_t)L.s_chunk * kSurrInPad);
   L.s_y = off;        off += align_up(sizeof(float) * (size_t)L.s_chunk * 4);
+  L.s_f = off;        off += g->dtype == MPT_DT_F32 ? align_up(npts * 16) : 0;   // surrogate needs F32 fields
   const size_t nw = (size_t)((n_max > 0 ? n_max : 0) + 63) / 64;
   L.fb_mask = off;    off += align_up(sizeof(uint64_t) * nw);
   L.fb_off = off;     off += align_up(sizeof(uint32_t) * (nw + 1));
@@ -194,6 +196,33 @@ void fill_step_args(const mpt_ctx *c, const mpt_particles *P, uint32_t step0, in
   a.r_ar = r;
   a.rs_fh = rs * q.meso_fh;
   a.rs_fv = rs * q.meso_fv;
+  {
+    // block aggregates of kSurrK steps (surrogate acceptance)
+    const int K = kSurrK;
+    double A = 0.0, rk = 1.0, s11 = 0.0, s22 = 0.0, s12 = 0.0;
+    for (int m = 1; m <= K; ++m) {
+      rk *= r;
+      A += rk;
+    }
+    for (int jj = 0; jj < K; ++jj) {
+      double B = 0.0, pw = 1.0;
+      for (int m = 0; m <= K - 1 - jj; ++m) {
+        B += pw;
+        pw *= r;
+      }
+      const double e = pow(r, K - 1 - jj);
+      s11 += B * B;
+      s22 += e * e;
+      s12 += B * e;
+    }
+    a.agg_sh = sqrt((double)K) * a.sig_h;
+    a.agg_sz = sqrt((double)K) * a.sig_z;
+    a.agg_a = A;
+    a.agg_rk = rk;
+    a.agg_l11 = sqrt(s11);
+    a.agg_l21 = s12 / a.agg_l11;
+    a.agg_l22 = sqrt(fmax(s22 - a.agg_l21 * a.agg_l21, 0.0));
+  }
   a.cos_cap = cos(89.999 * kPi / 180.0);
   a.seed = q.seed;
   a.step0 = step0;
@@ -441,6 +470,7 @@ mpt_status mpt_create(const mpt_grid *grid, const mpt_params *params, int64_t n_
   c->s_x = reinterpret_cast<uint16_t *>(ws + L.s_x);
   c->s_y = reinterpret_cast<float *>(ws + L.s_y);
   c->s_chunk = L.s_chunk;
+  c->s_f = reinterpret_cast<float4 *>(ws + L.s_f);
   c->fb_mask = reinterpret_cast<uint64_t *>(ws + L.fb_mask);
   c->fb_off = reinterpret_cast<uint32_t *>(ws + L.fb_off);
   c->fb_sums = reinterpret_cast<uint32_t *>(ws + L.fb_sums);
@@ -787,9 +817,11 @@ mpt_status mpt_step_surrogate(mpt_ctx *c, mpt_particles *P, uint32_t step0, int3
     }
     StepArgs a;
     fill_step_args(c, P, (uint32_t)b0, kSurrK, c->params.flags, a);
+    if (launch_surr_tfield(a, c->params.t_start + (double)b0 * c->params.dt, c->s_f, s) != hipSuccess)
+      return MPT_ERR_HIP;
     for (int64_t i0 = 0; i0 < P->n; i0 += c->s_chunk) {
       const int64_t cnt = P->n - i0 < c->s_chunk ? P->n - i0 : c->s_chunk;
-      if (launch_surr_x(a, W, i0, cnt, c->s_x, s) != hipSuccess ||
+      if (launch_surr_x(a, W, c->s_f, i0, cnt, c->s_x, s) != hipSuccess ||
           launch_surr_mlp(W, c->s_x, cnt, c->s_y, 4, s) != hipSuccess ||
           launch_surr_apply(a, c->s_tau, c->s_y, i0, cnt, fallbacks, err_out, c->fb_mask, s) != hipSuccess)
         return MPT_ERR_HIP;

@@ -203,3 +203,68 @@ def test_accepted_block_moves_by_the_forward_of_the_stencil(mpt, met3, n):
         assert np.percentile(dp[seg], 99) <= 1e-3 * sd[2]
     assert km.max() <= 5e-2 * max(sd[0], sd[1])
     assert dp.max() <= 5e-2 * sd[2]
+
+
+@pytest.mark.parametrize("turb", [True, False])
+def test_block_diffusion_matches_plain_statistics(mpt, met3, turb):
+    """An accepted block draws its turbulent and mesoscale diffusion at once
+    (spread held at its block-start value).  With a zero displacement (zero
+    weights, zero output mean, tau = inf) it must reproduce the statistics of
+    8 plain diffusion steps from the same state: displacement variances,
+    their regression on the start perturbation u'_0 (dt (r + ... + r^8)),
+    and the variance and regression (r^8) of the end perturbation.  With
+    2e5 parcels the sampling error of a variance is near 0.3 %; regressions
+    are held to six standard errors (the mesoscale-only case makes the
+    vertical one sharp)."""
+    import torch
+    n = 200_000
+    flags = (mpt.TURB if turb else 0) | mpt.MESO
+    part = inputs.make_particles(n, 63)
+    c = mpt.Context(met3, mpt.make_params(math=1, sort_interval=0, flags=flags), n_max=n)
+    c.upload_met(met3)
+    P = mpt.DeviceParticles.from_host(part, math=1, pingpong=False)
+    c.step(P, 0, 16)
+    torch.cuda.synchronize()
+    h16 = P.to_host()
+    c.step(P, 16, 8)
+    torch.cuda.synchronize()
+    hp = P.to_host()
+    s = mpt.Context(met3, mpt.make_params(math=1, sort_interval=0, flags=mpt.ADVECT | flags), n_max=n)
+    s.upload_met(met3)
+    params = torch.zeros(mpt.SURR_NPARAM, dtype=torch.float32, device="cuda")
+    norm = torch.tensor([0, 0, 0, 1, 1, 1, 0, 0, 0, 1, 1, 1], dtype=torch.float32, device="cuda")
+    s.surrogate_load(params, norm, float("inf"))
+    S = mpt.DeviceParticles.from_host(h16, math=1, pingpong=False)
+    fb = torch.zeros(1, dtype=torch.int32, device="cuda")
+    s.step_surrogate(S, 16, 8, fb)
+    torch.cuda.synchronize()
+    hs = S.to_host()
+    assert fb.item() == 0
+    m = np.abs(h16.lat) < 75.0
+    km = np.pi * 6371e3 / 180.0
+
+    def moves(h):
+        dl = (h.lon - h16.lon + 540.0) % 360.0 - 180.0
+        return (dl * np.cos(np.deg2rad(h16.lat)) * km)[m], ((h.lat - h16.lat) * km)[m], (h.p - h16.p)[m]
+
+    def fit(y, x):                     # slope and its standard error
+        b = np.cov(y, x)[0, 1] / np.var(x)
+        res = y - y.mean() - b * (x - x.mean())
+        return b, res.std() / (x.std() * np.sqrt(len(x)))
+
+    def close(fa, fb_):
+        return abs(fa[0] - fb_[0]) <= 6.0 * np.hypot(fa[1], fb_[1]) + 0.02 * abs(fa[0])
+
+    u0 = (h16.up[m], h16.vp[m], h16.wp[m])
+    for name, hh in (("plain", hp), ("block", hs)):
+        say(f"[block diffusion turb={turb}] {name}: std east {moves(hh)[0].std():.1f} m, north "
+            f"{moves(hh)[1].std():.1f} m, dp {moves(hh)[2].std():.3e} hPa, slope dp/w'0 "
+            f"{fit(moves(hh)[2], u0[2])[0]:.1f} s, u'8/u'0 {fit(hh.up[m], u0[0])[0]:.4f}")
+    for q in range(3):
+        a, b = moves(hp)[q], moves(hs)[q]
+        assert abs(b.var() / a.var() - 1.0) < 0.05
+        assert abs(b.mean()) < 0.02 * b.std()
+        assert close(fit(a, u0[q]), fit(b, u0[q]))
+        ep, es = (hp.up, hp.vp, hp.wp)[q][m], (hs.up, hs.vp, hs.wp)[q][m]
+        assert abs(es.var() / ep.var() - 1.0) < 0.05
+        assert close(fit(ep, u0[q]), fit(es, u0[q]))
