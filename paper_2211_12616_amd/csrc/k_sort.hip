@@ -11,9 +11,10 @@ namespace mpt {
 constexpr int kScanChunk = 1024;   // entries per scan block (256 threads x 4)
 
 // For lanes holding `key` (valid lanes form a prefix of the wave), add the
-// length of each run of equal keys to counters[key] once and return, for
-// every lane, the old counter value plus the lane's rank inside its run.
-__device__ __forceinline__ uint32_t wave_run_add(uint32_t *counters, uint32_t key, bool valid) {
+// length of each run of equal keys to the key's counter *ctr once and
+// return, for every lane, the old counter value plus the lane's rank inside
+// its run.
+__device__ __forceinline__ uint32_t wave_run_add(uint32_t *ctr, uint32_t key, bool valid) {
   const int lane = (int)__lane_id();
   const uint32_t prev = __shfl_up(key, 1);
   const bool head = valid && (lane == 0 || prev != key);
@@ -25,17 +26,21 @@ __device__ __forceinline__ uint32_t wave_run_add(uint32_t *counters, uint32_t ke
   const uint64_t above = heads & (myhead == 63 ? 0ull : ~((2ull << myhead) - 1ull));
   const int endl = above ? __ffsll((long long)above) - 1 : 64 - __clzll((long long)valids);
   uint32_t base = 0;
-  if (head) base = atomicAdd(&counters[key], (uint32_t)(endl - myhead));
+  if (head) base = atomicAdd(ctr, (uint32_t)(endl - myhead));
   base = __shfl(base, myhead);
   return base + (uint32_t)(lane - myhead);
 }
 
+// counts in key order from the spread counters
+__global__ void k_unspread(const uint32_t *spread, uint32_t s, uint32_t nkeys, uint32_t *hist) {
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < nkeys) hist[k] = spread[(k & 15u) * s + (k >> 4)];
+}
+
+// One parcel per thread.  The level table and levels are read from global
+// memory (cache resident): staging them in LDS per block would cost more
+// than the parcel data itself, as each parcel needs one table entry.
 __global__ __launch_bounds__(kBlock) void k_sort_keys(const SortArgs a) {
-  __shared__ double s_plev[kMaxLevels];
-  __shared__ uint16_t s_lut[kLutBins];
-  for (int q = threadIdx.x; q < a.nz; q += kBlock) s_plev[q] = a.plev[q];
-  for (int q = threadIdx.x; q < kLutBins; q += kBlock) s_lut[q] = a.lut[q];
-  __syncthreads();
   const int lb = logical_block((int)blockIdx.x, a.per_xcd);
   if (lb >= a.nblk) return;
   const int64_t i = (int64_t)lb * kBlock + threadIdx.x;
@@ -59,13 +64,15 @@ __global__ __launch_bounds__(kBlock) void k_sort_keys(const SortArgs a) {
       const double pc = fmin(fmax(p, a.p_top), a.p_bot);
       int b = (int)((__log2f((float)pc) - a.lut_lo) * a.lut_scale);
       b = min(max(b, 0), kLutBins - 1);
-      int k = s_lut[b];
-      while (k < a.nz - 2 && s_plev[k + 1] >= pc) ++k;
-      while (k > 0 && s_plev[k] < pc) --k;
+      int k = a.lut[b];
+      while (k < a.nz - 2 && a.plev[k + 1] >= pc) ++k;
+      while (k > 0 && a.plev[k] < pc) --k;
       key = ((uint32_t)(k >> 2) * a.nty + (uint32_t)(j >> 3)) * a.ntx + (uint32_t)(i0 >> 3);
     }
   }
-  const uint32_t rank = wave_run_add(a.hist, key, valid);
+  // counters of consecutive keys sit spread_s apart: nearly sorted parcels
+  // bump consecutive keys, and atomics on one cache line queue up
+  const uint32_t rank = wave_run_add(a.spread + (key & 15u) * a.spread_s + (key >> 4), key, valid);
   if (valid) {
     a.keys[i] = key;
     a.ranks[i] = rank;
@@ -170,10 +177,12 @@ hipError_t launch_scan_u32(uint32_t *data, uint32_t n, uint32_t *block_sums, hip
 
 hipError_t launch_sort(const SortArgs &sa, const ScatterArgs &xa, hipStream_t stream) {
   const uint32_t nb = (uint32_t)scan_block_sums_len(sa.nkeys);
-  unsigned fill_grid = (sa.nkeys + 255) / 256;
+  unsigned fill_grid = (16u * sa.spread_s + 255) / 256;
   if (fill_grid > 4096) fill_grid = 4096;
-  hipLaunchKernelGGL(k_fill_u32, dim3(fill_grid), dim3(256), 0, stream, sa.hist, sa.nkeys);
+  hipLaunchKernelGGL(k_fill_u32, dim3(fill_grid), dim3(256), 0, stream, sa.spread, 16u * sa.spread_s);
   hipLaunchKernelGGL(k_sort_keys, dim3((unsigned)(sa.per_xcd * kXcds)), dim3(kBlock), 0, stream, sa);
+  hipLaunchKernelGGL(k_unspread, dim3((sa.nkeys + 255) / 256), dim3(256), 0, stream, sa.spread, sa.spread_s,
+                     sa.nkeys, sa.hist);
   hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(256), 0, stream, sa.hist, sa.nkeys, sa.block_sums);
   hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(256), 0, stream, sa.block_sums, nb);
   hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(256), 0, stream, sa.hist, sa.nkeys, sa.block_sums);

@@ -39,7 +39,10 @@ struct SortArgs {
   const uint32_t *step_dev;
   uint32_t *keys;
   uint32_t *ranks;                 // rank of the parcel among its key's parcels
-  uint32_t *hist;                  // nkeys counters, then scanned in place
+  uint32_t *hist;                  // nkeys counts in key order, then scanned in place
+  uint32_t *spread;                // the counters while keys are counted: key k at
+                                   // (k % 16) * spread_s + k / 16
+  uint32_t spread_s;               // ceil(nkeys / 16)
   uint32_t *block_sums;
   int nblk, per_xcd;
 };

@@ -29,7 +29,7 @@ struct mpt_ctx {
   int32_t *rank;          // [kMaxScen] rank of the scenario in release order
   int32_t *rel_sorted;    // [kMaxScen] release steps in ascending order
   uint32_t *step_dev;     // step index read by graph-replayed kernels
-  uint32_t *keys, *ranks, *hist, *block_sums;
+  uint32_t *keys, *ranks, *hist, *spread, *block_sums;
   uint32_t ntx, nty, ntz, ntiles, nkeys;
   // host state
   double plev_h[kMaxLevels];
@@ -102,7 +102,7 @@ mpt_status check_params(const mpt_params *p, const mpt_grid *g) {
 }
 
 struct Layout {
-  size_t met, scales, plev, inv_dp, lut, release, rank, rel_sorted, step_dev, keys, ranks, hist,
+  size_t met, scales, plev, inv_dp, lut, release, rank, rel_sorted, step_dev, keys, ranks, hist, spread,
       block_sums, s_wt, s_wb, s_wi, s_norm, s_bias, s_x, s_y, s_f, fb_mask, fb_off, fb_sums, t_xn, t_h, t_dy, t_dh, t_yp, t_grad, t_part, total;
   uint32_t ntx, nty, ntz, ntiles, nkeys;
   int64_t s_chunk;
@@ -136,6 +136,7 @@ Layout layout(const mpt_grid *g, int64_t n_max) {
   L.keys = off;       off += align_up(sizeof(uint32_t) * (size_t)(n_max > 0 ? n_max : 0));
   L.ranks = off;      off += align_up(sizeof(uint32_t) * (size_t)(n_max > 0 ? n_max : 0));
   L.hist = off;       off += align_up(sizeof(uint32_t) * L.nkeys);
+  L.spread = off;     off += align_up(sizeof(uint32_t) * 16 * ((L.nkeys + 15) / 16));
   L.block_sums = off; off += align_up(sizeof(uint32_t) * scan_block_sums_len(L.nkeys));
   L.s_wt = off;       off += align_up(sizeof(uint16_t) * kWtSize);
   L.s_wb = off;       off += align_up(sizeof(uint16_t) * kWbSize);
@@ -309,6 +310,7 @@ mpt_status do_sort(mpt_ctx *c, mpt_particles *P, uint32_t step, bool dev_step, h
   sa.step = step;
   sa.step_dev = dev_step ? c->step_dev : nullptr;
   sa.keys = c->keys; sa.ranks = c->ranks; sa.hist = c->hist; sa.block_sums = c->block_sums;
+  sa.spread = c->spread; sa.spread_s = (c->nkeys + 15) / 16;
   const int64_t nblk = (P->n + kBlock - 1) / kBlock;
   sa.nblk = (int)nblk;
   sa.per_xcd = (int)((nblk + kXcds - 1) / kXcds);
@@ -460,6 +462,7 @@ mpt_status mpt_create(const mpt_grid *grid, const mpt_params *params, int64_t n_
   c->keys = reinterpret_cast<uint32_t *>(ws + L.keys);
   c->ranks = reinterpret_cast<uint32_t *>(ws + L.ranks);
   c->hist = reinterpret_cast<uint32_t *>(ws + L.hist);
+  c->spread = reinterpret_cast<uint32_t *>(ws + L.spread);
   c->block_sums = reinterpret_cast<uint32_t *>(ws + L.block_sums);
   c->ntx = L.ntx; c->nty = L.nty; c->ntz = L.ntz; c->ntiles = L.ntiles; c->nkeys = L.nkeys;
   c->s_wt = reinterpret_cast<uint16_t *>(ws + L.s_wt);
