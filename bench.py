@@ -29,15 +29,16 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
 # Per-unit figures of the step kernel, from rocprofv3 --pmc runs of this
-# workload (profiles/k_step_1e8_0p3deg.md): FP64 FLOP per parcel-step =
-# 64 x SQ_INSTS_VALU_FLOPS_FP64 per launch / parcel-steps per launch (F64 form);
-# FP32 likewise from SQ_INSTS_VALU_FLOPS_FP32 (F32 form).  HBM bytes per
-# 10-step launch of 1e8 parcels = 2 x FETCH_SIZE + WRITE_SIZE (KiB x 1024; a
-# 1 GiB copy reads FETCH_SIZE = 512 MiB and WRITE_SIZE = 1 GiB).
-FP64_FLOP_PER_PS = 1429.0
-FP32_FLOP_PER_PS = 669.0
-TRAFFIC_BYTES_PER_LAUNCH = {"f64": 2 * 3.689e6 * 1024 + 4.949e6 * 1024,
-                            "f32": 2 * 3.087e6 * 1024 + 3.516e6 * 1024}
+# workload (profiles/k_step_<form>_1e8_0p3deg.md): FLOP per parcel-step =
+# 64 x SQ_INSTS_VALU_FLOPS_FP64 (F64 form) or _FP32 (the FP32-arithmetic
+# forms) per launch / parcel-steps per launch; the FP16 form does the same
+# arithmetic as BF16 (decode, scale, interpolate).  HBM bytes per 10-step
+# launch of 1e8 parcels = 2 x FETCH_SIZE + WRITE_SIZE (KiB x 1024; a 1 GiB
+# copy reads FETCH_SIZE = 512 MiB and WRITE_SIZE = 1 GiB).
+FLOP_PER_PS = {"f64": 1169.0, "f32": 669.0, "bf16": 813.0, "f16": 813.0}
+TRAFFIC_BYTES_PER_LAUNCH = {"f64": (2 * 3.685e6 + 4.688e6) * 1024,
+                            "f32": (2 * 3.090e6 + 3.516e6) * 1024,
+                            "bf16": (2 * 2.541e6 + 3.516e6) * 1024}
 METRIC = "particle-steps/s (advect+diffuse, 1e8 particles, 0.3° grid); surrogate vs plain"
 FORMS = {"f64": (0, 0), "f32": (1, 0), "bf16": (1, 1), "f16": (1, 2)}   # (math, dtype)
 
@@ -384,7 +385,7 @@ def main():
     avg_ms = float(np.mean(durations))
     # the dominant kernel is bound by its vector ALU (FP64 for the F64 form):
     # algorithmic FLOP per launch = FLOP per parcel-step x parcel-steps
-    flop_ps = FP64_FLOP_PER_PS if math_ == 0 else FP32_FLOP_PER_PS
+    flop_ps = FLOP_PER_PS[args.form]
     peak = FP64_PEAK_TFLOPS if math_ == 0 else FP32_PEAK_TFLOPS
     achieved_tf = float(np.mean([flop_ps * n * k / (d * 1e-3) / 1e12
                                  for k, d in zip(main_r["step_steps"], durations)]))

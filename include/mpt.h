@@ -255,8 +255,10 @@ mpt_status mpt_surrogate_forward(mpt_ctx *ctx, int64_t n, const float *x, float 
  * advection, estimate its error as the distance [km] between the
  * prediction and MPT_SURR_K*dt times the wind at the predicted midpoint; if
  * at most tau, apply it plus the block's turbulent and mesoscale diffusion
- * (per-step random numbers as in mpt_step, mesoscale spread of the
- * block-start cell); otherwise run MPT_SURR_K plain steps.  Adds the number
+ * drawn at once from their distribution over MPT_SURR_K steps (mesoscale
+ * spread of the block-start cell; Philox purposes 2, 3, 4 at the block's
+ * first step, so the noise is not the plain steps' draws); otherwise run
+ * MPT_SURR_K plain steps (those parcels, in increasing index order).  Adds the number
  * of parcel-blocks that fell back to *fallbacks (device uint32).  err_out
  * (device, n floats, or NULL) receives each parcel's error estimate of the
  * last block (for calibrating tau; needs sort_interval == 0).  Needs
