@@ -69,6 +69,8 @@ def parse():
                     help="also run the batched release workload (16 scenarios, 480 steps)")
     ap.add_argument("--surrogate", action="store_true",
                     help="also train and run the learned 8-step surrogate (480 steps)")
+    ap.add_argument("--grid-output", action="store_true",
+                    help="also time the gridded output on 1e8 parcels (random and sorted order)")
     ap.add_argument("--surr-train", type=float, default=5e7, help="surrogate training segments")
     ap.add_argument("--surr-epochs", type=int, default=2)
     ap.add_argument("--surr-bound-km", type=float, default=1.0,
@@ -254,6 +256,51 @@ def run_surrogate(met, mpt, inputs, torch, args, nsteps=480):
                             "error_vs_plain_km": {"p50": float(np.percentile(da, 50)),
                                                   "p99": float(np.percentile(da, 99)),
                                                   "max": float(da.max())}}}
+
+
+def run_grid_output(met, mpt, inputs, torch, args, reps=5):
+    """Gridded output of 1e8 parcels on a 1 x 1 deg grid with 18 layers
+    (1000 .. 100 hPa): per call, count and FP64 mass sum per box plus the
+    mass mixing ratio.  Timed with HIP events on the library's stream, for
+    parcels in random order and after a sort by tile."""
+    n = int(args.n)
+    pe = np.linspace(1000.0, 100.0, 19)
+    nx, ny = 360, 180
+    ctx = mpt.Context(met, mpt.make_params(math=1, sort_interval=10), n_max=n)
+    ctx.upload_met(met)
+    ctx.set_outgrid(nx, ny, -0.5, -90.0, 1.0, pe)
+    part = inputs.make_particles(n, 23)
+    P = mpt.DeviceParticles.from_host(part, math=1)
+    mass = torch.rand(n, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(5))
+    inside = int(((P.p <= 1000.0) & (P.p > 100.0)).sum().item())
+    out = {"workload": f"gridded output, {n} parcels, 360x180x18 boxes (1 deg, 1000..100 hPa), FP64 masses",
+           "boxes": nx * ny * (len(pe) - 1)}
+    nbox = nx * ny * (len(pe) - 1)
+    bytes_call = n * (3 * 8 + 8) + nbox * (4 + 8) * 2 + nbox * 8
+    for label in ("random", "sorted"):
+        if label == "sorted":
+            ctx.sort(P)
+        ctx.grid_output(P, mass)
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            counts, msum, mmr = ctx.grid_output(P, mass)
+            b.record()
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b))
+        got = int(counts.sum().item())
+        if got != inside:
+            raise RuntimeError(f"grid output lost parcels: {got} != {inside}")
+        t = float(np.median(ms))
+        out[label] = {"ms_per_call": t, "parcels_per_s": n / (t * 1e-3),
+                      "algorithmic_GBps": bytes_call / (t * 1e-3) / 1e9,
+                      "hbm_frac": bytes_call / (t * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    out["algorithmic_bytes_per_call"] = bytes_call
+    del P, ctx
+    torch.cuda.empty_cache()
+    return out
 
 
 def _chord_km(lon1, lat1, lon2, lat2):
@@ -451,6 +498,10 @@ def main():
     if args.scenarios:
         log("scenario workload")
         extras["scenarios"] = run_scenarios(met, mpt, inputs, torch)
+        torch.cuda.empty_cache()
+    if args.grid_output:
+        log("gridded output")
+        extras["grid_output"] = run_grid_output(met, mpt, inputs, torch, args)
         torch.cuda.empty_cache()
     if args.surrogate:
         log("surrogate workload")

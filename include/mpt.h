@@ -207,6 +207,41 @@ mpt_status mpt_step(mpt_ctx *ctx, mpt_particles *particles, uint32_t step0, int3
 mpt_status mpt_step_graph(mpt_ctx *ctx, mpt_particles *particles, uint32_t step0, int32_t nsteps,
                           void *hip_stream);
 
+/* ---- Gridded output (write_grid, Sec. 3.3: the output functions write
+ * parcel data, gridded data and ensemble data).  The paper names the
+ * function only; the reading here: a regular grid of nx x ny boxes in lon x
+ * lat and nz pressure layers; box (k, j, i) at index (k*ny + j)*nx + i.  A
+ * parcel with finite position belongs to
+ *   i = floor((lon - lon0) / dlon) mod nx   (FP64 division, lon in [0, 360)),
+ *   j = floor((lat - lat0) / dlat), kept if 0 <= j < ny, with j = ny - 1 for
+ *       lat == lat0 + ny*dlat (a box's north edge belongs to it only at the
+ *       grid's last row),
+ *   k with pedges[k] >= p > pedges[k + 1], kept if it exists;
+ * others are not counted.  Per box: the parcel count, the sum of the
+ * parcels' masses, and the mass mixing ratio = mass / air mass of the box,
+ * air mass = R^2 dlon_rad (sin lat_north - sin lat_south) (pedges[k] -
+ * pedges[k+1]) * 100 / g, R = 6371 km, g = 9.80665 m/s^2. */
+enum { MPT_MAX_OUT_LEVELS = 512 };
+typedef struct {
+  int32_t nx, ny, nz;            /* boxes; nz <= MPT_MAX_OUT_LEVELS */
+  double lon0, dlon;             /* nx * dlon == 360 (global in longitude) */
+  double lat0, dlat;             /* -90 <= lat0, lat0 + ny * dlat <= 90, dlat > 0 */
+  const double *pedges;          /* host, nz + 1 layer edges [hPa], strictly decreasing; copied */
+} mpt_outgrid;
+
+/* Set the output grid (host struct and edges copied; synchronizes the
+ * stream).  MPT_ERR_ARG for a grid that breaks the rules above. */
+mpt_status mpt_set_outgrid(mpt_ctx *ctx, const mpt_outgrid *grid, void *hip_stream);
+
+/* Count and mass per box of the particles (primary set) into counts
+ * (device, nx*ny*nz uint32) and mass_sum (device, nx*ny*nz double), both
+ * overwritten; mass (device, n double, or NULL for unit masses); mmr
+ * (device, nx*ny*nz double, or NULL) receives mass_sum / air mass.  Sums
+ * of masses are accumulated in FP64 in no fixed order.  MPT_ERR_STATE
+ * before mpt_set_outgrid. */
+mpt_status mpt_grid_output(mpt_ctx *ctx, const mpt_particles *particles, const double *mass,
+                           uint32_t *counts, double *mass_sum, double *mmr, void *hip_stream);
+
 /* ---- Learned k-step advection surrogate (a project addition: the paper has
  * no counterpart).  A ReLU MLP 81 -> 128 -> 128 -> 128 -> 3 on bf16 MFMA
  * with FP32 accumulation predicts the MPT_SURR_K-step displacement of plain

@@ -68,6 +68,9 @@ def lib() -> ctypes.CDLL:
         L.orc_cell_sigma_many.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.c_double, P]
         L.orc_locate_many.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.c_double, P, P]
         L.orc_position_many.argtypes = [P, ctypes.c_int64, P, P, P]
+        L.orc_grid_output.argtypes = [ctypes.c_int64, P, P, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                      P, P, P, P]
         L.orc_philox_many.argtypes = [ctypes.c_int64, P, P, P]
         L.orc_normals_many.argtypes = [ctypes.c_uint64, ctypes.c_int64, P, ctypes.c_uint32,
                                        ctypes.c_uint32, P]
@@ -187,6 +190,22 @@ def tile_keys(m: Met, lon, lat, p) -> np.ndarray:
     out = np.empty(len(lon), np.uint32)
     lib().orc_tile_keys(m.ref, len(lon), _ptr(lon), _ptr(lat), _ptr(p), _ptr(out))
     return out
+
+
+def grid_output(lon, lat, p, mass, nx: int, ny: int, lon0: float, lat0: float, dlat: float,
+                pedges) -> tuple:
+    """Gridded output: (counts, mass sums, mass mixing ratios), each [nz, ny, nx]."""
+    lon, lat, p = (np.ascontiguousarray(a, np.float64) for a in (lon, lat, p))
+    pe = np.ascontiguousarray(pedges, np.float64)
+    nz = len(pe) - 1
+    m = None if mass is None else np.ascontiguousarray(mass, np.float64)
+    counts = np.empty((nz, ny, nx), np.uint32)
+    msum = np.empty((nz, ny, nx), np.float64)
+    mmr = np.empty((nz, ny, nx), np.float64)
+    lib().orc_grid_output(len(lon), _ptr(lon), _ptr(lat), _ptr(p), _ptr(m) if m is not None else None,
+                          nx, ny, nz, lon0, 360.0 / nx, lat0, dlat, _ptr(pe), _ptr(counts), _ptr(msum),
+                          _ptr(mmr))
+    return counts, msum, mmr
 
 
 def stencil81(m: Met, lon, lat, p, t: float) -> np.ndarray:

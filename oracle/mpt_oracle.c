@@ -534,4 +534,53 @@ void orc_displacement_many(const orc_met *m, const orc_ctl *c, int64_t n, const 
     }
 }
 
+/* ---- gridded output (write_grid, Sec. 3.3; a reading: the paper names the
+ * function only).  Box (k, j, i) of a regular grid, index (k*ny + j)*nx + i:
+ *   i = floor((lon - lon0) / dlon) mod nx,
+ *   j = floor((lat - lat0) / dlat) if 0 <= j < ny; j = ny - 1 when lat equals
+ *       the grid's north edge lat0 + ny*dlat; otherwise outside,
+ *   k: pedges[k] >= p > pedges[k+1] (edges decreasing), found by walking the
+ *       layers; outside if there is none.
+ * counts[b] = number of parcels in b, msum[b] = sum of their masses (1 each
+ * when mass is NULL), mmr[b] = msum[b] / air mass of b, air mass =
+ * R^2 * dlon[rad] * (sin(lat north) - sin(lat south)) * dp[Pa] / g. */
+#define ORC_G 9.80665
+void orc_grid_output(int64_t n, const double *lon, const double *lat, const double *p,
+                     const double *mass, int nx, int ny, int nz, double lon0, double dlon,
+                     double lat0, double dlat, const double *pedges, uint32_t *counts,
+                     double *msum, double *mmr)
+{
+  const int64_t nbox = (int64_t)nx * ny * nz;
+  for (int64_t b = 0; b < nbox; ++b) { counts[b] = 0; msum[b] = 0.0; }
+  for (int64_t q = 0; q < n; ++q) {
+    if (!isfinite(lon[q]) || !isfinite(lat[q]) || !isfinite(p[q])) continue;
+    int64_t i = (int64_t)floor((lon[q] - lon0) / dlon) % nx;
+    if (i < 0) i += nx;
+    const double y = floor((lat[q] - lat0) / dlat);
+    int64_t j;
+    if (y < 0.0) continue;
+    if (y >= (double)ny) {
+      if (lat[q] != lat0 + ny * dlat) continue;
+      j = ny - 1;
+    } else {
+      j = (int64_t)y;
+    }
+    int k = -1;
+    for (int kk = 0; kk < nz; ++kk)
+      if (pedges[kk] >= p[q] && p[q] > pedges[kk + 1]) { k = kk; break; }
+    if (k < 0) continue;
+    const int64_t b = ((int64_t)k * ny + j) * nx + i;
+    counts[b] += 1;
+    msum[b] += mass ? mass[q] : 1.0;
+  }
+  for (int64_t b = 0; b < nbox; ++b) {
+    const int64_t k = b / ((int64_t)nx * ny), j = (b / nx) % ny;
+    const double s0 = sin((lat0 + j * dlat) * ORC_PI / 180.0);
+    const double s1 = sin((lat0 + (j + 1) * dlat) * ORC_PI / 180.0);
+    const double air = ORC_R_EARTH * ORC_R_EARTH * (dlon * ORC_PI / 180.0) * (s1 - s0) *
+                       (pedges[k] - pedges[k + 1]) * 100.0 / ORC_G;
+    mmr[b] = msum[b] / air;
+  }
+}
+
 int orc_max_threads(void) { return omp_get_max_threads(); }

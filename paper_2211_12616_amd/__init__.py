@@ -45,6 +45,12 @@ class Grid(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
 
+class OutGrid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("lon0", ctypes.c_double), ("dlon", ctypes.c_double), ("lat0", ctypes.c_double),
+                ("dlat", ctypes.c_double), ("pedges", ctypes.c_void_p)]
+
+
 class Params(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("t_start", ctypes.c_double),
                 ("turb_dx", ctypes.c_double), ("turb_dz", ctypes.c_double),
@@ -93,6 +99,8 @@ def lib() -> ctypes.CDLL:
         L.mpt_surrogate_load.argtypes = [P, P, P, ctypes.c_float, P]
         L.mpt_surrogate_forward.argtypes = [P, ctypes.c_int64, P, P, P]
         L.mpt_step_surrogate.argtypes = [P, P, ctypes.c_uint32, ctypes.c_int32, P, P, P]
+        L.mpt_set_outgrid.argtypes = [P, P, P]
+        L.mpt_grid_output.argtypes = [P, P, P, P, P, P, P]
         L.mpt_destroy.argtypes = [P]
         L.mpt_status_string.argtypes = [S]
         L.mpt_status_string.restype = ctypes.c_char_p
@@ -100,7 +108,8 @@ def lib() -> ctypes.CDLL:
                    "mpt_advect", "mpt_diffuse", "mpt_sort_particles", "mpt_step", "mpt_step_graph",
                    "mpt_destroy", "mpt_surrogate_datagen", "mpt_surrogate_stats",
                    "mpt_surrogate_init", "mpt_surrogate_train_step", "mpt_surrogate_grad",
-                   "mpt_surrogate_load", "mpt_surrogate_forward", "mpt_step_surrogate"):
+                   "mpt_surrogate_load", "mpt_surrogate_forward", "mpt_step_surrogate",
+                   "mpt_set_outgrid", "mpt_grid_output"):
             getattr(L, fn).restype = S
         _lib = L
     return _lib
@@ -112,7 +121,8 @@ def exported_symbols():
             "mpt_sort_particles", "mpt_step", "mpt_step_graph", "mpt_destroy",
             "mpt_status_string", "mpt_surrogate_datagen", "mpt_surrogate_stats",
             "mpt_surrogate_init", "mpt_surrogate_train_step", "mpt_surrogate_grad",
-            "mpt_surrogate_load", "mpt_surrogate_forward", "mpt_step_surrogate"]
+            "mpt_surrogate_load", "mpt_surrogate_forward", "mpt_step_surrogate",
+            "mpt_set_outgrid", "mpt_grid_output"]
 
 SURR_K, SURR_NIN, SURR_NOUT, SURR_NPARAM, SURR_MAX_BATCH = 8, 81, 3, 47504, 8192
 
@@ -278,6 +288,29 @@ class Context:
         rel = np.ascontiguousarray(release_step, np.int32)
         _check("mpt_set_release", lib().mpt_set_release(self.h, len(rel), rel.ctypes.data,
                                                         _stream_handle(stream)))
+
+    def set_outgrid(self, nx: int, ny: int, lon0: float, lat0: float, dlat: float,
+                    pedges: np.ndarray, stream=None):
+        """Output grid: nx boxes over 360 deg of longitude from lon0, ny rows of
+        dlat from lat0, layers between the decreasing pressure edges [hPa]."""
+        pe = np.ascontiguousarray(pedges, np.float64)
+        g = OutGrid(nx=nx, ny=ny, nz=len(pe) - 1, lon0=lon0, dlon=360.0 / nx, lat0=lat0, dlat=dlat,
+                    pedges=pe.ctypes.data)
+        _check("mpt_set_outgrid", lib().mpt_set_outgrid(self.h, ctypes.byref(g), _stream_handle(stream)))
+        self._outgrid = (nx, ny, len(pe) - 1)
+
+    def grid_output(self, P: DeviceParticles, mass=None, mmr: bool = True, stream=None):
+        """(counts [nz, ny, nx] uint32 as int32, mass sums, mass mixing ratios or None)."""
+        import torch
+        nx, ny, nz = self._outgrid
+        counts = torch.empty((nz, ny, nx), dtype=torch.int32, device="cuda")
+        msum = torch.empty((nz, ny, nx), dtype=torch.float64, device="cuda")
+        m = torch.empty((nz, ny, nx), dtype=torch.float64, device="cuda") if mmr else None
+        s = P.cstruct()
+        _check("mpt_grid_output", lib().mpt_grid_output(
+            self.h, ctypes.byref(s), mass.data_ptr() if mass is not None else None, counts.data_ptr(),
+            msum.data_ptr(), m.data_ptr() if m is not None else None, _stream_handle(stream)))
+        return counts, msum, m
 
     def advect(self, P: DeviceParticles, step: int, stream=None):
         s = P.cstruct()

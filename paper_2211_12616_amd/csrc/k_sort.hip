@@ -167,6 +167,14 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(const ScatterArgs a) {
 
 size_t scan_block_sums_len(uint32_t nkeys) { return (nkeys + kScanChunk - 1) / kScanChunk; }
 
+hipError_t launch_fill_u32(uint32_t *dst, uint32_t n, hipStream_t stream) {
+  unsigned g = (n + 255) / 256;
+  if (g > 4096) g = 4096;
+  if (g == 0) g = 1;
+  hipLaunchKernelGGL(k_fill_u32, dim3(g), dim3(256), 0, stream, dst, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_scan_u32(uint32_t *data, uint32_t n, uint32_t *block_sums, hipStream_t stream) {
   const uint32_t nb = (uint32_t)scan_block_sums_len(n);
   hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(256), 0, stream, data, n, block_sums);

@@ -18,6 +18,7 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr double kREarth = 6371000.0;                 // m
 constexpr double kH0 = 7000.0;                        // scale height, dz -> dp [m]
 constexpr double kDeg = 180.0 / (kPi * kREarth);      // metres -> degrees of arc
+constexpr double kG = 9.80665;                        // m s^-2 (box air mass)
 constexpr int kMaxLevels = 512;                       // LDS level table capacity
 constexpr int kLutBins = 8192;                        // level lookup bins over log2(p)
 constexpr int kBlock = 256;                           // 4 wave64 per block

@@ -133,6 +133,22 @@ hipError_t launch_surr_train(const SurrW &W, const SurrTrain &T, float *params, 
                              float lr, float bc1, float bc2, hipStream_t s);
 hipError_t launch_surr_grad(const SurrW &W, const SurrTrain &T, hipStream_t s);
 
+// Gridded output (k_out.hip).
+struct OutArgs {
+  const double *lon, *lat, *p;
+  const double *mass;              // null: unit masses
+  int64_t n;
+  int nx, ny, nz;
+  double lon0, dlon, lat0, dlat;
+  const double *pedges;            // device [nz + 1], strictly decreasing
+  int nblk, per_xcd;
+};
+constexpr int64_t kOutParcelsPerBlock = 1024;    // parcels per block of the output kernel
+// zero counts and sums, accumulate the parcels, then mmr (if not null)
+hipError_t launch_grid_out(const OutArgs &o, uint32_t *counts, double *msum, double *mmr, hipStream_t s);
+// dst[0 .. n) = 0 (k_sort.hip)
+hipError_t launch_fill_u32(uint32_t *dst, uint32_t n, hipStream_t s);
+
 // Single-word device helpers (k_step.hip).
 hipError_t launch_set_u32(uint32_t *p, uint32_t v, hipStream_t stream);
 hipError_t launch_add_u32(uint32_t *p, uint32_t v, hipStream_t stream);

@@ -37,6 +37,10 @@ struct mpt_ctx {
   int32_t nscen;
   // surrogate: bf16 weight copies, normalization, training scratch
   uint16_t *s_wt, *s_wb, *s_wi;
+  // gridded output: grid (edges on the device) and whether it is set
+  mpt_outgrid og;
+  double *out_pe;
+  int out_set;
   float *s_norm, *s_bias;               // loaded normalization and biases (FP32)
   uint16_t *s_x;                        // stencil rows of one chunk (bf16 [s_chunk][96])
   float *s_y;                           // predictions of one chunk ([s_chunk][4])
@@ -103,7 +107,7 @@ mpt_status check_params(const mpt_params *p, const mpt_grid *g) {
 
 struct Layout {
   size_t met, scales, plev, inv_dp, lut, release, rank, rel_sorted, step_dev, keys, ranks, hist, spread,
-      block_sums, s_wt, s_wb, s_wi, s_norm, s_bias, s_x, s_y, s_f, fb_mask, fb_off, fb_sums, t_xn, t_h, t_dy, t_dh, t_yp, t_grad, t_part, total;
+      block_sums, out_pe, s_wt, s_wb, s_wi, s_norm, s_bias, s_x, s_y, s_f, fb_mask, fb_off, fb_sums, t_xn, t_h, t_dy, t_dh, t_yp, t_grad, t_part, total;
   uint32_t ntx, nty, ntz, ntiles, nkeys;
   int64_t s_chunk;
 };
@@ -138,6 +142,7 @@ Layout layout(const mpt_grid *g, int64_t n_max) {
   L.hist = off;       off += align_up(sizeof(uint32_t) * L.nkeys);
   L.spread = off;     off += align_up(sizeof(uint32_t) * 16 * ((L.nkeys + 15) / 16));
   L.block_sums = off; off += align_up(sizeof(uint32_t) * scan_block_sums_len(L.nkeys));
+  L.out_pe = off;     off += align_up(sizeof(double) * (MPT_MAX_OUT_LEVELS + 1));
   L.s_wt = off;       off += align_up(sizeof(uint16_t) * kWtSize);
   L.s_wb = off;       off += align_up(sizeof(uint16_t) * kWbSize);
   L.s_wi = off;       off += align_up(sizeof(uint16_t) * kWiSize);
@@ -464,6 +469,7 @@ mpt_status mpt_create(const mpt_grid *grid, const mpt_params *params, int64_t n_
   c->hist = reinterpret_cast<uint32_t *>(ws + L.hist);
   c->spread = reinterpret_cast<uint32_t *>(ws + L.spread);
   c->block_sums = reinterpret_cast<uint32_t *>(ws + L.block_sums);
+  c->out_pe = reinterpret_cast<double *>(ws + L.out_pe);
   c->ntx = L.ntx; c->nty = L.nty; c->ntz = L.ntz; c->ntiles = L.ntiles; c->nkeys = L.nkeys;
   c->s_wt = reinterpret_cast<uint16_t *>(ws + L.s_wt);
   c->s_wb = reinterpret_cast<uint16_t *>(ws + L.s_wb);
@@ -841,6 +847,49 @@ mpt_status mpt_step_surrogate(mpt_ctx *c, mpt_particles *P, uint32_t step0, int3
     if (launch_step(c->grid.dtype, 0, f, s) != hipSuccess) return MPT_ERR_HIP;
   }
   return MPT_OK;
+}
+
+mpt_status mpt_set_outgrid(mpt_ctx *c, const mpt_outgrid *g, void *hip_stream) {
+  if (!c || !g || !g->pedges) return MPT_ERR_ARG;
+  if (g->nx < 1 || g->ny < 1 || g->nz < 1 || g->nz > MPT_MAX_OUT_LEVELS) return MPT_ERR_ARG;
+  if ((int64_t)g->nx * g->ny * g->nz > (int64_t)0x7FFFFFFF) return MPT_ERR_ARG;
+  if (!(g->dlon > 0.0) || fabs(g->nx * g->dlon - 360.0) > 1e-9 || !isfinite(g->lon0)) return MPT_ERR_ARG;
+  if (!(g->dlat > 0.0) || !(g->lat0 >= -90.0) || g->lat0 + g->ny * g->dlat > 90.0 + 1e-9) return MPT_ERR_ARG;
+  for (int k = 0; k <= g->nz; ++k)
+    if (!isfinite(g->pedges[k]) || (k > 0 && !(g->pedges[k] < g->pedges[k - 1]))) return MPT_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if (hipMemcpyAsync(c->out_pe, g->pedges, sizeof(double) * (g->nz + 1), hipMemcpyHostToDevice, s) !=
+          hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return MPT_ERR_HIP;
+  c->og = *g;
+  c->og.pedges = c->out_pe;
+  c->out_set = 1;
+  return MPT_OK;
+}
+
+mpt_status mpt_grid_output(mpt_ctx *c, const mpt_particles *P, const double *mass, uint32_t *counts,
+                           double *mass_sum, double *mmr, void *hip_stream) {
+  if (!c || !P || !counts || !mass_sum || P->n < 0) return MPT_ERR_ARG;
+  if (!aligned(counts, 4) || !aligned(mass_sum, 8) || (mmr && !aligned(mmr, 8))) return MPT_ERR_ARG;
+  if (P->n > ((int64_t)1 << 31) * kBlock / 2) return MPT_ERR_UNSUPPORTED;
+  if (P->n > 0) {
+    if (!P->lon || !P->lat || !P->p) return MPT_ERR_ARG;
+    if (!aligned(P->lon, 8) || !aligned(P->lat, 8) || !aligned(P->p, 8) || (mass && !aligned(mass, 8)))
+      return MPT_ERR_ARG;
+  }
+  if (!c->out_set) return MPT_ERR_STATE;
+  OutArgs o;
+  o.lon = P->lon; o.lat = P->lat; o.p = P->p;
+  o.mass = mass;
+  o.n = P->n;
+  o.nx = c->og.nx; o.ny = c->og.ny; o.nz = c->og.nz;
+  o.lon0 = c->og.lon0; o.dlon = c->og.dlon; o.lat0 = c->og.lat0; o.dlat = c->og.dlat;
+  o.pedges = c->out_pe;
+  const int64_t nblk = (P->n + kOutParcelsPerBlock - 1) / kOutParcelsPerBlock;
+  o.nblk = (int)nblk;
+  o.per_xcd = (int)((nblk + kXcds - 1) / kXcds);
+  return from_hip(launch_grid_out(o, counts, mass_sum, mmr, static_cast<hipStream_t>(hip_stream)));
 }
 
 mpt_status mpt_destroy(mpt_ctx *c) {

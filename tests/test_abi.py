@@ -143,6 +143,11 @@ def test_null_context_newer_entry_points():
     assert L.mpt_surrogate_load(None, None, None, 1.0, None) == -1
     assert L.mpt_surrogate_forward(None, 1, None, None, None) == -1
     assert L.mpt_step_surrogate(None, ctypes.byref(s), 0, 8, None, None, None) == -1
+    pe = (ctypes.c_double * 2)(1000.0, 500.0)
+    og = mpt.OutGrid(nx=8, ny=4, nz=1, lon0=0.0, dlon=45.0, lat0=-90.0, dlat=45.0,
+                     pedges=ctypes.cast(pe, ctypes.c_void_p))
+    assert L.mpt_set_outgrid(None, ctypes.byref(og), None) == -1
+    assert L.mpt_grid_output(None, ctypes.byref(s), None, None, None, None, None) == -1
 
 
 def test_surrogate_constants_match_header():
