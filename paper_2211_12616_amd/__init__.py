@@ -252,8 +252,9 @@ class Context:
         self.h = h
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib().mpt_destroy(self.h)
+        # at interpreter exit the module's globals may already be gone
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.mpt_destroy(self.h)
             self.h = None
 
     def init_met(self, level: int, u, v, w, stream=None):

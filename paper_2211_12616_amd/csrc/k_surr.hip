@@ -338,7 +338,7 @@ __global__ void k_surr_pack(const float *params, uint16_t *wt, uint16_t *wb) {
 // 32 kt + 4 g + j for j < 4 and 32 kt + 16 + 4 g + j - 4 for j >= 4.
 // Activations never leave registers; every weight fragment read from LDS
 // serves the 4 parcel tiles of a wave.
-constexpr int kMlpThreads = 256;
+constexpr int kMlpThreads = 512;
 constexpr int kMlpBlocks = 256;                               // one per CU
 
 typedef __attribute__((__vector_size__(8 * sizeof(float)))) float f32x8;
