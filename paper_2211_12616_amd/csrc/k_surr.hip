@@ -610,9 +610,13 @@ __global__ __launch_bounds__(64) void k_surr_train_bwd(const SurrW W, const Surr
 }
 
 // Weight gradients dW = A^T dH (reduction over the batch) for 16 x 16 tiles,
-// one wave each; the last blocks sum bias gradients.
+// one wave per tile and share of the batch (blockIdx.y of gridDim.y shares
+// of its 32-row chunks), added into grad (zeroed before); the last blocks
+// sum bias gradients the same way.
 __global__ __launch_bounds__(64) void k_surr_wgrad(const SurrTrain T, float *grad) {
   const int l = threadIdx.x, row = l & 15, kq = l >> 4;
+  const int64_t nch = T.batch / 32;
+  const int64_t r_lo = 32 * (nch * blockIdx.y / gridDim.y), r_hi = 32 * (nch * (blockIdx.y + 1) / gridDim.y);
   int tile = blockIdx.x;
   // tiles per layer: 6x8, 8x8, 8x8, 8x1
   const int tiles[4] = {48, 64, 64, 8};
@@ -628,8 +632,8 @@ __global__ __launch_bounds__(64) void k_surr_wgrad(const SurrTrain T, float *gra
     else if (c < 400) { src = T.dy; ld = kSurrOutPad; col = c - 384; off = kOffB4; }
     else return;
     float s = 0.0f;
-    for (int64_t r = 0; r < T.batch; ++r) s += bf2f(src[r * ld + col]);
-    grad[off + col] = s;
+    for (int64_t r = r_lo; r < r_hi; ++r) s += bf2f(src[r * ld + col]);
+    atomicAdd(&grad[off + col], s);
     return;
   }
   const LayerDims d = layer_dims(layer);
@@ -640,12 +644,12 @@ __global__ __launch_bounds__(64) void k_surr_wgrad(const SurrTrain T, float *gra
   const int lda = layer == 0 ? kSurrInPad : kSurrHid;
   const int ldb = layer == 3 ? kSurrOutPad : kSurrHid;
   f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-  for (int64_t b0 = 0; b0 < T.batch; b0 += 32) {
+  for (int64_t b0 = r_lo; b0 < r_hi; b0 += 32) {
     const int64_t r = b0 + kq * 8;
     acc = mfma(frag8_strided(A + r * lda + m0 + row, lda), frag8_strided(B + r * ldb + n0 + row, ldb), acc);
   }
 #pragma unroll
-  for (int q = 0; q < 4; ++q) grad[d.off_w + (m0 + kq * 4 + q) * d.out_pad + n0 + row] = acc[q];
+  for (int q = 0; q < 4; ++q) atomicAdd(&grad[d.off_w + (m0 + kq * 4 + q) * d.out_pad + n0 + row], acc[q]);
 }
 
 __global__ void k_surr_adam(float *params, const float *grad, float *m, float *v, float lr, float bc1,
@@ -946,12 +950,24 @@ hipError_t launch_surr_fblist(const uint64_t *fb_mask, int64_t n, uint32_t *off,
   return hipGetLastError();
 }
 
+// Splits of the batch for the weight gradients: about 256 rows each, at
+// most 16 (the 191 tiles x 16 shares fill the chip).
+static hipError_t launch_wgrad(const SurrTrain &T, hipStream_t s) {
+  int64_t split = T.batch / 256;
+  if (split < 1) split = 1;
+  if (split > 16) split = 16;
+  const hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(T.grad), (uint32_t)kSurrNParam, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_surr_wgrad, dim3(48 + 64 + 64 + 8 + 7, (unsigned)split), dim3(64), 0, s, T, T.grad);
+  return hipGetLastError();
+}
+
 hipError_t launch_surr_train(const SurrW &W, const SurrTrain &T, float *params, float *m, float *v,
                              float lr, float bc1, float bc2, hipStream_t s) {
   const unsigned nb = (unsigned)(T.batch / 64);
   hipLaunchKernelGGL(k_surr_train_fwd, dim3(nb), dim3(64), 0, s, W, T);
   hipLaunchKernelGGL(k_surr_train_bwd, dim3(nb), dim3(64), 0, s, W, T);
-  hipLaunchKernelGGL(k_surr_wgrad, dim3(48 + 64 + 64 + 8 + 7), dim3(64), 0, s, T, T.grad);
+  if (launch_wgrad(T, s) != hipSuccess) return hipGetLastError();
   hipLaunchKernelGGL(k_surr_adam, dim3((kSurrNParam + 255) / 256), dim3(256), 0, s, params, T.grad, m, v,
                      lr, bc1, bc2);
   return hipGetLastError();
@@ -961,7 +977,7 @@ hipError_t launch_surr_grad(const SurrW &W, const SurrTrain &T, hipStream_t s) {
   const unsigned nb = (unsigned)(T.batch / 64);
   hipLaunchKernelGGL(k_surr_train_fwd, dim3(nb), dim3(64), 0, s, W, T);
   hipLaunchKernelGGL(k_surr_train_bwd, dim3(nb), dim3(64), 0, s, W, T);
-  hipLaunchKernelGGL(k_surr_wgrad, dim3(48 + 64 + 64 + 8 + 7), dim3(64), 0, s, T, T.grad);
+  if (launch_wgrad(T, s) != hipSuccess) return hipGetLastError();
   return hipGetLastError();
 }
 
