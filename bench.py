@@ -69,6 +69,9 @@ def parse():
                     help="also run the batched release workload (16 scenarios, 480 steps)")
     ap.add_argument("--surrogate", action="store_true",
                     help="also train and run the learned 8-step surrogate (480 steps)")
+    ap.add_argument("--stream-met", action="store_true",
+                    help="also run 480 steps over 5 met levels with 2 resident, the next level "
+                         "copied on a second stream while stepping, against all 5 resident")
     ap.add_argument("--grid-output", action="store_true",
                     help="also time the gridded output on 1e8 parcels (random and sorted order)")
     ap.add_argument("--surr-train", type=float, default=5e7, help="surrogate training segments")
@@ -258,6 +261,79 @@ def run_surrogate(met, mpt, inputs, torch, args, nsteps=480):
                                                   "max": float(da.max())}}}
 
 
+def run_stream_met(met, mpt, inputs, torch, args, nsteps=480):
+    """A run longer than the resident window: 5 time levels (24 h), 2 on the
+    device; while the steps of one 6 h interval run, the next level goes
+    host -> pinned staging (CPU) -> device (second stream), and is pushed
+    into the ring on the compute stream once copied.  Timed against the same
+    run with all 5 levels resident; the final states must be identical."""
+    math_, dtype = FORMS[args.form]
+    n = int(args.n)
+    per = int(round(met.dt_met / 180.0))
+    part = inputs.make_particles(n, 23)
+    prm = mpt.make_params(math=math_, sort_interval=args.sort_interval, fuse=args.fuse)
+    out = {"workload": f"{n} parcels, {nsteps} steps over {met.nt} met levels (6 h apart), "
+                       f"form {args.form.upper()}; streamed: 2 levels resident"}
+    ctx = mpt.Context(met, prm, n_max=n, dtype=dtype)
+    ctx.upload_met(met)
+    A = mpt.DeviceParticles.from_host(part, math=math_)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(A, 0, nsteps)
+    torch.cuda.synchronize()
+    t_all = time.perf_counter() - t0
+    del ctx
+    torch.cuda.empty_cache()
+    ctx = mpt.Context(met, prm, n_max=n, dtype=dtype, resident=2)
+    ctx.upload_met(met)
+    B = mpt.DeviceParticles.from_host(part, math=math_)
+    shape = met.u[0].shape
+    pinned = [[torch.empty(shape, dtype=torch.float32, pin_memory=True) for _ in range(3)] for _ in range(2)]
+    dev = [[torch.empty(shape, dtype=torch.float32, device="cuda") for _ in range(3)] for _ in range(2)]
+    copy = torch.cuda.Stream()
+    comp = torch.cuda.current_stream()
+    copied, pushed = [None, None], [None, None]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nxt = 2
+    for b in range(nsteps // per):
+        ctx.step(B, per * b, per)                      # async on the compute stream
+        if nxt < met.nt:
+            k = nxt % 2
+            if copied[k] is not None:
+                copied[k].synchronize()                # staging buffer k free again
+            for h, a in zip(pinned[k], (met.u, met.v, met.w)):
+                h.numpy()[...] = a[nxt]
+            with torch.cuda.stream(copy):
+                if pushed[k] is not None:
+                    copy.wait_event(pushed[k])         # device buffer k consumed
+                for d, h in zip(dev[k], pinned[k]):
+                    d.copy_(h, non_blocking=True)
+                copied[k] = torch.cuda.Event()
+                copied[k].record(copy)
+            comp.wait_event(copied[k])
+            ctx.push_met(*dev[k])
+            pushed[k] = torch.cuda.Event()
+            pushed[k].record(comp)
+            nxt += 1
+    torch.cuda.synchronize()
+    t_stream = time.perf_counter() - t0
+    # the order within a tile follows the sort's atomics: compare by parcel id
+    oa, ob = torch.argsort(A.id), torch.argsort(B.id)
+    same = all(bool(torch.equal(getattr(A, f)[oa], getattr(B, f)[ob])) for f in ("lon", "lat", "p", "id"))
+    del oa, ob
+    out.update({"all_resident_particle_steps_per_s": n * nsteps / t_all,
+                "streamed_particle_steps_per_s": n * nsteps / t_stream,
+                "streamed_over_all_resident": t_all / t_stream,
+                "level_bytes_copied": 3 * int(np.prod(shape)) * 4,
+                "identical_final_state": same})
+    del A, B, ctx, dev, pinned
+    torch.cuda.empty_cache()
+    if not same:
+        raise RuntimeError("streamed run differs from the all-resident run")
+    return out
+
+
 def run_grid_output(met, mpt, inputs, torch, args, reps=5):
     """Gridded output of 1e8 parcels on a 1 x 1 deg grid with 18 layers
     (1000 .. 100 hPa): per call, count and FP64 mass sum per box plus the
@@ -358,7 +434,7 @@ def main():
     dt = 180.0
     total = W + K
     nt = int(math.ceil(total * dt / inputs.DT_MET)) + 1
-    if args.scenarios or args.surrogate:
+    if args.scenarios or args.surrogate or args.stream_met:
         nt = max(nt, int(math.ceil(480 * dt / inputs.DT_MET)) + 1)
     t0 = time.time()
     log(f"generating fields {args.nx}x{args.ny}x{args.nz}, nt={nt}")
@@ -498,6 +574,10 @@ def main():
     if args.scenarios:
         log("scenario workload")
         extras["scenarios"] = run_scenarios(met, mpt, inputs, torch)
+        torch.cuda.empty_cache()
+    if args.stream_met:
+        log("streamed met levels")
+        extras["stream_met"] = run_stream_met(met, mpt, inputs, torch, args)
         torch.cuda.empty_cache()
     if args.grid_output:
         log("gridded output")

@@ -134,15 +134,32 @@ size_t mpt_workspace_bytes(const mpt_grid *grid, const mpt_params *params, int64
 mpt_status mpt_create(const mpt_grid *grid, const mpt_params *params, int64_t n_max,
                       void *dev_workspace, size_t ws_bytes, mpt_ctx **out);
 
-/* Store time level `level` (0 .. nt-1) from device arrays u, v, w of
- * nz*ny*nx float each, index (k*ny + j)*nx + i, w in hPa/s (read_met,
- * Sec. 3.1; the kernel layout packs {u,v,w,0} per grid point, lon fastest;
- * BF16/F16 grids also compute the per-level scales).  The source arrays
- * may be freed once the stream has passed this call. */
+/* Store resident time level `level` (0 .. nt-1; the level at t_met0 +
+ * (first + level) * dt_met, first = number of mpt_push_met calls so far)
+ * from device arrays u, v, w of nz*ny*nx float each, index
+ * (k*ny + j)*nx + i, w in hPa/s (read_met, Sec. 3.1; the kernel layout
+ * packs {u,v,w,0} per grid point, lon fastest; BF16/F16 grids also compute
+ * the per-level scales).  The source arrays may be freed once the stream
+ * has passed this call. */
 mpt_status mpt_init_met(mpt_ctx *ctx, int32_t level, const float *u, const float *v,
                         const float *w, void *hip_stream);
 
-/* Copy the stored (packed) time level into dst (device, at least
+/* Advance the resident window by one time level (read_met supplying the
+ * next met0/met1 pair, Sec. 3.1 and the data regions of Sec. 4.1): the level
+ * at t_met0 + (first + nt) * dt_met, from device arrays as in mpt_init_met,
+ * replaces the oldest resident level (first), in place in a ring of nt
+ * slots.  Stream-ordered: work enqueued earlier on the same stream uses the
+ * old window; later calls must keep their steps inside the new window
+ * [t_met0 + (first + 1) dt_met, t_met0 + (first + nt) dt_met] (else
+ * MPT_ERR_TIME).  A caller overlapping the host-to-device copy of the next
+ * level with stepping copies it on another stream and orders this call
+ * after that copy.  MPT_ERR_STATE until all nt levels are stored.  Drops a
+ * captured step graph. */
+mpt_status mpt_push_met(mpt_ctx *ctx, const float *u, const float *v, const float *w,
+                        void *hip_stream);
+
+/* Copy the stored (packed) resident time level `level` (as in
+ * mpt_init_met) into dst (device, at least
  * mpt_met_level_bytes(ctx) bytes) and its scales into scales_dst (device,
  * 3*nz floats, index var*nz + k; all 1 for F32 storage).  Packed layout:
  * point (k, j, i) at element ((k*ny + j)*nx + i) of {u, v, w, 0} records of

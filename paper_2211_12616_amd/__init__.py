@@ -99,6 +99,7 @@ def lib() -> ctypes.CDLL:
         L.mpt_surrogate_load.argtypes = [P, P, P, ctypes.c_float, P]
         L.mpt_surrogate_forward.argtypes = [P, ctypes.c_int64, P, P, P]
         L.mpt_step_surrogate.argtypes = [P, P, ctypes.c_uint32, ctypes.c_int32, P, P, P]
+        L.mpt_push_met.argtypes = [P, P, P, P, P]
         L.mpt_set_outgrid.argtypes = [P, P, P]
         L.mpt_grid_output.argtypes = [P, P, P, P, P, P, P]
         L.mpt_destroy.argtypes = [P]
@@ -109,7 +110,7 @@ def lib() -> ctypes.CDLL:
                    "mpt_destroy", "mpt_surrogate_datagen", "mpt_surrogate_stats",
                    "mpt_surrogate_init", "mpt_surrogate_train_step", "mpt_surrogate_grad",
                    "mpt_surrogate_load", "mpt_surrogate_forward", "mpt_step_surrogate",
-                   "mpt_set_outgrid", "mpt_grid_output"):
+                   "mpt_set_outgrid", "mpt_grid_output", "mpt_push_met"):
             getattr(L, fn).restype = S
         _lib = L
     return _lib
@@ -122,7 +123,7 @@ def exported_symbols():
             "mpt_status_string", "mpt_surrogate_datagen", "mpt_surrogate_stats",
             "mpt_surrogate_init", "mpt_surrogate_train_step", "mpt_surrogate_grad",
             "mpt_surrogate_load", "mpt_surrogate_forward", "mpt_step_surrogate",
-            "mpt_set_outgrid", "mpt_grid_output"]
+            "mpt_set_outgrid", "mpt_grid_output", "mpt_push_met"]
 
 SURR_K, SURR_NIN, SURR_NOUT, SURR_NPARAM, SURR_MAX_BATCH = 8, 81, 3, 47504, 8192
 
@@ -237,9 +238,13 @@ class Context:
     """One mpt_ctx with its workspace (a torch uint8 tensor on the GPU)."""
 
     def __init__(self, met_meta, params: Params, n_max: int = 0, dtype: int = DT_F32,
-                 device: str = "cuda"):
+                 device: str = "cuda", resident: Optional[int] = None):
+        """``resident``: number of met time levels held on the device (default:
+        all of ``met_meta``); later levels arrive with push_met."""
         import torch
         self.grid, self._plev = make_grid(met_meta, dtype)
+        if resident is not None:
+            self.grid.nt = resident
         self.params = params
         L = lib()
         nbytes = L.mpt_workspace_bytes(ctypes.byref(self.grid), ctypes.byref(params), n_max)
@@ -263,10 +268,17 @@ class Context:
         _check("mpt_init_met", lib().mpt_init_met(self.h, level, u.data_ptr(), v.data_ptr(),
                                                   w.data_ptr(), _stream_handle(stream)))
 
+    def push_met(self, u, v, w, stream=None):
+        """mpt_push_met: the next time level replaces the oldest resident one."""
+        for t in (u, v, w):
+            assert t.is_cuda and t.dtype.itemsize == 4 and t.is_contiguous()
+        _check("mpt_push_met", lib().mpt_push_met(self.h, u.data_ptr(), v.data_ptr(), w.data_ptr(),
+                                                  _stream_handle(stream)))
+
     def upload_met(self, met, stream=None):
-        """Store every time level of an ``inputs.Met`` (host float32)."""
+        """Store the first grid.nt time levels of an ``inputs.Met`` (host float32)."""
         import torch
-        for l in range(met.nt):
+        for l in range(self.grid.nt):
             u = torch.from_numpy(met.u[l]).cuda()
             v = torch.from_numpy(met.v[l]).cuda()
             w = torch.from_numpy(met.w[l]).cuda()

@@ -113,7 +113,7 @@ template <bool kTime, class Sink>
 __device__ __forceinline__ void stencil81(const StepArgs &a, const Loc<float> &L, const float4 *f0, Sink sink) {
   const float4 *base = reinterpret_cast<const float4 *>(a.met);
   const float4 *lev0 = kTime ? base + (int64_t)L.l * a.level_elems : f0;
-  const float4 *lev1 = lev0 + a.level_elems;
+  const float4 *lev1 = base + (int64_t)L.l1 * a.level_elems;
   int ic[4], jr[4], kr[4], pb[3], pc[3];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -678,7 +678,7 @@ __global__ __launch_bounds__(256) void k_surr_tfield(const StepArgs a, double t,
   Loc<float> L;
   locate_t<float>(a, t, L);
   const float4 *lev0 = reinterpret_cast<const float4 *>(a.met) + (int64_t)L.l * a.level_elems;
-  const float4 *lev1 = lev0 + a.level_elems;
+  const float4 *lev1 = reinterpret_cast<const float4 *>(a.met) + (int64_t)L.l1 * a.level_elems;
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < a.level_elems;
        q += (int64_t)gridDim.x * blockDim.x) {
     const float4 r0 = lev0[q], r1 = lev1[q];

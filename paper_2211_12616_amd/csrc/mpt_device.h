@@ -36,7 +36,7 @@ struct StepArgs {
   const int32_t *release;      // per scenario, device; null when scen is null
   int64_t n;
 
-  const void *met;             // packed levels, level l at met + l*level_elems records
+  const void *met;             // packed levels, ring slot s at met + s*level_elems records
   int64_t level_elems;         // nx*ny*nz
   const float *scales;         // [nt][3][nz] (R16 storage)
   const double *plev;          // [nz] device
@@ -72,6 +72,8 @@ struct StepArgs {
   // Index-list mode: advance only parcels index[0 .. *index_count).
   const uint32_t *index;
   const uint32_t *index_count;
+  // Resident met levels: absolute index of the oldest and its ring slot.
+  int32_t lev_first, slot_first;
   // Diffusion of a k-step surrogate block drawn at once (spread frozen):
   // turbulence sqrt(k) sig_h, sqrt(k) sig_z; AR(1) sums A = r + ... + r^k,
   // r^k, and the Cholesky factor (l11, l21, l22) of the covariance of
@@ -203,7 +205,8 @@ struct Fetch<kF32, R> {
 // ---- locate ----------------------------------------------------------------------
 template <typename R>
 struct Loc {
-  int i0, i1, j, k, l;
+  int i0, i1, j, k;
+  int l, l1;            // storage slots of the earlier and the later time level
   R fx, fy, fz, ft;
 };
 
@@ -249,14 +252,21 @@ __device__ __forceinline__ void locate_xyz(const StepArgs &a, const double *s_pl
   L.fz = (R)((s_plev[k] - pc) * s_idp[k]);
 }
 
-// Time-level pair bracketing t and the weight of the later level.
+// Time-level pair bracketing t and the weight of the later level.  The
+// resident levels are lev_first .. lev_first + nt - 1 (absolute indices,
+// level L at t_met0 + L dt_met), stored in a ring of nt slots starting at
+// slot_first; the pair is clamped to the resident window.
 template <typename R>
 __device__ __forceinline__ void locate_t(const StepArgs &a, double t, Loc<R> &L) {
   double tl = floor((t - a.t_met0) * a.inv_dt_met);
   int l = (int)tl;
-  if (tl < 0.0) l = 0;
-  if (l > a.nt - 2) l = a.nt - 2;
-  L.l = l;
+  if (tl < (double)a.lev_first) l = a.lev_first;
+  if (l > a.lev_first + a.nt - 2) l = a.lev_first + a.nt - 2;
+  int s0 = a.slot_first + (l - a.lev_first);
+  if (s0 >= a.nt) s0 -= a.nt;
+  const int s1 = s0 + 1 == a.nt ? 0 : s0 + 1;
+  L.l = s0;
+  L.l1 = s1;
   L.ft = (R)((t - (a.t_met0 + (double)l * a.dt_met)) * a.inv_dt_met);
 }
 
@@ -288,7 +298,7 @@ __device__ __forceinline__ void load_cell(const StepArgs &a, const Loc<R> &L, Ce
   const int ip = seam ? L.i0 - 1 : L.i0;
 #pragma unroll
   for (int dl = 0; dl < 2; ++dl) {
-    const T *lev = base + (int64_t)(L.l + dl) * a.level_elems;
+    const T *lev = base + (int64_t)(dl ? L.l1 : L.l) * a.level_elems;
 #pragma unroll
     for (int dk = 0; dk < 2; ++dk)
 #pragma unroll
@@ -320,7 +330,7 @@ __device__ __forceinline__ void cell_scales(const StepArgs &a, const Loc<R> &L, 
       if (F == kF32) {
         sc[dl][dk][0] = sc[dl][dk][1] = sc[dl][dk][2] = 1.0f;
       } else {
-        const float *s = a.scales + (int64_t)(L.l + dl) * 3 * a.nz + (L.k + dk);
+        const float *s = a.scales + (int64_t)(dl ? L.l1 : L.l) * 3 * a.nz + (L.k + dk);
         sc[dl][dk][0] = s[0];
         sc[dl][dk][1] = s[a.nz];
         sc[dl][dk][2] = s[2 * a.nz];

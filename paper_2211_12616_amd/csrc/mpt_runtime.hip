@@ -37,6 +37,8 @@ struct mpt_ctx {
   int32_t nscen;
   // surrogate: bf16 weight copies, normalization, training scratch
   uint16_t *s_wt, *s_wb, *s_wi;
+  // resident met levels: absolute index of the oldest, its ring slot
+  int32_t lev_first, slot_first;
   // gridded output: grid (edges on the device) and whether it is set
   mpt_outgrid og;
   double *out_pe;
@@ -176,6 +178,8 @@ void fill_step_args(const mpt_ctx *c, const mpt_particles *P, uint32_t step0, in
   a.lon = P->lon; a.lat = P->lat; a.p = P->p; a.id = P->id;
   a.up = P->up; a.vp = P->vp; a.wp = P->wp;
   a.scen = P->scen;
+  a.lev_first = c->lev_first;
+  a.slot_first = c->slot_first;
   a.release = P->scen ? c->release : nullptr;
   a.n = P->n;
   a.met = c->met;
@@ -284,7 +288,8 @@ mpt_status check_time(const mpt_ctx *c, uint32_t step0, int64_t nsteps) {
   if (nsteps == 0) return MPT_OK;
   if ((uint64_t)step0 + (uint64_t)nsteps - 1 > 0xFFFFFFFFull) return MPT_ERR_ARG;
   const mpt_grid &g = c->grid;
-  const double t_lo = g.t_met0, t_hi = g.t_met0 + (g.nt - 1) * g.dt_met;
+  const double t_lo = g.t_met0 + (double)c->lev_first * g.dt_met;
+  const double t_hi = g.t_met0 + (double)(c->lev_first + g.nt - 1) * g.dt_met;
   const double eps = 1e-9 * g.dt_met;
   const double t_first = c->params.t_start + (double)step0 * c->params.dt;
   const double t_last_end = c->params.t_start + (double)(step0 + (uint64_t)nsteps - 1) * c->params.dt +
@@ -526,15 +531,14 @@ mpt_status mpt_create(const mpt_grid *grid, const mpt_params *params, int64_t n_
   return MPT_OK;
 }
 
-mpt_status mpt_init_met(mpt_ctx *c, int32_t level, const float *u, const float *v, const float *w,
-                        void *hip_stream) {
-  if (!c || !u || !v || !w) return MPT_ERR_ARG;
-  if (level < 0 || level >= c->grid.nt) return MPT_ERR_ARG;
-  if (!aligned(u, 4) || !aligned(v, 4) || !aligned(w, 4)) return MPT_ERR_ARG;
-  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+namespace {
+// Pack a time level from device arrays into ring slot `slot` (F32 records,
+// or R16 codes with their per-level scales).
+mpt_status pack_level(mpt_ctx *c, int slot, const float *u, const float *v, const float *w,
+                      hipStream_t s) {
   const int64_t nxy = (int64_t)c->grid.nx * c->grid.ny;
-  unsigned char *dst = static_cast<unsigned char *>(c->met) + c->level_bytes * (size_t)level;
-  float *sc = c->scales + (size_t)level * 3 * c->grid.nz;
+  unsigned char *dst = static_cast<unsigned char *>(c->met) + c->level_bytes * (size_t)slot;
+  float *sc = c->scales + (size_t)slot * 3 * c->grid.nz;
   hipError_t e;
   if (c->grid.dtype == MPT_DT_F32) {
     e = launch_pack_f32(u, v, w, reinterpret_cast<float4 *>(dst), c->npts, s);
@@ -545,9 +549,39 @@ mpt_status mpt_init_met(mpt_ctx *c, int32_t level, const float *u, const float *
                           c->grid.nz, s);
   }
   if (e != hipSuccess) return MPT_ERR_HIP;
-  c->levels_ready |= 1ull << level;
   return MPT_OK;
 }
+}  // namespace
+
+mpt_status mpt_init_met(mpt_ctx *c, int32_t level, const float *u, const float *v, const float *w,
+                        void *hip_stream) {
+  if (!c || !u || !v || !w) return MPT_ERR_ARG;
+  if (level < 0 || level >= c->grid.nt) return MPT_ERR_ARG;
+  if (!aligned(u, 4) || !aligned(v, 4) || !aligned(w, 4)) return MPT_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const int slot = (c->slot_first + level) % c->grid.nt;
+  const mpt_status st = pack_level(c, slot, u, v, w, s);
+  if (st != MPT_OK) return st;
+  c->levels_ready |= 1ull << slot;
+  return MPT_OK;
+}
+
+mpt_status mpt_push_met(mpt_ctx *c, const float *u, const float *v, const float *w, void *hip_stream) {
+  if (!c || !u || !v || !w) return MPT_ERR_ARG;
+  if (!aligned(u, 4) || !aligned(v, 4) || !aligned(w, 4)) return MPT_ERR_ARG;
+  const uint64_t all = (c->grid.nt >= 64) ? ~0ull : ((1ull << c->grid.nt) - 1ull);
+  if ((c->levels_ready & all) != all) return MPT_ERR_STATE;
+  if (c->lev_first > 0x7FFFFFFF - c->grid.nt - 1) return MPT_ERR_UNSUPPORTED;
+  // the oldest level's slot receives level lev_first + nt
+  const mpt_status st = pack_level(c, c->slot_first, u, v, w, static_cast<hipStream_t>(hip_stream));
+  if (st != MPT_OK) return st;
+  c->lev_first += 1;
+  c->slot_first = c->slot_first + 1 == c->grid.nt ? 0 : c->slot_first + 1;
+  drop_graph(c);                        // captured launches hold the old window
+  return MPT_OK;
+}
+
+
 
 size_t mpt_met_level_bytes(const mpt_ctx *c) { return c ? c->level_bytes : 0; }
 
@@ -555,6 +589,7 @@ mpt_status mpt_copy_met_level(mpt_ctx *c, int32_t level, void *dst, float *scale
                               void *hip_stream) {
   if (!c || !dst || !scales_dst) return MPT_ERR_ARG;
   if (level < 0 || level >= c->grid.nt) return MPT_ERR_ARG;
+  level = (c->slot_first + level) % c->grid.nt;          // its ring slot
   if (!(c->levels_ready & (1ull << level))) return MPT_ERR_STATE;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   const unsigned char *src = static_cast<const unsigned char *>(c->met) + c->level_bytes * (size_t)level;

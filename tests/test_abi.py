@@ -148,6 +148,7 @@ def test_null_context_newer_entry_points():
                      pedges=ctypes.cast(pe, ctypes.c_void_p))
     assert L.mpt_set_outgrid(None, ctypes.byref(og), None) == -1
     assert L.mpt_grid_output(None, ctypes.byref(s), None, None, None, None, None) == -1
+    assert L.mpt_push_met(None, None, None, None, None) == -1
 
 
 def test_surrogate_constants_match_header():
