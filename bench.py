@@ -69,6 +69,8 @@ def parse():
                     help="also run the batched release workload (16 scenarios, 480 steps)")
     ap.add_argument("--surrogate", action="store_true",
                     help="also train and run the learned 8-step surrogate (480 steps)")
+    ap.add_argument("--ml2pl", action="store_true",
+                    help="also time the model-level -> pressure-level regridding of one time level")
     ap.add_argument("--stream-met", action="store_true",
                     help="also run 480 steps over 5 met levels with 2 resident, the next level "
                          "copied on a second stream while stepping, against all 5 resident")
@@ -259,6 +261,37 @@ def run_surrogate(met, mpt, inputs, torch, args, nsteps=480):
                             "error_vs_plain_km": {"p50": float(np.percentile(da, 50)),
                                                   "p99": float(np.percentile(da, 99)),
                                                   "max": float(da.max())}}}
+
+
+def run_ml2pl(met, mpt, inputs, torch, args, reps=5):
+    """Regridding of one time level from 137 hybrid model levels (terrain
+    following below 100 hPa) to the 137 pressure levels of the grid, with a
+    smooth surface pressure field; the stored pressure-level fields stand in
+    for the model-level data (the values do not change the work)."""
+    a, b = inputs.hybrid_levels(met.plev)
+    ctx = mpt.Context(met, mpt.make_params(math=0), n_max=16)
+    ctx.set_hybrid(a, b)
+    ps = torch.from_numpy(inputs.make_surface_pressure(31, met.nx, met.ny)).cuda()
+    u, v, w = (torch.from_numpy(x[0]).cuda() for x in (met.u, met.v, met.w))
+    ctx.ml_to_pl(ps, u, v, w)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        out = ctx.ml_to_pl(ps, u, v, w)
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    t = float(np.median(ms))
+    ncol = met.nx * met.ny
+    nbytes = 3 * 4 * ncol * (len(a) + met.nz) + 4 * ncol
+    del out, ctx
+    torch.cuda.empty_cache()
+    return {"workload": f"one time level, {len(a)} hybrid model levels -> {met.nz} pressure levels, "
+                        f"{met.nx}x{met.ny} columns, u, v, w",
+            "ms_per_level": t, "algorithmic_GBps": nbytes / (t * 1e-3) / 1e9,
+            "hbm_frac": nbytes / (t * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
 def run_stream_met(met, mpt, inputs, torch, args, nsteps=480):
@@ -574,6 +607,10 @@ def main():
     if args.scenarios:
         log("scenario workload")
         extras["scenarios"] = run_scenarios(met, mpt, inputs, torch)
+        torch.cuda.empty_cache()
+    if args.ml2pl:
+        log("model levels to pressure levels")
+        extras["ml2pl"] = run_ml2pl(met, mpt, inputs, torch, args)
         torch.cuda.empty_cache()
     if args.stream_met:
         log("streamed met levels")

@@ -224,6 +224,30 @@ mpt_status mpt_step(mpt_ctx *ctx, mpt_particles *particles, uint32_t step0, int3
 mpt_status mpt_step_graph(mpt_ctx *ctx, mpt_particles *particles, uint32_t step0, int32_t nsteps,
                           void *hip_stream);
 
+/* ---- Hybrid model levels (read_met reads model-level data and regrids it,
+ * Sec. 3.1: read_met_levels).  A reading: column pressures p_k = a_k +
+ * b_k ps [hPa] for model levels k = 0 .. nml-1 (k = 0 lowest, pressure
+ * decreasing with k); each of the context's pressure levels is interpolated
+ * per column linearly in ln p between the two model levels around it; a
+ * level below the lowest or above the highest model level of its column
+ * takes that level's value.  The results feed mpt_init_met / mpt_push_met. */
+enum { MPT_MAX_ML_LEVELS = 512 };
+
+/* Set the model levels (host arrays, copied; synchronizes the stream).
+ * MPT_ERR_ARG unless 2 <= nml <= MPT_MAX_ML_LEVELS, values finite, column
+ * pressures strictly decreasing with k and positive for ps in [500, 1100]
+ * hPa (checked at both ends; the pressures are linear in ps). */
+mpt_status mpt_set_hybrid(mpt_ctx *ctx, int32_t nml, const double *a, const double *b,
+                          void *hip_stream);
+
+/* ps (device, ny*nx float, hPa, index j*nx + i) and u, v, w (device,
+ * nml*ny*nx float each, index (k*ny + j)*nx + i) on the model levels ->
+ * u_pl, v_pl, w_pl (device, nz*ny*nx float each) on the context's pressure
+ * levels, interpolation in FP64, results rounded to FP32.  MPT_ERR_STATE
+ * before mpt_set_hybrid. */
+mpt_status mpt_ml_to_pl(mpt_ctx *ctx, const float *ps, const float *u, const float *v,
+                        const float *w, float *u_pl, float *v_pl, float *w_pl, void *hip_stream);
+
 /* ---- Gridded output (write_grid, Sec. 3.3: the output functions write
  * parcel data, gridded data and ensemble data).  The paper names the
  * function only; the reading here: a regular grid of nx x ny boxes in lon x

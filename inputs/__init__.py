@@ -138,6 +138,57 @@ def make_met_c1(seed: int = 11, nt: int = 2, nx: int = 180, ny: int = 91, nz: in
 
 
 # --------------------------------------------------------------------------
+# hybrid model levels (input for the model-level -> pressure-level step)
+# --------------------------------------------------------------------------
+def hybrid_levels(p_ref: np.ndarray, p_pure: float = 100.0, ps_ref: float = 1013.25):
+    """Coefficients (a [hPa], b) of model levels at the pressures p_ref
+    (decreasing) where the surface pressure is ps_ref: terrain following
+    below p_pure, b = ((p - p_pure) / (ps_ref - p_pure))^1.5, pure pressure
+    above (b = 0); a = p - b ps_ref.  Column pressures a + b ps decrease
+    with the level index for every ps in [500, 1100] hPa."""
+    p_ref = np.asarray(p_ref, np.float64)
+    b = np.clip((p_ref - p_pure) / (ps_ref - p_pure), 0.0, None) ** 1.5
+    return p_ref - b * ps_ref, b
+
+
+def make_surface_pressure(seed: int, nx: int, ny: int, mean: float = 1013.25,
+                          amp: float = 40.0) -> np.ndarray:
+    """ps [ny, nx] float32 hPa: mean + amp * a smooth sum of 4 sinusoids in
+    lon / lat with amplitudes summing to 1."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lam = np.deg2rad(np.arange(nx) * 360.0 / nx)[None, :]
+    phi = np.deg2rad(-90.0 + np.arange(ny) * 180.0 / (ny - 1))[:, None]
+    a = rng.uniform(0.0, 1.0, 4)
+    a /= a.sum()
+    acc = np.zeros((ny, nx))
+    for m in range(4):
+        acc += a[m] * np.cos(rng.integers(0, 4) * lam + rng.integers(1, 4) * phi + rng.uniform(0, 2 * math.pi))
+    return (mean + amp * acc).astype(np.float32)
+
+
+def make_model_level_fields(seed: int, p_ref: np.ndarray, nx: int, ny: int) -> tuple:
+    """u, v, w [nml, ny, nx] float32 on model levels: smooth sinusoids of lon,
+    lat and ln(p_ref / 1000) as in the tiny workload (winds 50 m/s, omega
+    0.005 hPa/s), with its taper (cos lat on u and v, p_ref / 1000 on omega)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lam = np.deg2rad(np.arange(nx) * 360.0 / nx)[None, None, :]
+    phi = np.deg2rad(-90.0 + np.arange(ny) * 180.0 / (ny - 1))[None, :, None]
+    lnp = np.log(np.asarray(p_ref, np.float64) / 1000.0)[:, None, None]
+    taper_h = np.cos(phi)
+    taper_w = (np.asarray(p_ref, np.float64) / 1000.0)[:, None, None]
+    out = []
+    for amp, taper in ((50.0, taper_h), (50.0, taper_h), (0.005, taper_w)):
+        a = rng.uniform(0.0, 1.0, 6)
+        a /= a.sum()
+        acc = np.zeros((len(p_ref), ny, nx))
+        for m in range(6):
+            acc += a[m] * np.cos(rng.integers(0, 4) * lam + rng.integers(1, 4) * phi
+                                 + rng.uniform(0.5, 2.0) * lnp + rng.uniform(0, 2 * math.pi))
+        out.append((amp * taper * acc).astype(np.float32))
+    return tuple(out)
+
+
+# --------------------------------------------------------------------------
 # realistic case: jet band + smoothed perturbations
 # --------------------------------------------------------------------------
 

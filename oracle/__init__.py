@@ -68,6 +68,7 @@ def lib() -> ctypes.CDLL:
         L.orc_cell_sigma_many.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.c_double, P]
         L.orc_locate_many.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.c_double, P, P]
         L.orc_position_many.argtypes = [P, ctypes.c_int64, P, P, P]
+        L.orc_ml_to_pl.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P, P, P, P, P]
         L.orc_grid_output.argtypes = [ctypes.c_int64, P, P, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                       ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                       P, P, P, P]
@@ -189,6 +190,18 @@ def tile_keys(m: Met, lon, lat, p) -> np.ndarray:
     lon, lat, p = (np.ascontiguousarray(a, np.float64) for a in (lon, lat, p))
     out = np.empty(len(lon), np.uint32)
     lib().orc_tile_keys(m.ref, len(lon), _ptr(lon), _ptr(lat), _ptr(p), _ptr(out))
+    return out
+
+
+def ml_to_pl(plev, a, b, ps, f) -> np.ndarray:
+    """Model-level field f [nml, ny, nx] with surface pressure ps [ny, nx] to
+    the pressure levels plev: [nz, ny, nx] float32."""
+    plev, a, b = (np.ascontiguousarray(x, np.float64) for x in (plev, a, b))
+    ps = np.ascontiguousarray(ps, np.float32)
+    f = np.ascontiguousarray(f, np.float32)
+    ny, nx = ps.shape
+    out = np.empty((len(plev), ny, nx), np.float32)
+    lib().orc_ml_to_pl(nx, ny, len(plev), _ptr(plev), len(a), _ptr(a), _ptr(b), _ptr(ps), _ptr(f), _ptr(out))
     return out
 
 

@@ -583,4 +583,33 @@ void orc_grid_output(int64_t n, const double *lon, const double *lat, const doub
   }
 }
 
+/* ---- hybrid model levels to pressure levels (read_met regridding the
+ * model-level data, Sec. 3.1; a reading).  Column pressures
+ * p_k = a_k + b_k ps (k = 0 lowest, decreasing with k); a target level p
+ * between p_k >= p > p_{k+1} gets f_k + (ln p_k - ln p) / (ln p_k - ln p_{k+1})
+ * (f_{k+1} - f_k); a target below the lowest or above the highest model level
+ * of its column gets that level's value.  FP64, rounded to float. */
+void orc_ml_to_pl(int nx, int ny, int nz, const double *plev, int nml, const double *a,
+                  const double *b, const float *ps, const float *f, float *out)
+{
+  const int64_t ncol = (int64_t)nx * ny;
+  for (int m = 0; m < nz; ++m)
+    for (int64_t col = 0; col < ncol; ++col) {
+      const double s = ps[col], p = plev[m];
+      double val;
+      if (p >= a[0] + b[0] * s) {
+        val = f[col];
+      } else if (p <= a[nml - 1] + b[nml - 1] * s) {
+        val = f[(int64_t)(nml - 1) * ncol + col];
+      } else {
+        int k = 0;
+        while (!(a[k] + b[k] * s >= p && p > a[k + 1] + b[k + 1] * s)) ++k;
+        const double pk = a[k] + b[k] * s, pk1 = a[k + 1] + b[k + 1] * s;
+        const double f0 = f[(int64_t)k * ncol + col], f1 = f[(int64_t)(k + 1) * ncol + col];
+        val = f0 + (log(pk) - log(p)) / (log(pk) - log(pk1)) * (f1 - f0);
+      }
+      out[(int64_t)m * ncol + col] = (float)val;
+    }
+}
+
 int orc_max_threads(void) { return omp_get_max_threads(); }

@@ -100,6 +100,8 @@ def lib() -> ctypes.CDLL:
         L.mpt_surrogate_forward.argtypes = [P, ctypes.c_int64, P, P, P]
         L.mpt_step_surrogate.argtypes = [P, P, ctypes.c_uint32, ctypes.c_int32, P, P, P]
         L.mpt_push_met.argtypes = [P, P, P, P, P]
+        L.mpt_set_hybrid.argtypes = [P, ctypes.c_int32, P, P, P]
+        L.mpt_ml_to_pl.argtypes = [P, P, P, P, P, P, P, P, P]
         L.mpt_set_outgrid.argtypes = [P, P, P]
         L.mpt_grid_output.argtypes = [P, P, P, P, P, P, P]
         L.mpt_destroy.argtypes = [P]
@@ -110,7 +112,8 @@ def lib() -> ctypes.CDLL:
                    "mpt_destroy", "mpt_surrogate_datagen", "mpt_surrogate_stats",
                    "mpt_surrogate_init", "mpt_surrogate_train_step", "mpt_surrogate_grad",
                    "mpt_surrogate_load", "mpt_surrogate_forward", "mpt_step_surrogate",
-                   "mpt_set_outgrid", "mpt_grid_output", "mpt_push_met"):
+                   "mpt_set_outgrid", "mpt_grid_output", "mpt_push_met", "mpt_set_hybrid",
+                   "mpt_ml_to_pl"):
             getattr(L, fn).restype = S
         _lib = L
     return _lib
@@ -123,7 +126,7 @@ def exported_symbols():
             "mpt_status_string", "mpt_surrogate_datagen", "mpt_surrogate_stats",
             "mpt_surrogate_init", "mpt_surrogate_train_step", "mpt_surrogate_grad",
             "mpt_surrogate_load", "mpt_surrogate_forward", "mpt_step_surrogate",
-            "mpt_set_outgrid", "mpt_grid_output", "mpt_push_met"]
+            "mpt_set_outgrid", "mpt_grid_output", "mpt_push_met", "mpt_set_hybrid", "mpt_ml_to_pl"]
 
 SURR_K, SURR_NIN, SURR_NOUT, SURR_NPARAM, SURR_MAX_BATCH = 8, 81, 3, 47504, 8192
 
@@ -267,6 +270,26 @@ class Context:
             assert t.is_cuda and t.dtype.itemsize == 4 and t.is_contiguous()
         _check("mpt_init_met", lib().mpt_init_met(self.h, level, u.data_ptr(), v.data_ptr(),
                                                   w.data_ptr(), _stream_handle(stream)))
+
+    def set_hybrid(self, a: np.ndarray, b: np.ndarray, stream=None):
+        """Hybrid model levels p_k = a_k + b_k ps [hPa], k = 0 lowest."""
+        a = np.ascontiguousarray(a, np.float64)
+        b = np.ascontiguousarray(b, np.float64)
+        _check("mpt_set_hybrid", lib().mpt_set_hybrid(self.h, len(a), a.ctypes.data, b.ctypes.data,
+                                                      _stream_handle(stream)))
+
+    def ml_to_pl(self, ps, u, v, w, stream=None):
+        """Model-level u, v, w [nml, ny, nx] (torch float32 cuda) with surface
+        pressure ps [ny, nx] -> the context's pressure levels, [nz, ny, nx]."""
+        import torch
+        g = self.grid
+        out = [torch.empty((g.nz, g.ny, g.nx), dtype=torch.float32, device="cuda") for _ in range(3)]
+        for t in (ps, u, v, w):
+            assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
+        _check("mpt_ml_to_pl", lib().mpt_ml_to_pl(self.h, ps.data_ptr(), u.data_ptr(), v.data_ptr(),
+                                                  w.data_ptr(), *(o.data_ptr() for o in out),
+                                                  _stream_handle(stream)))
+        return out
 
     def push_met(self, u, v, w, stream=None):
         """mpt_push_met: the next time level replaces the oldest resident one."""

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmpt.so")
-SOURCES = ["mpt_runtime.hip", "k_step.hip", "k_sort.hip", "k_met.hip", "k_surr.hip", "k_out.hip"]
+SOURCES = ["mpt_runtime.hip", "k_step.hip", "k_sort.hip", "k_met.hip", "k_surr.hip", "k_out.hip", "k_ml2pl.hip"]
 
 # -ffp-contract=off: multiply-adds only where the source writes fma(), so
 # fused and split step kernels round identically.  Packed FP32 instructions

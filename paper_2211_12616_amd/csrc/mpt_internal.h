@@ -149,6 +149,15 @@ hipError_t launch_grid_out(const OutArgs &o, uint32_t *counts, double *msum, dou
 // dst[0 .. n) = 0 (k_sort.hip)
 hipError_t launch_fill_u32(uint32_t *dst, uint32_t n, hipStream_t s);
 
+// Hybrid model levels to pressure levels (k_ml2pl.hip).
+struct Ml2PlArgs {
+  int nx, ny, nz, nml;             // target grid, number of model levels
+  const double *plev;              // device [nz] target pressures
+  const double *a, *b;             // device [nml]: p_k = a_k + b_k ps, decreasing with k
+};
+hipError_t launch_ml_to_pl(const Ml2PlArgs &g, const float *ps, const float *u, const float *v,
+                           const float *w, float *uo, float *vo, float *wo, hipStream_t s);
+
 // Single-word device helpers (k_step.hip).
 hipError_t launch_set_u32(uint32_t *p, uint32_t v, hipStream_t stream);
 hipError_t launch_add_u32(uint32_t *p, uint32_t v, hipStream_t stream);

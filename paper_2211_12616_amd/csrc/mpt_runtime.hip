@@ -43,6 +43,9 @@ struct mpt_ctx {
   mpt_outgrid og;
   double *out_pe;
   int out_set;
+  // hybrid model levels: a[0 .. nml) then b[0 .. nml) on the device
+  double *hyb_ab;
+  int hyb_nml;
   float *s_norm, *s_bias;               // loaded normalization and biases (FP32)
   uint16_t *s_x;                        // stencil rows of one chunk (bf16 [s_chunk][96])
   float *s_y;                           // predictions of one chunk ([s_chunk][4])
@@ -109,7 +112,7 @@ mpt_status check_params(const mpt_params *p, const mpt_grid *g) {
 
 struct Layout {
   size_t met, scales, plev, inv_dp, lut, release, rank, rel_sorted, step_dev, keys, ranks, hist, spread,
-      block_sums, out_pe, s_wt, s_wb, s_wi, s_norm, s_bias, s_x, s_y, s_f, fb_mask, fb_off, fb_sums, t_xn, t_h, t_dy, t_dh, t_yp, t_grad, t_part, total;
+      block_sums, out_pe, hyb_ab, s_wt, s_wb, s_wi, s_norm, s_bias, s_x, s_y, s_f, fb_mask, fb_off, fb_sums, t_xn, t_h, t_dy, t_dh, t_yp, t_grad, t_part, total;
   uint32_t ntx, nty, ntz, ntiles, nkeys;
   int64_t s_chunk;
 };
@@ -145,6 +148,7 @@ Layout layout(const mpt_grid *g, int64_t n_max) {
   L.spread = off;     off += align_up(sizeof(uint32_t) * 16 * ((L.nkeys + 15) / 16));
   L.block_sums = off; off += align_up(sizeof(uint32_t) * scan_block_sums_len(L.nkeys));
   L.out_pe = off;     off += align_up(sizeof(double) * (MPT_MAX_OUT_LEVELS + 1));
+  L.hyb_ab = off;     off += align_up(sizeof(double) * 2 * MPT_MAX_ML_LEVELS);
   L.s_wt = off;       off += align_up(sizeof(uint16_t) * kWtSize);
   L.s_wb = off;       off += align_up(sizeof(uint16_t) * kWbSize);
   L.s_wi = off;       off += align_up(sizeof(uint16_t) * kWiSize);
@@ -475,6 +479,7 @@ mpt_status mpt_create(const mpt_grid *grid, const mpt_params *params, int64_t n_
   c->spread = reinterpret_cast<uint32_t *>(ws + L.spread);
   c->block_sums = reinterpret_cast<uint32_t *>(ws + L.block_sums);
   c->out_pe = reinterpret_cast<double *>(ws + L.out_pe);
+  c->hyb_ab = reinterpret_cast<double *>(ws + L.hyb_ab);
   c->ntx = L.ntx; c->nty = L.nty; c->ntz = L.ntz; c->ntiles = L.ntiles; c->nkeys = L.nkeys;
   c->s_wt = reinterpret_cast<uint16_t *>(ws + L.s_wt);
   c->s_wb = reinterpret_cast<uint16_t *>(ws + L.s_wb);
@@ -925,6 +930,39 @@ mpt_status mpt_grid_output(mpt_ctx *c, const mpt_particles *P, const double *mas
   o.nblk = (int)nblk;
   o.per_xcd = (int)((nblk + kXcds - 1) / kXcds);
   return from_hip(launch_grid_out(o, counts, mass_sum, mmr, static_cast<hipStream_t>(hip_stream)));
+}
+
+mpt_status mpt_set_hybrid(mpt_ctx *c, int32_t nml, const double *a, const double *b, void *hip_stream) {
+  if (!c || !a || !b || nml < 2 || nml > MPT_MAX_ML_LEVELS) return MPT_ERR_ARG;
+  for (int k = 0; k < nml; ++k) {
+    if (!isfinite(a[k]) || !isfinite(b[k])) return MPT_ERR_ARG;
+    if (k > 0)
+      for (double ps = 500.0; ps <= 1100.0; ps += 600.0)
+        if (!(a[k] + b[k] * ps < a[k - 1] + b[k - 1] * ps)) return MPT_ERR_ARG;
+    if (!(a[k] + b[k] * 500.0 > 0.0)) return MPT_ERR_ARG;
+  }
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if (hipMemcpyAsync(c->hyb_ab, a, sizeof(double) * nml, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(c->hyb_ab + nml, b, sizeof(double) * nml, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return MPT_ERR_HIP;
+  c->hyb_nml = nml;
+  return MPT_OK;
+}
+
+mpt_status mpt_ml_to_pl(mpt_ctx *c, const float *ps, const float *u, const float *v, const float *w,
+                        float *u_pl, float *v_pl, float *w_pl, void *hip_stream) {
+  if (!c || !ps || !u || !v || !w || !u_pl || !v_pl || !w_pl) return MPT_ERR_ARG;
+  const float *ptrs[7] = {ps, u, v, w, u_pl, v_pl, w_pl};
+  for (const float *q : ptrs)
+    if (!aligned(q, 4)) return MPT_ERR_ARG;
+  if (c->hyb_nml < 2) return MPT_ERR_STATE;
+  Ml2PlArgs g;
+  g.nx = c->grid.nx; g.ny = c->grid.ny; g.nz = c->grid.nz; g.nml = c->hyb_nml;
+  g.plev = c->plev;
+  g.a = c->hyb_ab;
+  g.b = c->hyb_ab + c->hyb_nml;
+  return from_hip(launch_ml_to_pl(g, ps, u, v, w, u_pl, v_pl, w_pl, static_cast<hipStream_t>(hip_stream)));
 }
 
 mpt_status mpt_destroy(mpt_ctx *c) {

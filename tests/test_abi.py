@@ -149,6 +149,8 @@ def test_null_context_newer_entry_points():
     assert L.mpt_set_outgrid(None, ctypes.byref(og), None) == -1
     assert L.mpt_grid_output(None, ctypes.byref(s), None, None, None, None, None) == -1
     assert L.mpt_push_met(None, None, None, None, None) == -1
+    assert L.mpt_set_hybrid(None, 2, None, None, None) == -1
+    assert L.mpt_ml_to_pl(None, None, None, None, None, None, None, None, None) == -1
 
 
 def test_surrogate_constants_match_header():
