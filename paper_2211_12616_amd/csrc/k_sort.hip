@@ -2,7 +2,7 @@
 // inside the tile and histogram in one pass, exclusive scan of the
 // histogram, then an atomic-free scatter of the whole parcel state into the
 // second buffer set at offset[key] + rank.  Parcels that are already nearly
-// sorted share keys across a wavefront, so the histogram counter of a key
+// sorted share keys along a wave's range, so the histogram counter of a key
 // is bumped once per run of equal keys within a wave.
 #include "mpt_internal.h"
 
@@ -10,72 +10,160 @@ namespace mpt {
 
 constexpr int kScanChunk = 1024;   // entries per scan block (256 threads x 4)
 
-// For lanes holding `key` (valid lanes form a prefix of the wave), add the
-// length of each run of equal keys to the key's counter *ctr once and
-// return, for every lane, the old counter value plus the lane's rank inside
-// its run.
-__device__ __forceinline__ uint32_t wave_run_add(uint32_t *ctr, uint32_t key, bool valid) {
-  const int lane = (int)__lane_id();
-  const uint32_t prev = __shfl_up(key, 1);
-  const bool head = valid && (lane == 0 || prev != key);
-  const uint64_t heads = __ballot(head);
-  const uint64_t valids = __ballot(valid);
-  if (heads == 0) return 0;
-  const uint64_t le = heads & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull));
-  const int myhead = le ? 63 - __clzll((long long)le) : 0;
-  const uint64_t above = heads & (myhead == 63 ? 0ull : ~((2ull << myhead) - 1ull));
-  const int endl = above ? __ffsll((long long)above) - 1 : 64 - __clzll((long long)valids);
-  uint32_t base = 0;
-  if (head) base = atomicAdd(ctr, (uint32_t)(endl - myhead));
-  base = __shfl(base, myhead);
-  return base + (uint32_t)(lane - myhead);
-}
-
 // counts in key order from the spread counters
 __global__ void k_unspread(const uint32_t *spread, uint32_t s, uint32_t nkeys, uint32_t *hist) {
   const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k < nkeys) hist[k] = spread[(k & 15u) * s + (k >> 4)];
 }
 
-// One parcel per thread.  The level table and levels are read from global
-// memory (cache resident): staging them in LDS per block would cost more
-// than the parcel data itself, as each parcel needs one table entry.
+// Tile key: 8 x 8 x 4 cells (lon x lat x level), lon fastest; parcels not
+// yet released at the sort's step go behind the tiles in the release order
+// of their scenario; non-finite positions last.  The level table and levels
+// are read from global memory (cache resident): staging them in LDS per
+// block would cost more than the parcel data itself.
+//
+// Each wave takes kSortPer * 64 consecutive parcels (group q = parcels
+// q*64 .. q*64+63 of the wave's range, one per lane), so a thread has
+// kSortPer independent parcels in flight.  Runs of equal keys are found over
+// the wave's whole range (a run may cross groups); each run adds its length
+// to its key's counter once, every atomic of the wave is issued before any
+// result is used, and a parcel's rank is the run's old counter value plus
+// its place in the run.  Counters of consecutive keys sit spread_s apart:
+// nearly sorted parcels bump consecutive keys, and atomics on one cache line
+// queue up.
 __global__ __launch_bounds__(kBlock) void k_sort_keys(const SortArgs a) {
   const int lb = logical_block((int)blockIdx.x, a.per_xcd);
   if (lb >= a.nblk) return;
-  const int64_t i = (int64_t)lb * kBlock + threadIdx.x;
-  const bool valid = i < a.n;
-  uint32_t key = 0xFFFFFFFFu;
+  const int lane = (int)__lane_id();
+  const int64_t i_w = (int64_t)lb * (kBlock * kSortPer) + (int64_t)(threadIdx.x >> 6) * (64 * kSortPer);
   const uint32_t step = a.step + (a.step_dev ? *a.step_dev : 0u);
-  if (valid) {
-    const double lon = a.lon[i], lat = a.lat[i], p = a.p[i];
-    if (!finite3(lon, lat, p)) {
-      key = a.nkeys - 1;
-    } else if (a.scen && (int64_t)step < (int64_t)a.release[a.scen[i]]) {
-      key = a.ntx * a.nty * a.ntz + (uint32_t)a.rank[a.scen[i]];
-    } else {
-      const double lam = lon - 360.0 * floor((lon - a.lon0) * (1.0 / 360.0));
-      int i0 = (int)floor((lam - a.lon0) * a.inv_dlon);
-      if (i0 >= a.nx) i0 -= a.nx;
-      if (i0 < 0) i0 += a.nx;
-      const double phi = fmin(fmax(lat, a.lat0), a.lat_hi);
-      int j = (int)floor((phi - a.lat0) * a.inv_dlat);
-      j = min(max(j, 0), a.ny - 2);
-      const double pc = fmin(fmax(p, a.p_top), a.p_bot);
-      int b = (int)((__log2f((float)pc) - a.lut_lo) * a.lut_scale);
-      b = min(max(b, 0), kLutBins - 1);
-      int k = a.lut[b];
-      while (k < a.nz - 2 && a.plev[k + 1] >= pc) ++k;
-      while (k > 0 && a.plev[k] < pc) --k;
-      key = ((uint32_t)(k >> 2) * a.nty + (uint32_t)(j >> 3)) * a.ntx + (uint32_t)(i0 >> 3);
+  // The tile key of each parcel, computed in stages over the kSortPer parcels
+  // so that their dependent loads (position, level table, levels) are in
+  // flight together.  Invalid lanes read parcel n-1 and get key 0xFFFFFFFF.
+  int64_t ic[kSortPer];
+  double lon[kSortPer], lat[kSortPer], p[kSortPer];
+#pragma unroll
+  for (int q = 0; q < kSortPer; ++q) {
+    const int64_t i = i_w + q * 64 + lane;
+    ic[q] = i < a.n ? i : a.n - 1;
+    lon[q] = a.lon[ic[q]];
+    lat[q] = a.lat[ic[q]];
+    p[q] = a.p[ic[q]];
+  }
+  uint32_t key[kSortPer];
+  double pc[kSortPer];
+  int k[kSortPer];
+#pragma unroll
+  for (int q = 0; q < kSortPer; ++q) {
+    const double lam = lon[q] - 360.0 * floor((lon[q] - a.lon0) * (1.0 / 360.0));
+    int i0 = (int)floor((lam - a.lon0) * a.inv_dlon);
+    if (i0 >= a.nx) i0 -= a.nx;
+    if (i0 < 0) i0 += a.nx;
+    const double phi = fmin(fmax(lat[q], a.lat0), a.lat_hi);
+    int j = (int)floor((phi - a.lat0) * a.inv_dlat);
+    j = min(max(j, 0), a.ny - 2);
+    key[q] = (uint32_t)(j >> 3) * a.ntx + (uint32_t)(i0 >> 3);     // level part added below
+    pc[q] = fmin(fmax(p[q], a.p_top), a.p_bot);
+    int b = (int)((__log2f((float)pc[q]) - a.lut_lo) * a.lut_scale);
+    b = min(max(b, 0), kLutBins - 1);
+    k[q] = a.lut[b];
+  }
+  uint16_t sc[kSortPer];
+  if (a.scen) {
+#pragma unroll
+    for (int q = 0; q < kSortPer; ++q) sc[q] = a.scen[ic[q]];
+  }
+  // Level: the largest k <= nz-2 with plev[k] >= pc.  The table's k is a
+  // lower bound up to the FP32 rounding of the bin, so the answer is almost
+  // always within k-2 .. k+2: the four levels around k decide up to two
+  // steps either way, further steps (rare) walk on.
+  double pm[kSortPer], p0[kSortPer], p1[kSortPer], p2[kSortPer];
+#pragma unroll
+  for (int q = 0; q < kSortPer; ++q) {
+    pm[q] = a.plev[max(k[q] - 1, 0)];
+    p0[q] = a.plev[k[q]];
+    p1[q] = a.plev[min(k[q] + 1, a.nz - 1)];
+    p2[q] = a.plev[min(k[q] + 2, a.nz - 1)];
+  }
+  int32_t rel[kSortPer], rk[kSortPer];
+  if (a.scen) {
+#pragma unroll
+    for (int q = 0; q < kSortPer; ++q) {
+      rel[q] = a.release[sc[q]];
+      rk[q] = a.rank[sc[q]];
     }
   }
-  // counters of consecutive keys sit spread_s apart: nearly sorted parcels
-  // bump consecutive keys, and atomics on one cache line queue up
-  const uint32_t rank = wave_run_add(a.spread + (key & 15u) * a.spread_s + (key >> 4), key, valid);
-  if (valid) {
-    a.keys[i] = key;
-    a.ranks[i] = rank;
+  const int top = a.nz - 2;
+  uint64_t heads[kSortPer];
+  int nvalid = 0;                     // valid parcels form a prefix of the wave's range
+#pragma unroll
+  for (int q = 0; q < kSortPer; ++q) {
+    int kk = k[q];
+    if (kk < top && p1[q] >= pc[q]) {
+      ++kk;
+      if (kk < top && p2[q] >= pc[q]) {
+        ++kk;
+        while (kk < top && a.plev[kk + 1] >= pc[q]) ++kk;
+      }
+    } else if (kk > 0 && p0[q] < pc[q]) {
+      --kk;
+      if (kk > 0 && pm[q] < pc[q]) {
+        --kk;
+        while (kk > 0 && a.plev[kk] < pc[q]) --kk;
+      }
+    }
+    key[q] += (uint32_t)(kk >> 2) * a.nty * a.ntx;
+    if (a.scen && (int64_t)step < (int64_t)rel[q]) key[q] = a.ntx * a.nty * a.ntz + (uint32_t)rk[q];
+    if (!finite3(lon[q], lat[q], p[q])) key[q] = a.nkeys - 1;
+    const bool valid = i_w + q * 64 + lane < a.n;
+    if (!valid) key[q] = 0xFFFFFFFFu;
+    uint32_t prev = __shfl_up(key[q], 1);
+    if (lane == 0) prev = q > 0 ? __shfl(key[q - 1], 63) : ~key[q];
+    heads[q] = __ballot(valid && prev != key[q]);
+    nvalid += __popcll(__ballot(valid));
+  }
+  // run ends and the atomics, all issued before any result is waited for
+  uint32_t base[kSortPer];
+  const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);   // lanes <= lane
+#pragma unroll
+  for (int q = 0; q < kSortPer; ++q) {
+    base[q] = 0;
+    if ((heads[q] >> lane) & 1ull) {
+      const uint64_t above = heads[q] & ~upto;
+      int end = nvalid;
+      if (above) {
+        end = q * 64 + __ffsll((long long)above) - 1;
+      } else {
+#pragma unroll
+        for (int r = kSortPer - 1; r > q; --r)
+          if (heads[r]) end = r * 64 + __ffsll((long long)heads[r]) - 1;
+      }
+      base[q] = atomicAdd(a.spread + (key[q] & 15u) * a.spread_s + (key[q] >> 4),
+                          (uint32_t)(end - (q * 64 + lane)));
+    }
+  }
+  uint32_t cbase = 0;                 // base and wave position of the last head so far
+  int cpos = 0;
+#pragma unroll
+  for (int q = 0; q < kSortPer; ++q) {
+    const int64_t i = i_w + q * 64 + lane;
+    const uint64_t le = heads[q] & upto;
+    uint32_t rank;
+    if (le) {
+      const int h = 63 - __clzll((long long)le);
+      rank = __shfl(base[q], h) + (uint32_t)(lane - h);
+    } else {
+      rank = cbase + (uint32_t)(q * 64 + lane - cpos);
+    }
+    if (heads[q]) {
+      const int h = 63 - __clzll((long long)heads[q]);
+      cbase = __shfl(base[q], h);
+      cpos = q * 64 + h;
+    }
+    if (i < a.n) {
+      a.keys[i] = key[q];
+      a.ranks[i] = rank;
+    }
   }
 }
 
@@ -143,6 +231,7 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t *dst, uint32_t n) {
   for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) dst[q] = 0u;
 }
 
+// One parcel per thread: from i to offset[key] + rank.
 __global__ __launch_bounds__(kBlock) void k_sort_scatter(const ScatterArgs a) {
   const int lb = logical_block((int)blockIdx.x, a.per_xcd);
   if (lb >= a.nblk) return;

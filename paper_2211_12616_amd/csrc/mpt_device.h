@@ -157,7 +157,13 @@ template <typename R>
 __device__ __forceinline__ void normals3(uint64_t seed, uint32_t id, uint32_t step, uint32_t purpose,
                                          R xi[3]) {
   uint32_t x[4];
-  philox4x32_10(id, step, purpose, 0u, (uint32_t)seed, (uint32_t)(seed >> 32), x);
+  // The key words are tied to the step (an empty asm that takes the step as
+  // input), so the nine round keys are formed on the scalar unit at each
+  // draw instead of being hoisted out of the step loop, where they would be
+  // spilled to vector lanes and read back every step.
+  uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  asm("" : "+s"(k0), "+s"(k1) : "s"(step));
+  philox4x32_10(id, step, purpose, 0u, k0, k1, x);
   const R u0 = Math<R>::uni(x[0]), u1 = Math<R>::uni(x[1]);
   const R u2 = Math<R>::uni(x[2]), u3 = Math<R>::uni(x[3]);
   const R r0 = Math<R>::sqrt_((R)-2 * Math<R>::log_(u0));

@@ -22,6 +22,10 @@ hipError_t launch_pack_r16(int field, const float *u, const float *v, const floa
 hipError_t launch_fill_f32(float *dst, float value, int64_t n, hipStream_t stream);
 
 // Sort (k_sort.hip).
+// Parcels per thread in the sort's key kernel (a block covers
+// kSortPer * kBlock parcels).
+constexpr int kSortPer = 4;
+
 struct SortArgs {
   const double *lon, *lat, *p;
   const double *plev, *inv_dp;

@@ -325,7 +325,7 @@ mpt_status do_sort(mpt_ctx *c, mpt_particles *P, uint32_t step, bool dev_step, h
   sa.step_dev = dev_step ? c->step_dev : nullptr;
   sa.keys = c->keys; sa.ranks = c->ranks; sa.hist = c->hist; sa.block_sums = c->block_sums;
   sa.spread = c->spread; sa.spread_s = (c->nkeys + 15) / 16;
-  const int64_t nblk = (P->n + kBlock - 1) / kBlock;
+  const int64_t nblk = (P->n + kBlock * kSortPer - 1) / (kBlock * kSortPer);
   sa.nblk = (int)nblk;
   sa.per_xcd = (int)((nblk + kXcds - 1) / kXcds);
   ScatterArgs xa;
@@ -335,7 +335,9 @@ mpt_status do_sort(mpt_ctx *c, mpt_particles *P, uint32_t step, bool dev_step, h
   xa.lon2 = P->lon2; xa.lat2 = P->lat2; xa.p2 = P->p2; xa.id2 = P->id2;
   xa.up2 = P->up2; xa.vp2 = P->vp2; xa.wp2 = P->wp2; xa.scen2 = P->scen2;
   xa.meso_bytes = c->params.math == MPT_MATH_F64 ? 8 : 4;
-  xa.nblk = sa.nblk; xa.per_xcd = sa.per_xcd;
+  const int64_t nblk_x = (P->n + kBlock - 1) / kBlock;
+  xa.nblk = (int)nblk_x;
+  xa.per_xcd = (int)((nblk_x + kXcds - 1) / kXcds);
   const mpt_status st = from_hip(launch_sort(sa, xa, s));
   if (st != MPT_OK) return st;
   // the sorted state now lives in the *2 set: swap the sets
