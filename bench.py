@@ -76,6 +76,9 @@ def parse():
                          "copied on a second stream while stepping, against all 5 resident")
     ap.add_argument("--grid-output", action="store_true",
                     help="also time the gridded output on 1e8 parcels (random and sorted order)")
+    ap.add_argument("--physics", action="store_true",
+                    help="also run all modules plus convection and sedimentation (F64 and F32 "
+                         "forms, 60 timed steps) against the same run without them")
     ap.add_argument("--surr-train", type=float, default=5e7, help="surrogate training segments")
     ap.add_argument("--surr-epochs", type=int, default=2)
     ap.add_argument("--surr-bound-km", type=float, default=1.0,
@@ -367,6 +370,62 @@ def run_stream_met(met, mpt, inputs, torch, args, nsteps=480):
     return out
 
 
+def run_physics(met, mpt, inputs, torch, args, nsteps=60, warm=10):
+    """All modules plus convection (CAPE threshold 800 J/kg) and
+    sedimentation (radius 5 um, density 1000 kg/m^3) on the headline
+    workload, F64 and F32 forms, against the same runs without the two
+    modules; launches of 10 steps timed with events, sort every 10 steps."""
+    inputs.add_phys_fields(met, seed=31)
+    n = int(args.n)
+    part = inputs.make_particles(n, 23)
+    out = {"workload": f"{n} parcels, 0.3deg grid {met.nx}x{met.ny}x{met.nz}, advect+turb+meso"
+                       f"+convection+sedimentation, {nsteps} timed steps"}
+    S = args.sort_interval
+    for form in ("f64", "f32"):
+        math_, dtype = FORMS[form]
+        for phys in (False, True):
+            flags = mpt.ADVECT | mpt.TURB | mpt.MESO | ((mpt.CONV | mpt.SEDI) if phys else 0)
+            prm = mpt.make_params(math=math_, flags=flags, fuse=args.fuse, conv_cape=800.0,
+                                  sedi_radius=5e-6, sedi_density=1000.0)
+            ctx = mpt.Context(met, prm, n_max=n, dtype=dtype)
+            ctx.upload_met(met)
+            P = mpt.DeviceParticles.from_host(part, math=math_)
+            stream = torch.cuda.current_stream()
+            ev = []
+
+            def run(s0, k, timed):
+                s = s0
+                while s < s0 + k:
+                    if S > 0 and s % S == 0:
+                        ctx.sort(P)
+                    stop = min(s0 + k, (s // S + 1) * S if S > 0 else s0 + k, s + args.fuse)
+                    if timed:
+                        ev.append([torch.cuda.Event(enable_timing=True) for _ in range(2)])
+                        ev[-1][0].record(stream)
+                    ctx.step(P, s, stop - s)
+                    if timed:
+                        ev[-1][1].record(stream)
+                    s = stop
+
+            run(0, warm, False)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            run(warm, nsteps, True)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            key = f"{form}_{'phys' if phys else 'plain'}"
+            out[key] = {"particle_steps_per_s": n * nsteps / el,
+                        "step_kernel_ms_avg": float(np.mean([a.elapsed_time(b) for a, b in ev])),
+                        "finite": bool(torch.isfinite(P.lon).all().item())}
+            log(f"physics leg {key}: {n * nsteps / el:.3e} particle-steps/s")
+            del ctx, P
+            torch.cuda.empty_cache()
+        out[f"{form}_phys_over_plain_time"] = (out[f"{form}_plain"]["particle_steps_per_s"]
+                                               / out[f"{form}_phys"]["particle_steps_per_s"])
+    met.temp = met.cape = met.pel = met.ps = None
+    return out
+
+
 def run_grid_output(met, mpt, inputs, torch, args, reps=5):
     """Gridded output of 1e8 parcels on a 1 x 1 deg grid with 18 layers
     (1000 .. 100 hPa): per call, count and FP64 mass sum per box plus the
@@ -619,6 +678,10 @@ def main():
     if args.grid_output:
         log("gridded output")
         extras["grid_output"] = run_grid_output(met, mpt, inputs, torch, args)
+        torch.cuda.empty_cache()
+    if args.physics:
+        log("convection and sedimentation")
+        extras["physics"] = run_physics(met, mpt, inputs, torch, args)
         torch.cuda.empty_cache()
     if args.surrogate:
         log("surrogate workload")

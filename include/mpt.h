@@ -68,8 +68,11 @@ typedef enum { MPT_MATH_F64 = 0, MPT_MATH_F32 = 1 } mpt_math;
  * FP32.  BF16 and F16 require MPT_MATH_F32. */
 typedef enum { MPT_DT_F32 = 0, MPT_DT_BF16 = 1, MPT_DT_F16 = 2 } mpt_dtype;
 
-/* Module flags (mpt_params.flags). */
-enum { MPT_ADVECT = 1u, MPT_TURB = 2u, MPT_MESO = 4u };
+/* Module flags (mpt_params.flags).  MPT_CONV and MPT_SEDI (module_convection
+ * and module_sedi, Sec. 3.2) act in mpt_step and mpt_step_graph only, after
+ * the diffusion, and need the fields of mpt_set_met_phys on every resident
+ * level. */
+enum { MPT_ADVECT = 1u, MPT_TURB = 2u, MPT_MESO = 4u, MPT_CONV = 8u, MPT_SEDI = 16u };
 
 /* Regular lon-lat grid with fixed pressure levels and nt resident time
  * levels (read_met / read_met_periodic, Sec. 3.1).
@@ -101,6 +104,9 @@ typedef struct {
     uint32_t flags;            /* MPT_ADVECT | MPT_TURB | MPT_MESO */
     int32_t fuse;              /* max steps one kernel launch may advance
                                   with the state kept in registers (>= 1) */
+    double conv_cape;          /* MPT_CONV: CAPE threshold [J/kg], finite */
+    double sedi_radius;        /* MPT_SEDI: particle radius [m], > 0 */
+    double sedi_density;       /* MPT_SEDI: particle density [kg/m^3], > 0 */
 } mpt_params;
 
 /* Parcel state (atm_t, Sec. 4.4, plus the mesoscale state of `cache`).
@@ -158,12 +164,34 @@ mpt_status mpt_init_met(mpt_ctx *ctx, int32_t level, const float *u, const float
 mpt_status mpt_push_met(mpt_ctx *ctx, const float *u, const float *v, const float *w,
                         void *hip_stream);
 
+/* Convection and sedimentation fields of resident time level `level` (as
+ * in mpt_init_met; read_met_cape and the temperature of read_met_levels,
+ * Sec. 3.1), from device arrays of float: temp [K], nz*ny*nx, index
+ * (k*ny + j)*nx + i, positive; cape [J/kg], pel (equilibrium level) and ps
+ * (surface pressure) [hPa], ny*nx, index j*nx + i.  The temperature goes
+ * into the fourth value of each packed record (BF16 / F16 storage: with its
+ * own per-level scale); the three surface fields are kept as FP32 records
+ * {cape, pel, ps, 0}.  Must follow the level's mpt_init_met (or, for the
+ * newest level after mpt_push_met, level nt-1): storing u, v, w for a level
+ * clears these fields.  Readings used by the step:
+ *   convection: with CAPE >= conv_cape and p > pel at the parcel (bilinear
+ *     in lon, lat, linear in time, at the middle of the step), the parcel
+ *     moves to p = ps + (pel - ps) u, u uniform from the Philox block of
+ *     counter (id, step, 5, 0), first word;
+ *   sedimentation: settling velocity v of a sphere (Stokes drag, Cunningham
+ *     slip correction 1 + Kn (1.257 + 0.4 exp(-1.1/Kn)), Sutherland
+ *     viscosity) at the interpolated temperature; p += p v dt / 7000 m.
+ * The source arrays may be freed once the stream has passed this call. */
+mpt_status mpt_set_met_phys(mpt_ctx *ctx, int32_t level, const float *temp, const float *cape,
+                            const float *pel, const float *ps, void *hip_stream);
+
 /* Copy the stored (packed) resident time level `level` (as in
  * mpt_init_met) into dst (device, at least
  * mpt_met_level_bytes(ctx) bytes) and its scales into scales_dst (device,
  * 3*nz floats, index var*nz + k; all 1 for F32 storage).  Packed layout:
- * point (k, j, i) at element ((k*ny + j)*nx + i) of {u, v, w, 0} records of
- * 4 x float (F32) or 4 x uint16 (BF16 / F16 bit patterns). */
+ * point (k, j, i) at element ((k*ny + j)*nx + i) of {u, v, w, T} records of
+ * 4 x float (F32) or 4 x uint16 (BF16 / F16 bit patterns); T is 0 unless
+ * mpt_set_met_phys stored the level's temperature. */
 mpt_status mpt_copy_met_level(mpt_ctx *ctx, int32_t level, void *dst, float *scales_dst,
                               void *hip_stream);
 size_t mpt_met_level_bytes(const mpt_ctx *ctx);

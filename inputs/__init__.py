@@ -24,6 +24,7 @@ import dataclasses
 import math
 import os
 from concurrent.futures import ThreadPoolExecutor
+from typing import Optional
 
 import numpy as np
 
@@ -72,6 +73,13 @@ class Met:
     u: np.ndarray
     v: np.ndarray
     w: np.ndarray
+    # convection / sedimentation fields (optional): temperature [K] shaped
+    # like u; CAPE [J/kg], equilibrium-level and surface pressure [hPa]
+    # shaped (nt, ny, nx)
+    temp: Optional[np.ndarray] = None
+    cape: Optional[np.ndarray] = None
+    pel: Optional[np.ndarray] = None
+    ps: Optional[np.ndarray] = None
 
     @property
     def t_end(self) -> float:
@@ -291,6 +299,44 @@ def make_met_c2(seed: int = 12, nt: int = 3, nx: int = 1200, ny: int = 601, nz: 
 # --------------------------------------------------------------------------
 # particles
 # --------------------------------------------------------------------------
+
+def add_phys_fields(met: Met, seed: int = 31, cape_max: float = 2500.0) -> Met:
+    """Seeded convection / sedimentation fields on met's grid (in place):
+
+    * temperature: the standard-atmosphere troposphere 288.15 (p/1013.25)^0.1903
+      K floored at 216.65 K, minus 25 sin^2(lat) K below 200 hPa, plus a
+      smooth +-3 K wave moving in time;
+    * CAPE: cape_max * max(0, cos(2 lat)) * (1/2 + 1/2 sin(2 lon + om t + th)),
+      so about half of the tropics and mid-latitudes exceed a few hundred J/kg
+      at any time and the rest is below;
+    * equilibrium level: 150 + 150 |lat| / 90 hPa plus a +-30 hPa wave;
+    * surface pressure: 1013.25 - 60 max(0, sin(3 lon) cos(lat))^2 + a +-5 hPa
+      wave (orography-like lows down to about 950 hPa)."""
+    rng = np.random.default_rng(seed)
+    th = rng.uniform(0.0, 2.0 * np.pi, 4)
+    om = rng.uniform(-1.0, 1.0, 4) * 2.0 * np.pi / (2.0 * 86400.0)
+    lon = np.deg2rad(met.lon_axis())[None, :]
+    lat = np.deg2rad(met.lat_axis())[:, None]
+    p = met.plev[:, None, None]
+    base = np.maximum(216.65, 288.15 * (p / 1013.25) ** 0.190263)
+    base = base - 25.0 * np.sin(lat)[None] ** 2 * (p > 200.0)
+    shape3, shape2 = (met.nt, met.nz, met.ny, met.nx), (met.nt, met.ny, met.nx)
+    met.temp = np.empty(shape3, np.float32)
+    met.cape = np.empty(shape2, np.float32)
+    met.pel = np.empty(shape2, np.float32)
+    met.ps = np.empty(shape2, np.float32)
+    for l in range(met.nt):
+        t = met.t_met0 + l * met.dt_met
+        wave = 3.0 * np.sin(lon + 2.0 * lat + om[0] * t + th[0])
+        met.temp[l] = (base + wave[None]).astype(np.float32)
+        met.cape[l] = (cape_max * np.maximum(0.0, np.cos(2.0 * lat))
+                       * (0.5 + 0.5 * np.sin(2.0 * lon + om[1] * t + th[1]))).astype(np.float32)
+        met.pel[l] = (150.0 + 150.0 * np.abs(lat) / (0.5 * np.pi)
+                      + 30.0 * np.sin(3.0 * lon - lat + om[2] * t + th[2])).astype(np.float32)
+        met.ps[l] = (1013.25 - 60.0 * np.maximum(0.0, np.sin(3.0 * lon) * np.cos(lat)) ** 2
+                     + 5.0 * np.sin(lon + lat + om[3] * t + th[3])).astype(np.float32)
+    return met
+
 
 @dataclasses.dataclass
 class Particles:

@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mpt_oracle.c")
 _LIB = os.path.join(_HERE, "libmpt_oracle.so")
 
-ADVECT, TURB, MESO = 1, 2, 4
+ADVECT, TURB, MESO, CONV, SEDI = 1, 2, 4, 8, 16
 SEED = 221112616
 
 
@@ -42,14 +42,18 @@ class OrcMet(ctypes.Structure):
                 ("dt_met", ctypes.c_double), ("u", ctypes.POINTER(ctypes.c_float)),
                 ("v", ctypes.POINTER(ctypes.c_float)), ("w", ctypes.POINTER(ctypes.c_float)),
                 ("analytic", ctypes.c_int32), ("pad_", ctypes.c_int32),
-                ("an_u0", ctypes.c_double), ("an_alpha", ctypes.c_double)]
+                ("an_u0", ctypes.c_double), ("an_alpha", ctypes.c_double),
+                ("temp", ctypes.POINTER(ctypes.c_float)), ("cape", ctypes.POINTER(ctypes.c_float)),
+                ("pel", ctypes.POINTER(ctypes.c_float)), ("ps", ctypes.POINTER(ctypes.c_float))]
 
 
 class OrcCtl(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("t_start", ctypes.c_double),
                 ("turb_dx", ctypes.c_double), ("turb_dz", ctypes.c_double),
                 ("meso_fh", ctypes.c_double), ("meso_fv", ctypes.c_double),
-                ("seed", ctypes.c_uint64), ("flags", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+                ("seed", ctypes.c_uint64), ("flags", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("conv_cape", ctypes.c_double), ("sedi_r", ctypes.c_double),
+                ("sedi_rho", ctypes.c_double)]
 
 
 _lib: Optional[ctypes.CDLL] = None
@@ -79,6 +83,8 @@ def lib() -> ctypes.CDLL:
         L.orc_stencil81_many.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.c_double, P]
         L.orc_displacement_many.argtypes = [P, P, ctypes.c_int64, P, P, P, ctypes.c_uint32,
                                             ctypes.c_int32, P, ctypes.c_int32]
+        L.orc_settling_velocity.argtypes = [ctypes.c_double] * 4
+        L.orc_settling_velocity.restype = ctypes.c_double
         L.orc_uniform.argtypes = [ctypes.c_uint32]
         L.orc_uniform.restype = ctypes.c_double
         L.orc_max_threads.restype = ctypes.c_int
@@ -100,13 +106,25 @@ class Met:
         self.v = np.ascontiguousarray(met.v, np.float32)
         self.w = np.ascontiguousarray(met.w, np.float32)
         fp = ctypes.POINTER(ctypes.c_float)
+        # convection / sedimentation fields (absent: null pointers)
+        self.temp = self.cape = self.pel = self.ps = None
+        if getattr(met, "temp", None) is not None:
+            self.temp = np.ascontiguousarray(met.temp, np.float32)
+            self.cape = np.ascontiguousarray(met.cape, np.float32)
+            self.pel = np.ascontiguousarray(met.pel, np.float32)
+            self.ps = np.ascontiguousarray(met.ps, np.float32)
+
+        def opt(a):
+            return a.ctypes.data_as(fp) if a is not None else None
+
         self.s = OrcMet(nx=met.nx, ny=met.ny, nz=met.nz, nt=met.nt, lon0=met.lon0,
                         dlon=met.dlon, lat0=met.lat0, dlat=met.dlat,
                         plev=self.plev.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                         t_met0=met.t_met0, dt_met=met.dt_met,
                         u=self.u.ctypes.data_as(fp), v=self.v.ctypes.data_as(fp),
                         w=self.w.ctypes.data_as(fp), analytic=int(analytic), pad_=0,
-                        an_u0=an_u0, an_alpha=an_alpha)
+                        an_u0=an_u0, an_alpha=an_alpha, temp=opt(self.temp),
+                        cape=opt(self.cape), pel=opt(self.pel), ps=opt(self.ps))
 
     @property
     def ref(self):
@@ -115,9 +133,17 @@ class Met:
 
 def ctl(dt: float = 180.0, t_start: float = 0.0, turb_dx: float = 50.0, turb_dz: float = 0.1,
         meso_fh: float = 0.16, meso_fv: float = 0.16, seed: int = SEED,
-        flags: int = ADVECT | TURB | MESO) -> OrcCtl:
+        flags: int = ADVECT | TURB | MESO, conv_cape: float = 500.0, sedi_r: float = 5e-6,
+        sedi_rho: float = 1000.0) -> OrcCtl:
     return OrcCtl(dt=dt, t_start=t_start, turb_dx=turb_dx, turb_dz=turb_dz, meso_fh=meso_fh,
-                  meso_fv=meso_fv, seed=seed, flags=flags, pad_=0)
+                  meso_fv=meso_fv, seed=seed, flags=flags, pad_=0, conv_cape=conv_cape,
+                  sedi_r=sedi_r, sedi_rho=sedi_rho)
+
+
+def settling_velocity(r: float, rho_p: float, p: float, T: float) -> float:
+    """Settling velocity [m/s] of a sphere (radius r [m], density rho_p
+    [kg/m^3]) in air at p [hPa], T [K] (module_sedi reading)."""
+    return lib().orc_settling_velocity(r, rho_p, p, T)
 
 
 def run(m: Met, c: OrcCtl, part, step0: int, nsteps: int, release: Optional[np.ndarray] = None,

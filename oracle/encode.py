@@ -54,12 +54,19 @@ def decode_level(q: np.ndarray, s: np.ndarray, kind: int) -> np.ndarray:
 
 
 def dequantized_met(met, kind: int):
-    """A copy of an ``inputs.Met`` whose u, v, w hold the decoded stored
-    values (what a reduced-precision run actually interpolates)."""
+    """A copy of an ``inputs.Met`` whose u, v, w (and temperature, when
+    present: the fourth value of each record, with its own per-level scale)
+    hold the decoded stored values (what a reduced-precision run actually
+    interpolates).  The surface fields are stored in FP32 and stay as they
+    are."""
     import dataclasses
     out = dataclasses.replace(met, u=np.empty_like(met.u), v=np.empty_like(met.v),
                               w=np.empty_like(met.w))
-    for name in ("u", "v", "w"):
+    names = ("u", "v", "w")
+    if getattr(met, "temp", None) is not None:
+        out.temp = np.empty_like(met.temp)
+        names = names + ("temp",)
+    for name in names:
         src, dst = getattr(met, name), getattr(out, name)
         for l in range(met.nt):
             q, s = encode_level(src[l], kind)

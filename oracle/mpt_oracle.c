@@ -24,7 +24,15 @@
  *     Sec. 4.1 data regions);
  *   - pole reflection, lon wrap to [0, 360), p clamp (module_position);
  *   - activity gating: non-finite or not-yet-released parcels are skipped
- *     (module_timesteps, Sec. 4.3).
+ *     (module_timesteps, Sec. 4.3);
+ *   - unresolved convection (module_convection, Sec. 3.2): where the CAPE at
+ *     the parcel reaches a threshold and the parcel is below the equilibrium
+ *     level, it is placed at a pressure drawn uniformly between the surface
+ *     and the equilibrium level (one uniform per parcel and step, the
+ *     `convection` slot of randoms_t, Sec. 4.3);
+ *   - sedimentation (module_sedi, Sec. 3.2): Stokes settling of a sphere
+ *     with the Cunningham slip correction, air viscosity by Sutherland's law,
+ *     converted to pressure with the scale height of the turbulent step.
  *
  * Build: gcc -O2 -fopenmp -ffp-contract=off -shared -fPIC (no -ffast-math).
  */
@@ -39,9 +47,14 @@
 #define ORC_H0        7000.0             /* scale height for dz -> dp [m]   */
 #define ORC_LAT_CAP   89.999             /* cos(lat) floor latitude [deg]   */
 
+#define ORC_G0        9.80665            /* standard gravity [m/s^2]        */
+#define ORC_RD        287.058            /* gas constant of dry air [J/kg/K] */
+
 #define ORC_ADVECT 1
 #define ORC_TURB   2
 #define ORC_MESO   4
+#define ORC_CONV   8
+#define ORC_SEDI   16
 
 /* Met fields on a regular lon-lat grid with fixed pressure levels.
  * u, v in m/s, w in hPa/s; index ((l*nz + k)*ny + j)*nx + i. */
@@ -54,6 +67,10 @@ typedef struct {
     int32_t analytic;            /* 0: gridded winds; 1: solid-body rotation */
     int32_t pad_;
     double an_u0, an_alpha;      /* rotation speed [m/s], axis tilt [rad]   */
+    /* convection and sedimentation: temperature [K] as u; CAPE [J/kg],
+     * equilibrium-level and surface pressure [hPa] per (l, j, i) */
+    const float *temp;
+    const float *cape, *pel, *ps;
 } orc_met;
 
 typedef struct {
@@ -61,8 +78,11 @@ typedef struct {
     double turb_dx, turb_dz;     /* m^2/s                                    */
     double meso_fh, meso_fv;     /* dimensionless                            */
     uint64_t seed;
-    int32_t flags;               /* ORC_ADVECT | ORC_TURB | ORC_MESO        */
+    int32_t flags;               /* ORC_ADVECT | ORC_TURB | ORC_MESO |
+                                    ORC_CONV | ORC_SEDI                      */
     int32_t pad_;
+    double conv_cape;            /* CAPE threshold [J/kg]                    */
+    double sedi_r, sedi_rho;     /* particle radius [m], density [kg/m^3]    */
 } orc_ctl;
 
 /* ======================================================================= */
@@ -346,8 +366,78 @@ static void orc_meso(const orc_met *m, const orc_ctl *c, double t_mid, const dou
     *p += dp;
 }
 
+/* Bilinear in (lon, lat) at both time levels, then linear in time, of a
+ * field with one value per (l, j, i). */
+static double orc_interp_2d(const orc_met *m, const float *f, const orc_loc *L)
+{
+    double lev[2];
+    for (int dl = 0; dl < 2; ++dl) {
+        size_t r0 = ((size_t)(L->l + dl) * m->ny + L->j) * (size_t)m->nx;
+        size_t r1 = r0 + (size_t)m->nx;
+        double y0 = orc_lerp(f[r0 + L->i0], f[r0 + L->i1], L->fx);
+        double y1 = orc_lerp(f[r1 + L->i0], f[r1 + L->i1], L->fx);
+        lev[dl] = orc_lerp(y0, y1, L->fy);
+    }
+    return orc_lerp(lev[0], lev[1], L->ft);
+}
+
+/* Unresolved convection: CAPE, equilibrium level pel and surface pressure ps
+ * at the parcel (time t_mid); where CAPE >= the threshold and the parcel is
+ * below the equilibrium level (p > pel), the new pressure is
+ * ps + (pel - ps) u with u uniform on (0, 1): equal pressure intervals hold
+ * equal air mass, so the column between surface and equilibrium level is
+ * mixed by mass.  u is the first word of the Philox block of counter
+ * (id, step, 5, 0). */
+static void orc_convection(const orc_met *m, const orc_ctl *c, uint32_t id, uint32_t step,
+                           double t_mid, double lon, double lat, double *p)
+{
+    orc_loc L;
+    orc_locate(m, lon, lat, *p, t_mid, &L);
+    double cape = orc_interp_2d(m, m->cape, &L);
+    double pel = orc_interp_2d(m, m->pel, &L);
+    double ps = orc_interp_2d(m, m->ps, &L);
+    if (!(cape >= c->conv_cape) || !(*p > pel)) return;
+    uint32_t ctr[4] = {id, step, 5u, 0u};
+    uint32_t key[2] = {(uint32_t)c->seed, (uint32_t)(c->seed >> 32)};
+    uint32_t x[4];
+    orc_philox4x32_10(ctr, key, x);
+    *p = ps + (pel - ps) * orc_uniform(x[0]);
+}
+
+/* Settling velocity [m/s] of a sphere of radius r [m] and density rho_p
+ * [kg/m^3] in air at pressure p [hPa] and temperature T [K]: Stokes drag
+ * with the Cunningham slip correction
+ *   v = 2 r^2 (rho_p - rho) g Cc / (9 eta),
+ *   Cc = 1 + Kn (1.257 + 0.4 exp(-1.1 / Kn)),  Kn = lambda / r,
+ *   lambda = 2 eta / (rho vbar),  vbar = sqrt(8 R_d T / pi),
+ *   rho = 100 p / (R_d T),  eta = 1.458e-6 T^1.5 / (T + 110.4)  (Sutherland). */
+double orc_settling_velocity(double r, double rho_p, double p, double T)
+{
+    double rho = 100.0 * p / (ORC_RD * T);
+    double eta = 1.458e-6 * T * sqrt(T) / (T + 110.4);
+    double vbar = sqrt(8.0 * ORC_RD * T / ORC_PI);
+    double lambda = 2.0 * eta / (rho * vbar);
+    double kn = lambda / r;
+    double cc = 1.0 + kn * (1.257 + 0.4 * exp(-1.1 / kn));
+    return 2.0 * r * r * (rho_p - rho) * ORC_G0 * cc / (9.0 * eta);
+}
+
+/* Sedimentation: the parcel sinks v dt metres; dp = p v dt / H0 (the
+ * scale-height conversion of the turbulent step).  T at the parcel, time
+ * t_mid. */
+static void orc_sedi(const orc_met *m, const orc_ctl *c, double t_mid, double lon, double lat,
+                     double *p)
+{
+    orc_loc L;
+    orc_locate(m, lon, lat, *p, t_mid, &L);
+    double T = orc_interp_var(m, m->temp, &L);
+    double v = orc_settling_velocity(c->sedi_r, c->sedi_rho, *p, T);
+    *p += (*p) * v * c->dt / ORC_H0;
+}
+
 /* one time step of one parcel, in the order advection, position,
- * turbulent diffusion, mesoscale diffusion, position */
+ * turbulent diffusion, mesoscale diffusion, position, convection,
+ * sedimentation, position */
 static void orc_step_one(const orc_met *m, const orc_ctl *c, uint32_t step, uint32_t id,
                          int32_t release, double *lon, double *lat, double *p,
                          double *up, double *vp, double *wp)
@@ -369,6 +459,11 @@ static void orc_step_one(const orc_met *m, const orc_ctl *c, uint32_t step, uint
             orc_normals3(c->seed, id, step, 1u, xi);
             orc_meso(m, c, t + 0.5 * c->dt, xi, lon, lat, p, up, vp, wp);
         }
+        orc_position(m, lon, lat, p);
+    }
+    if (c->flags & (ORC_CONV | ORC_SEDI)) {
+        if (c->flags & ORC_CONV) orc_convection(m, c, id, step, t + 0.5 * c->dt, *lon, *lat, p);
+        if (c->flags & ORC_SEDI) orc_sedi(m, c, t + 0.5 * c->dt, *lon, *lat, p);
         orc_position(m, lon, lat, p);
     }
 }

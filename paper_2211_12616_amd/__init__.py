@@ -26,7 +26,7 @@ STATUS = {0: "MPT_OK", -1: "MPT_ERR_ARG", -2: "MPT_ERR_STATE", -3: "MPT_ERR_TIME
           -4: "MPT_ERR_WORKSPACE", -5: "MPT_ERR_HIP", -6: "MPT_ERR_UNSUPPORTED"}
 MATH_F64, MATH_F32 = 0, 1
 DT_F32, DT_BF16, DT_F16 = 0, 1, 2
-ADVECT, TURB, MESO = 1, 2, 4
+ADVECT, TURB, MESO, CONV, SEDI = 1, 2, 4, 8, 16
 SEED = 221112616
 
 
@@ -56,7 +56,9 @@ class Params(ctypes.Structure):
                 ("turb_dx", ctypes.c_double), ("turb_dz", ctypes.c_double),
                 ("meso_fh", ctypes.c_double), ("meso_fv", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("sort_interval", ctypes.c_int32),
-                ("math", ctypes.c_int32), ("flags", ctypes.c_uint32), ("fuse", ctypes.c_int32)]
+                ("math", ctypes.c_int32), ("flags", ctypes.c_uint32), ("fuse", ctypes.c_int32),
+                ("conv_cape", ctypes.c_double), ("sedi_radius", ctypes.c_double),
+                ("sedi_density", ctypes.c_double)]
 
 
 class ParticlesC(ctypes.Structure):
@@ -75,6 +77,12 @@ def lib() -> ctypes.CDLL:
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: the HIP library has not been built")
+        # torch carries its own HIP runtime under the same soname as the
+        # system's.  Loaded first, it is the one the library binds to; loaded
+        # after the library, it would be a second runtime in the process that
+        # does not know the library's allocations, nor the library its
+        # tensors (device copies into a torch workspace then fail).
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         P, S = ctypes.c_void_p, ctypes.c_int
         L.mpt_workspace_bytes.argtypes = [P, P, ctypes.c_int64]
@@ -100,6 +108,7 @@ def lib() -> ctypes.CDLL:
         L.mpt_surrogate_forward.argtypes = [P, ctypes.c_int64, P, P, P]
         L.mpt_step_surrogate.argtypes = [P, P, ctypes.c_uint32, ctypes.c_int32, P, P, P]
         L.mpt_push_met.argtypes = [P, P, P, P, P]
+        L.mpt_set_met_phys.argtypes = [P, ctypes.c_int32, P, P, P, P, P]
         L.mpt_set_hybrid.argtypes = [P, ctypes.c_int32, P, P, P]
         L.mpt_ml_to_pl.argtypes = [P, P, P, P, P, P, P, P, P]
         L.mpt_set_outgrid.argtypes = [P, P, P]
@@ -113,7 +122,7 @@ def lib() -> ctypes.CDLL:
                    "mpt_surrogate_init", "mpt_surrogate_train_step", "mpt_surrogate_grad",
                    "mpt_surrogate_load", "mpt_surrogate_forward", "mpt_step_surrogate",
                    "mpt_set_outgrid", "mpt_grid_output", "mpt_push_met", "mpt_set_hybrid",
-                   "mpt_ml_to_pl"):
+                   "mpt_ml_to_pl", "mpt_set_met_phys"):
             getattr(L, fn).restype = S
         _lib = L
     return _lib
@@ -126,7 +135,8 @@ def exported_symbols():
             "mpt_status_string", "mpt_surrogate_datagen", "mpt_surrogate_stats",
             "mpt_surrogate_init", "mpt_surrogate_train_step", "mpt_surrogate_grad",
             "mpt_surrogate_load", "mpt_surrogate_forward", "mpt_step_surrogate",
-            "mpt_set_outgrid", "mpt_grid_output", "mpt_push_met", "mpt_set_hybrid", "mpt_ml_to_pl"]
+            "mpt_set_outgrid", "mpt_grid_output", "mpt_push_met", "mpt_set_hybrid", "mpt_ml_to_pl",
+            "mpt_set_met_phys"]
 
 SURR_K, SURR_NIN, SURR_NOUT, SURR_NPARAM, SURR_MAX_BATCH = 8, 81, 3, 47504, 8192
 
@@ -149,10 +159,11 @@ def make_grid(met, dtype: int = DT_F32) -> tuple[Grid, np.ndarray]:
 
 def make_params(dt=180.0, t_start=0.0, turb_dx=50.0, turb_dz=0.1, meso_fh=0.16, meso_fv=0.16,
                 seed=SEED, sort_interval=0, math=MATH_F64, flags=ADVECT | TURB | MESO,
-                fuse=1) -> Params:
+                fuse=1, conv_cape=500.0, sedi_radius=5e-6, sedi_density=1000.0) -> Params:
     return Params(dt=dt, t_start=t_start, turb_dx=turb_dx, turb_dz=turb_dz, meso_fh=meso_fh,
                   meso_fv=meso_fv, seed=seed, sort_interval=sort_interval, math=math,
-                  flags=flags, fuse=fuse)
+                  flags=flags, fuse=fuse, conv_cape=conv_cape, sedi_radius=sedi_radius,
+                  sedi_density=sedi_density)
 
 
 def _stream_handle(stream) -> Optional[int]:
@@ -298,8 +309,18 @@ class Context:
         _check("mpt_push_met", lib().mpt_push_met(self.h, u.data_ptr(), v.data_ptr(), w.data_ptr(),
                                                   _stream_handle(stream)))
 
+    def set_met_phys(self, level: int, temp, cape, pel, ps, stream=None):
+        """mpt_set_met_phys: temperature [nz, ny, nx] and CAPE, equilibrium-level
+        and surface pressure [ny, nx] (torch float32 cuda) of a resident level."""
+        for t in (temp, cape, pel, ps):
+            assert t.is_cuda and t.dtype.itemsize == 4 and t.is_contiguous()
+        _check("mpt_set_met_phys", lib().mpt_set_met_phys(self.h, level, temp.data_ptr(),
+                                                          cape.data_ptr(), pel.data_ptr(),
+                                                          ps.data_ptr(), _stream_handle(stream)))
+
     def upload_met(self, met, stream=None):
-        """Store the first grid.nt time levels of an ``inputs.Met`` (host float32)."""
+        """Store the first grid.nt time levels of an ``inputs.Met`` (host float32),
+        with its convection / sedimentation fields when it has them."""
         import torch
         for l in range(self.grid.nt):
             u = torch.from_numpy(met.u[l]).cuda()
@@ -308,6 +329,12 @@ class Context:
             self.init_met(l, u, v, w, stream)
             torch.cuda.current_stream().synchronize()
             del u, v, w
+            if getattr(met, "temp", None) is not None:
+                f = [torch.from_numpy(np.ascontiguousarray(a[l])).cuda()
+                     for a in (met.temp, met.cape, met.pel, met.ps)]
+                self.set_met_phys(l, *f, stream=stream)
+                torch.cuda.current_stream().synchronize()
+                del f
 
     def met_level_bytes(self) -> int:
         return lib().mpt_met_level_bytes(self.h)

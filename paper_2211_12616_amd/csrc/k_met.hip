@@ -1,5 +1,6 @@
 // k_met.hip -- storing meteorological time levels in the kernel layout:
-// one {u, v, w, 0} record per grid point, longitude fastest, so that a cell
+// one {u, v, w, T} record per grid point (T, the temperature, is 0 unless
+// stored for convection / sedimentation), longitude fastest, so that a cell
 // corner is one 16-byte (F32) or 8-byte (BF16 / F16) load.  Reduced
 // precision stores q = RNE(f * (1/s)) with s = max|f| per (variable, level).
 #include "mpt_internal.h"
@@ -75,6 +76,39 @@ __global__ __launch_bounds__(256) void k_pack_r16(const float *__restrict__ u,
   }
 }
 
+// Temperature into the fourth value of each record of a stored level (the
+// other three are left as they are).  F32: the float itself; R16: the code
+// of T / s with the level's temperature scale s.
+__global__ __launch_bounds__(256) void k_pack_temp_f32(const float *__restrict__ T,
+                                                       float4 *__restrict__ dst, int64_t npts) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < npts; q += stride)
+    reinterpret_cast<float *>(dst + q)[3] = T[q];
+}
+
+template <int F>
+__global__ __launch_bounds__(256) void k_pack_temp_r16(const float *__restrict__ T,
+                                                       const float *__restrict__ scales,
+                                                       ushort4 *__restrict__ dst, int64_t nxy, int nz) {
+  const int64_t npts = nxy * nz;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < npts; q += stride) {
+    const int k = (int)(q / nxy);
+    const float a = __fmul_rn(T[q], __fdiv_rn(1.0f, scales[k]));
+    reinterpret_cast<unsigned short *>(dst + q)[3] = F == kBF16 ? to_bf16_rne(a) : to_f16_rne(a);
+  }
+}
+
+// Surface records {cape, pel, ps, 0}.
+__global__ __launch_bounds__(256) void k_pack_sfc(const float *__restrict__ cape,
+                                                  const float *__restrict__ pel,
+                                                  const float *__restrict__ ps,
+                                                  float4 *__restrict__ dst, int64_t nxy) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nxy; q += stride)
+    dst[q] = make_float4(cape[q], pel[q], ps[q], 0.0f);
+}
+
 __global__ __launch_bounds__(256) void k_fill_f32(float *dst, float value, int64_t n) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) dst[q] = value;
@@ -108,6 +142,32 @@ hipError_t launch_pack_r16(int field, const float *u, const float *v, const floa
     hipLaunchKernelGGL(k_pack_r16<kBF16>, dim3(g), dim3(256), 0, stream, u, v, w, scales, dst, nxy, nz);
   else
     hipLaunchKernelGGL(k_pack_r16<kF16>, dim3(g), dim3(256), 0, stream, u, v, w, scales, dst, nxy, nz);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_temp(int field, const float *T, float *t_scales, void *dst, int64_t nxy, int nz,
+                            hipStream_t stream) {
+  const unsigned g = grid_for(nxy * nz);
+  if (field == kF32) {
+    hipLaunchKernelGGL(k_pack_temp_f32, dim3(g), dim3(256), 0, stream, T, static_cast<float4 *>(dst),
+                       nxy * nz);
+    return hipGetLastError();
+  }
+  // one block per level: max |T| into t_scales[k] (the u slot of the kernel)
+  hipLaunchKernelGGL(k_level_absmax, dim3((unsigned)nz, 1), dim3(256), 0, stream, T, T, T, nxy, nz,
+                     t_scales);
+  if (field == kBF16)
+    hipLaunchKernelGGL(k_pack_temp_r16<kBF16>, dim3(g), dim3(256), 0, stream, T, t_scales,
+                       static_cast<ushort4 *>(dst), nxy, nz);
+  else
+    hipLaunchKernelGGL(k_pack_temp_r16<kF16>, dim3(g), dim3(256), 0, stream, T, t_scales,
+                       static_cast<ushort4 *>(dst), nxy, nz);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_sfc(const float *cape, const float *pel, const float *ps, float4 *dst, int64_t nxy,
+                           hipStream_t stream) {
+  hipLaunchKernelGGL(k_pack_sfc, dim3(grid_for(nxy)), dim3(256), 0, stream, cape, pel, ps, dst, nxy);
   return hipGetLastError();
 }
 

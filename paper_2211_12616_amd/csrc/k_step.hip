@@ -8,13 +8,14 @@
 // that walks 256-parcel chunks of the active prefix of a scenario run, whose
 // length it reads from device memory; the same walk over a device list of
 // parcel indices in increasing order, whose length it reads from device
-// memory.
+// memory.  Convection and sedimentation are compiled into kernels of their
+// own (k_step_phys_*), so the plain kernels keep their code and registers.
 #include "mpt_device.h"
 #include "mpt_internal.h"
 
 namespace mpt {
 
-template <int F, typename R>
+template <int F, typename R, bool P>
 __device__ __forceinline__ void step_parcel(const StepArgs &a, const double *s_plev,
                                             const double *s_idp, const uint16_t *s_lut, int64_t i,
                                             uint32_t step0) {
@@ -45,6 +46,14 @@ __device__ __forceinline__ void step_parcel(const StepArgs &a, const double *s_p
       if (a.flags & kTurb) turb<R>(a, id, step, lon, lat, p);
       if (do_meso) meso<F, R>(a, s_plev, s_idp, s_lut, id, step, t + 0.5 * a.dt, lon, lat, p, up, vp, wp);
       position(a, lon, lat, p);
+    }
+    if constexpr (P) {
+      if (a.flags & (kConv | kSedi)) {
+        const double t_mid = t + 0.5 * a.dt;
+        if (a.flags & kConv) convection<F, R>(a, s_plev, s_idp, s_lut, id, step, t_mid, lon, lat, p);
+        if (a.flags & kSedi) sedimentation<F, R>(a, s_plev, s_idp, s_lut, t_mid, lon, lat, p);
+        position(a, lon, lat, p);
+      }
     }
   }
   if (!moved) return;
@@ -81,7 +90,7 @@ __device__ __forceinline__ int64_t active_bound(const StepArgs &a, uint32_t last
 
 enum : int { kModeBlock = 0, kModePersistent = 1, kModeIndex = 2 };
 
-template <int M, int F, typename R>
+template <int M, int F, typename R, bool P>
 __device__ __forceinline__ void step_body(const StepArgs &a) {
   __shared__ double s_plev[kMaxLevels];
   __shared__ double s_idp[kMaxLevels];
@@ -104,13 +113,13 @@ __device__ __forceinline__ void step_body(const StepArgs &a) {
     const int64_t c_lo = nchunks * xcd / kXcds, c_hi = nchunks * (xcd + 1) / kXcds;
     for (int64_t c = c_lo + q; c < c_hi; c += nq) {
       const int64_t j = c * kBlock + threadIdx.x;
-      if (j < cnt) step_parcel<F, R>(a, s_plev, s_idp, s_lut, (int64_t)a.index[j], step0);
+      if (j < cnt) step_parcel<F, R, P>(a, s_plev, s_idp, s_lut, (int64_t)a.index[j], step0);
     }
   } else if constexpr (M == kModeBlock) {
     const int lb = logical_block((int)blockIdx.x, a.per_xcd);
     if (lb >= a.nblk) return;
     const int64_t i = (int64_t)lb * kBlock + threadIdx.x;
-    if (i < a.n) step_parcel<F, R>(a, s_plev, s_idp, s_lut, i, step0);
+    if (i < a.n) step_parcel<F, R, P>(a, s_plev, s_idp, s_lut, i, step0);
   } else {
     // persistent: XCD x owns an even share of the chunks of the prefix and
     // its blocks stride through that share
@@ -121,7 +130,7 @@ __device__ __forceinline__ void step_body(const StepArgs &a) {
     const int64_t c_lo = nchunks * xcd / kXcds, c_hi = nchunks * (xcd + 1) / kXcds;
     for (int64_t c = c_lo + q; c < c_hi; c += nq) {
       const int64_t i = c * kBlock + threadIdx.x;
-      if (i < bound) step_parcel<F, R>(a, s_plev, s_idp, s_lut, i, step0);
+      if (i < bound) step_parcel<F, R, P>(a, s_plev, s_idp, s_lut, i, step0);
     }
   }
 }
@@ -129,13 +138,25 @@ __device__ __forceinline__ void step_body(const StepArgs &a) {
 template <int M>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MPT_WAVES_F64)))
 void k_step_f64(const StepArgs a) {
-  step_body<M, kF32, double>(a);
+  step_body<M, kF32, double, false>(a);
 }
 
 template <int M, int F>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MPT_WAVES_F32)))
 void k_step_f32(const StepArgs a) {
-  step_body<M, F, float>(a);
+  step_body<M, F, float, false>(a);
+}
+
+template <int M>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MPT_WAVES_F64)))
+void k_step_phys_f64(const StepArgs a) {
+  step_body<M, kF32, double, true>(a);
+}
+
+template <int M, int F>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MPT_WAVES_F32)))
+void k_step_phys_f32(const StepArgs a) {
+  step_body<M, F, float, true>(a);
 }
 
 template <int M>
@@ -155,8 +176,31 @@ static hipError_t launch_mode(int field, int math_f64, const StepArgs &args, dim
   return hipGetLastError();
 }
 
+// Convection / sedimentation kernels: block and persistent shapes only.
+template <int M>
+static hipError_t launch_phys(int field, int math_f64, const StepArgs &args, dim3 grid,
+                              hipStream_t stream) {
+  const dim3 block(kBlock);
+  if (math_f64) {
+    if (field != kF32) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_step_phys_f64<M>, grid, block, 0, stream, args);
+  } else if (field == kF32) {
+    hipLaunchKernelGGL((k_step_phys_f32<M, kF32>), grid, block, 0, stream, args);
+  } else if (field == kBF16) {
+    hipLaunchKernelGGL((k_step_phys_f32<M, kBF16>), grid, block, 0, stream, args);
+  } else {
+    hipLaunchKernelGGL((k_step_phys_f32<M, kF16>), grid, block, 0, stream, args);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_step(int field, int math_f64, const StepArgs &args, hipStream_t stream) {
   const dim3 grid((unsigned)(args.persistent ? args.nblk : args.per_xcd * kXcds));
+  if (args.flags & (kConv | kSedi)) {
+    if (args.index) return hipErrorInvalidValue;
+    if (args.persistent) return launch_phys<kModePersistent>(field, math_f64, args, grid, stream);
+    return launch_phys<kModeBlock>(field, math_f64, args, grid, stream);
+  }
   if (args.index) return launch_mode<kModeIndex>(field, math_f64, args, grid, stream);
   if (args.persistent) return launch_mode<kModePersistent>(field, math_f64, args, grid, stream);
   return launch_mode<kModeBlock>(field, math_f64, args, grid, stream);

@@ -18,13 +18,14 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr double kREarth = 6371000.0;                 // m
 constexpr double kH0 = 7000.0;                        // scale height, dz -> dp [m]
 constexpr double kDeg = 180.0 / (kPi * kREarth);      // metres -> degrees of arc
-constexpr double kG = 9.80665;                        // m s^-2 (box air mass)
+constexpr double kG = 9.80665;                        // m s^-2 (box air mass, settling)
+constexpr double kRd = 287.058;                       // gas constant of dry air [J/(kg K)]
 constexpr int kMaxLevels = 512;                       // LDS level table capacity
 constexpr int kLutBins = 8192;                        // level lookup bins over log2(p)
 constexpr int kBlock = 256;                           // 4 wave64 per block
 constexpr int kXcds = 8;                              // MI355X: 8 XCDs, 32 CUs each
 
-enum : uint32_t { kAdvect = 1u, kTurb = 2u, kMeso = 4u };
+enum : uint32_t { kAdvect = 1u, kTurb = 2u, kMeso = 4u, kConv = 8u, kSedi = 16u };
 enum FieldKind { kF32 = 0, kBF16 = 1, kF16 = 2 };
 
 // Arguments of the step kernels, passed by value.
@@ -79,6 +80,12 @@ struct StepArgs {
   // r^k, and the Cholesky factor (l11, l21, l22) of the covariance of
   // (sum_j B_j xi_j, sum_j r^(k-1-j) xi_j), B_j = 1 + r + ... + r^(k-1-j).
   double agg_sh, agg_sz, agg_a, agg_rk, agg_l11, agg_l21, agg_l22;
+  // Convection and sedimentation: surface records {cape, pel, ps, 0} per
+  // (ring slot, j, i); temperature scales per (ring slot, level) for R16
+  // storage; CAPE threshold, particle radius and density.
+  const float4 *sfc;
+  const float *t_scales;
+  double conv_cape, sedi_r, sedi_rho;
 };
 
 // Map the hardware block index to a logical block so that each XCD walks a
@@ -118,6 +125,7 @@ template <> struct Math<double> {
   // ln of a uniform in (0, 1): always a positive normal number
   static __device__ __forceinline__ double log_(double x) { return m64::ln_pos(x); }
   static __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
+  static __device__ __forceinline__ double exp_(double x) { return exp(x); }
   // sin(pi x), cos(pi x) for x in [0, 2] (twice a uniform)
   static __device__ __forceinline__ void sincospi_(double x, double *s, double *c) {
     m64::sincospi_02(x, s, c);
@@ -144,6 +152,7 @@ template <> struct Math<float> {
   }
   static __device__ __forceinline__ float log_(float x) { return __logf(x); }
   static __device__ __forceinline__ float sqrt_(float x) { return __fsqrt_rn(x); }
+  static __device__ __forceinline__ float exp_(float x) { return __expf(x); }
   static __device__ __forceinline__ void sincospi_(float x, float *s, float *c) {
     __sincosf(x * (float)kPi, s, c);
   }
@@ -547,6 +556,123 @@ __device__ __forceinline__ void meso(const StepArgs &a, const double *s_plev, co
   R sg[3];
   meso_sigma<F, R>(a, s_plev, s_idp, s_lut, t_mid, lon, lat, p, sg);
   meso_apply<R>(a, sg, xi, lon, lat, p, up, vp, wp);
+}
+
+// ---- convection and sedimentation ---------------------------------------------
+
+// Temperature at the parcel: the fourth value of the 16 records of its cell
+// (R16 storage: decoded with the temperature scale of the (slot, level)),
+// time weight first, then lon, lat and p as in interp_cell.  Only that value
+// is loaded from each record.
+template <int F, typename R>
+__device__ __forceinline__ R interp_temp(const StepArgs &a, const Loc<R> &L) {
+  using T = typename Rec<F>::T;
+  const T *base = reinterpret_cast<const T *>(a.met);
+  const int nxy = a.nx * a.ny;
+  const int r0 = L.k * nxy + L.j * a.nx;
+  R cv[2][2][2];
+#pragma unroll
+  for (int dk = 0; dk < 2; ++dk)
+#pragma unroll
+    for (int dj = 0; dj < 2; ++dj)
+#pragma unroll
+      for (int di = 0; di < 2; ++di) {
+        R v[2];
+#pragma unroll
+        for (int dl = 0; dl < 2; ++dl) {
+          const int slot = dl ? L.l1 : L.l;
+          const T *rec = base + (int64_t)slot * a.level_elems + r0 + dk * nxy + dj * a.nx + (di ? L.i1 : L.i0);
+          if constexpr (F == kF32) {
+            v[dl] = (R)reinterpret_cast<const float *>(rec)[3];
+          } else {
+            const float sc = a.t_scales[slot * a.nz + L.k + dk];
+            v[dl] = (R)(dec<F>(reinterpret_cast<const unsigned short *>(rec)[3]) * sc);
+          }
+        }
+        cv[dk][dj][di] = lerp(v[0], v[1], L.ft);
+      }
+  R yk[2];
+#pragma unroll
+  for (int dk = 0; dk < 2; ++dk) {
+    const R x0 = lerp(cv[dk][0][0], cv[dk][0][1], L.fx);
+    const R x1 = lerp(cv[dk][1][0], cv[dk][1][1], L.fx);
+    yk[dk] = lerp(x0, x1, L.fy);
+  }
+  return lerp(yk[0], yk[1], L.fz);
+}
+
+// CAPE, equilibrium-level and surface pressure at the parcel: bilinear in
+// (lon, lat) after the time weight at each of the 4 columns.
+template <typename R>
+__device__ __forceinline__ void interp_sfc(const StepArgs &a, const Loc<R> &L, R out[3]) {
+  const int64_t nxy = (int64_t)a.nx * a.ny;
+  R cv[2][2][3];
+#pragma unroll
+  for (int dj = 0; dj < 2; ++dj)
+#pragma unroll
+    for (int di = 0; di < 2; ++di) {
+      const int64_t q = (int64_t)(L.j + dj) * a.nx + (di ? L.i1 : L.i0);
+      const float4 r0 = a.sfc[(int64_t)L.l * nxy + q];
+      const float4 r1 = a.sfc[(int64_t)L.l1 * nxy + q];
+      cv[dj][di][0] = lerp((R)r0.x, (R)r1.x, L.ft);
+      cv[dj][di][1] = lerp((R)r0.y, (R)r1.y, L.ft);
+      cv[dj][di][2] = lerp((R)r0.z, (R)r1.z, L.ft);
+    }
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const R x0 = lerp(cv[0][0][q], cv[0][1][q], L.fx);
+    const R x1 = lerp(cv[1][0][q], cv[1][1][q], L.fx);
+    out[q] = lerp(x0, x1, L.fy);
+  }
+}
+
+// Unresolved convection: where the CAPE at the parcel reaches the threshold
+// and the parcel is below the equilibrium level, it moves to a pressure
+// drawn uniformly between the surface and the equilibrium level (equal
+// pressure intervals hold equal mass: the column is mixed by mass).  The
+// uniform is the first word of the Philox block (id, step, 5, 0), taken in
+// FP64 as the new pressure is.
+template <int F, typename R>
+__device__ __forceinline__ void convection(const StepArgs &a, const double *s_plev,
+                                           const double *s_idp, const uint16_t *s_lut, uint32_t id,
+                                           uint32_t step, double t_mid, double lon, double lat,
+                                           double &p) {
+  Loc<R> L;
+  locate_xyz<R>(a, s_plev, s_idp, s_lut, lon, lat, p, L);
+  locate_t<R>(a, t_mid, L);
+  R f[3];
+  interp_sfc<R>(a, L, f);
+  if (!(f[0] >= (R)a.conv_cape) || !(p > (double)f[1])) return;
+  uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+  asm("" : "+s"(k0), "+s"(k1) : "s"(step));     // round keys formed per draw, as in normals3
+  uint32_t x[4];
+  philox4x32_10(id, step, 5u, 0u, k0, k1, x);
+  const double ps = (double)f[2], pel = (double)f[1];
+  p = ps + (pel - ps) * Math<double>::uni(x[0]);
+}
+
+// Sedimentation: settling velocity of a sphere of radius r and density
+// rho_p at the parcel's pressure and interpolated temperature (Stokes drag
+// with the Cunningham slip correction; Sutherland viscosity; mean free path
+// from the mean molecular speed), the parcel sinking v dt metres:
+// dp = p v dt / H0, the scale-height conversion of the turbulent step.
+template <int F, typename R>
+__device__ __forceinline__ void sedimentation(const StepArgs &a, const double *s_plev,
+                                              const double *s_idp, const uint16_t *s_lut,
+                                              double t_mid, double lon, double lat, double &p) {
+  Loc<R> L;
+  locate_xyz<R>(a, s_plev, s_idp, s_lut, lon, lat, p, L);
+  locate_t<R>(a, t_mid, L);
+  const R T = interp_temp<F, R>(a, L);
+  const R pr = (R)p;
+  const R r = (R)a.sedi_r;
+  const R rho = (R)100 * pr / ((R)kRd * T);
+  const R eta = (R)1.458e-6 * T * Math<R>::sqrt_(T) / (T + (R)110.4);
+  const R vbar = Math<R>::sqrt_((R)(8.0 * kRd / kPi) * T);
+  const R kn = (R)2 * eta / (rho * vbar * r);
+  const R cc = (R)1 + kn * ((R)1.257 + (R)0.4 * Math<R>::exp_((R)-1.1 / kn));
+  const R v = (R)(2.0 * kG / 9.0) * r * r * ((R)a.sedi_rho - rho) * cc / eta;
+  p = p + (double)(pr * v * (R)(a.dt / kH0));
 }
 
 __device__ __forceinline__ bool finite3(double a, double b, double c) {

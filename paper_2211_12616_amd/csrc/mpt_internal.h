@@ -19,6 +19,12 @@ hipError_t launch_level_absmax(const float *u, const float *v, const float *w, i
 hipError_t launch_pack_r16(int field, const float *u, const float *v, const float *w,
                            const float *scales, ushort4 *dst, int64_t nxy, int nz,
                            hipStream_t stream);
+// Temperature into the fourth value of the records of a stored level
+// (R16: with the per-level scales t_scales[nz] it computes); surface records.
+hipError_t launch_pack_temp(int field, const float *T, float *t_scales, void *dst, int64_t nxy, int nz,
+                            hipStream_t stream);
+hipError_t launch_pack_sfc(const float *cape, const float *pel, const float *ps, float4 *dst, int64_t nxy,
+                           hipStream_t stream);
 hipError_t launch_fill_f32(float *dst, float value, int64_t n, hipStream_t stream);
 
 // Sort (k_sort.hip).

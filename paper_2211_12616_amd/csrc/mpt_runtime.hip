@@ -22,6 +22,8 @@ struct mpt_ctx {
   size_t level_bytes;     // bytes per packed level
   int64_t npts;
   float *scales;          // [nt][3][nz]
+  float *t_scales;        // [nt][nz] temperature scales (R16 storage)
+  float4 *sfc;            // [nt][ny*nx] {cape, pel, ps, 0}
   double *plev, *inv_dp;  // [nz]
   uint16_t *lut;          // [kLutBins] level lookup table
   float lut_lo, lut_scale;
@@ -34,6 +36,7 @@ struct mpt_ctx {
   // host state
   double plev_h[kMaxLevels];
   uint64_t levels_ready;  // bit l set once level l was stored (nt <= 64)
+  uint64_t phys_ready;    // bit l set once slot l has its convection / sedimentation fields
   int32_t nscen;
   // surrogate: bf16 weight copies, normalization, training scratch
   uint16_t *s_wt, *s_wb, *s_wi;
@@ -105,13 +108,17 @@ mpt_status check_params(const mpt_params *p, const mpt_grid *g) {
     return MPT_ERR_ARG;
   if (p->sort_interval < 0 || p->fuse < 1) return MPT_ERR_ARG;
   if (p->math != MPT_MATH_F64 && p->math != MPT_MATH_F32) return MPT_ERR_ARG;
-  if (p->flags & ~(uint32_t)(MPT_ADVECT | MPT_TURB | MPT_MESO)) return MPT_ERR_ARG;
+  if (p->flags & ~(uint32_t)(MPT_ADVECT | MPT_TURB | MPT_MESO | MPT_CONV | MPT_SEDI)) return MPT_ERR_ARG;
+  if ((p->flags & MPT_CONV) && !isfinite(p->conv_cape)) return MPT_ERR_ARG;
+  if ((p->flags & MPT_SEDI) && !(isfinite(p->sedi_radius) && p->sedi_radius > 0.0 &&
+                                 isfinite(p->sedi_density) && p->sedi_density > 0.0))
+    return MPT_ERR_ARG;
   if (p->math == MPT_MATH_F64 && g->dtype != MPT_DT_F32) return MPT_ERR_UNSUPPORTED;
   return MPT_OK;
 }
 
 struct Layout {
-  size_t met, scales, plev, inv_dp, lut, release, rank, rel_sorted, step_dev, keys, ranks, hist, spread,
+  size_t met, scales, t_scales, sfc, plev, inv_dp, lut, release, rank, rel_sorted, step_dev, keys, ranks, hist, spread,
       block_sums, out_pe, hyb_ab, s_wt, s_wb, s_wi, s_norm, s_bias, s_x, s_y, s_f, fb_mask, fb_off, fb_sums, t_xn, t_h, t_dy, t_dh, t_yp, t_grad, t_part, total;
   uint32_t ntx, nty, ntz, ntiles, nkeys;
   int64_t s_chunk;
@@ -135,6 +142,8 @@ Layout layout(const mpt_grid *g, int64_t n_max) {
   size_t off = 0;
   L.met = off;        off += align_up(npts * rec_bytes(g->dtype) * g->nt);
   L.scales = off;     off += align_up(sizeof(float) * 3 * g->nz * g->nt);
+  L.t_scales = off;   off += align_up(sizeof(float) * g->nz * g->nt);
+  L.sfc = off;        off += align_up((size_t)16 * g->nx * g->ny * g->nt);
   L.plev = off;       off += align_up(sizeof(double) * g->nz);
   L.inv_dp = off;     off += align_up(sizeof(double) * g->nz);
   L.lut = off;        off += align_up(sizeof(uint16_t) * kLutBins);
@@ -253,6 +262,11 @@ void fill_step_args(const mpt_ctx *c, const mpt_particles *P, uint32_t step0, in
   a.rel_sorted = c->rel_sorted;
   a.index = nullptr;
   a.index_count = nullptr;
+  a.sfc = c->sfc;
+  a.t_scales = c->t_scales;
+  a.conv_cape = q.conv_cape;
+  a.sedi_r = q.sedi_radius;
+  a.sedi_rho = q.sedi_density;
 }
 
 mpt_status check_particles(const mpt_ctx *c, const mpt_particles *P, bool need_pingpong) {
@@ -468,6 +482,8 @@ mpt_status mpt_create(const mpt_grid *grid, const mpt_params *params, int64_t n_
   c->level_bytes = (size_t)c->npts * rec_bytes(grid->dtype);
   c->met = ws + L.met;
   c->scales = reinterpret_cast<float *>(ws + L.scales);
+  c->t_scales = reinterpret_cast<float *>(ws + L.t_scales);
+  c->sfc = reinterpret_cast<float4 *>(ws + L.sfc);
   c->plev = reinterpret_cast<double *>(ws + L.plev);
   c->inv_dp = reinterpret_cast<double *>(ws + L.inv_dp);
   c->lut = reinterpret_cast<uint16_t *>(ws + L.lut);
@@ -556,9 +572,36 @@ mpt_status pack_level(mpt_ctx *c, int slot, const float *u, const float *v, cons
                           c->grid.nz, s);
   }
   if (e != hipSuccess) return MPT_ERR_HIP;
+  c->phys_ready &= ~(1ull << slot);     // the records' fourth values were cleared
   return MPT_OK;
 }
+
+// The convection / sedimentation fields must be stored on every resident
+// level when the step uses them.
+mpt_status check_phys(const mpt_ctx *c) {
+  if (!(c->params.flags & (MPT_CONV | MPT_SEDI))) return MPT_OK;
+  const uint64_t all = (c->grid.nt >= 64) ? ~0ull : ((1ull << c->grid.nt) - 1ull);
+  return (c->phys_ready & all) == all ? MPT_OK : MPT_ERR_STATE;
+}
 }  // namespace
+
+mpt_status mpt_set_met_phys(mpt_ctx *c, int32_t level, const float *temp, const float *cape,
+                            const float *pel, const float *ps, void *hip_stream) {
+  if (!c || !temp || !cape || !pel || !ps) return MPT_ERR_ARG;
+  if (level < 0 || level >= c->grid.nt) return MPT_ERR_ARG;
+  if (!aligned(temp, 4) || !aligned(cape, 4) || !aligned(pel, 4) || !aligned(ps, 4)) return MPT_ERR_ARG;
+  const int slot = (c->slot_first + level) % c->grid.nt;
+  if (!(c->levels_ready & (1ull << slot))) return MPT_ERR_STATE;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const int64_t nxy = (int64_t)c->grid.nx * c->grid.ny;
+  void *dst = static_cast<unsigned char *>(c->met) + c->level_bytes * (size_t)slot;
+  hipError_t e = launch_pack_temp(c->grid.dtype, temp, c->t_scales + (size_t)slot * c->grid.nz, dst, nxy,
+                                  c->grid.nz, s);
+  if (e == hipSuccess) e = launch_pack_sfc(cape, pel, ps, c->sfc + (size_t)slot * nxy, nxy, s);
+  if (e != hipSuccess) return MPT_ERR_HIP;
+  c->phys_ready |= 1ull << slot;
+  return MPT_OK;
+}
 
 mpt_status mpt_init_met(mpt_ctx *c, int32_t level, const float *u, const float *v, const float *w,
                         void *hip_stream) {
@@ -689,6 +732,8 @@ mpt_status mpt_step(mpt_ctx *c, mpt_particles *P, uint32_t step0, int32_t nsteps
   if (st != MPT_OK) return st;
   st = check_time(c, step0, nsteps);
   if (st != MPT_OK) return st;
+  st = check_phys(c);
+  if (st != MPT_OK) return st;
   if (P->n == 0 || nsteps == 0) return MPT_OK;
   return enqueue_steps(c, P, step0, nsteps, false, static_cast<hipStream_t>(hip_stream));
 }
@@ -703,6 +748,8 @@ mpt_status mpt_step_graph(mpt_ctx *c, mpt_particles *P, uint32_t step0, int32_t 
   mpt_status st = check_particles(c, P, nsteps > 0);
   if (st != MPT_OK) return st;
   st = check_time(c, step0, nsteps);
+  if (st != MPT_OK) return st;
+  st = check_phys(c);
   if (st != MPT_OK) return st;
   if (P->n == 0 || nsteps == 0) return MPT_OK;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
@@ -845,6 +892,7 @@ mpt_status mpt_step_surrogate(mpt_ctx *c, mpt_particles *P, uint32_t step0, int3
   if (!c || !fallbacks) return MPT_ERR_ARG;
   if (c->params.math != MPT_MATH_F32 || c->grid.dtype != MPT_DT_F32) return MPT_ERR_UNSUPPORTED;
   if (!P || P->scen) return MPT_ERR_UNSUPPORTED;
+  if (c->params.flags & (MPT_CONV | MPT_SEDI)) return MPT_ERR_UNSUPPORTED;
   if (err_out && c->params.sort_interval > 0 && nsteps > 0) return MPT_ERR_ARG;  // fixed order needed
   if (step0 % kSurrK != 0 || nsteps < 0 || nsteps % kSurrK != 0) return MPT_ERR_ARG;
   if (!c->s_loaded) return MPT_ERR_STATE;

@@ -74,7 +74,8 @@ def test_bad_grid_is_rejected(case):
     assert create(g, p, nbytes=1 << 30) == -1
 
 
-@pytest.mark.parametrize("case", ["dt", "turb", "sort", "fuse", "flags", "math"])
+@pytest.mark.parametrize("case", ["dt", "turb", "sort", "fuse", "flags", "math", "conv_cape",
+                                  "sedi_radius", "sedi_density"])
 def test_bad_params_are_rejected(case):
     g, plev, p = grid_params()
     if case == "dt":
@@ -86,7 +87,16 @@ def test_bad_params_are_rejected(case):
     elif case == "fuse":
         p.fuse = 0
     elif case == "flags":
-        p.flags = 8
+        p.flags = 32
+    elif case == "conv_cape":
+        p.flags |= mpt.CONV
+        p.conv_cape = float("nan")
+    elif case == "sedi_radius":
+        p.flags |= mpt.SEDI
+        p.sedi_radius = 0.0
+    elif case == "sedi_density":
+        p.flags |= mpt.SEDI
+        p.sedi_density = -1.0
     else:
         p.math = 3
     assert ws_bytes(g, p) == 0
@@ -151,6 +161,13 @@ def test_null_context_newer_entry_points():
     assert L.mpt_push_met(None, None, None, None, None) == -1
     assert L.mpt_set_hybrid(None, 2, None, None, None) == -1
     assert L.mpt_ml_to_pl(None, None, None, None, None, None, None, None, None) == -1
+    assert L.mpt_set_met_phys(None, 0, None, None, None, None, None) == -1
+
+
+def test_physics_flags_are_accepted():
+    g, plev, p = grid_params()
+    p.flags |= mpt.CONV | mpt.SEDI
+    assert ws_bytes(g, p) > 0
 
 
 def test_surrogate_constants_match_header():
