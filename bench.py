@@ -39,6 +39,13 @@ FLOP_PER_PS = {"f64": 1169.0, "f32": 669.0, "bf16": 813.0, "f16": 813.0}
 TRAFFIC_BYTES_PER_LAUNCH = {"f64": (2 * 3.685e6 + 4.688e6) * 1024,
                             "f32": (2 * 3.090e6 + 3.516e6) * 1024,
                             "bf16": (2 * 2.541e6 + 3.516e6) * 1024}
+# The convection / sedimentation kernel, F64 form, same workload
+# (profiles/k_step_phys_1e8_0p3deg.md): FP64 FLOP per parcel-step and HBM
+# bytes per 10-step launch (2 x FETCH_SIZE + WRITE_SIZE), with sedimentation
+# alone and with both modules.
+FLOP_PER_PS_PHYS = {"f64_sedi": 1391.0, "f64_phys": 1452.0}
+TRAFFIC_BYTES_PER_LAUNCH_PHYS = {"f64_sedi": (2 * 3.679e6 + 4.688e6) * 1024,
+                                 "f64_phys": (2 * 1.995e7 + 4.688e6) * 1024}
 METRIC = "particle-steps/s (advect+diffuse, 1e8 particles, 0.3° grid); surrogate vs plain"
 FORMS = {"f64": (0, 0), "f32": (1, 0), "bf16": (1, 1), "f16": (1, 2)}   # (math, dtype)
 
@@ -374,17 +381,21 @@ def run_physics(met, mpt, inputs, torch, args, nsteps=60, warm=10):
     """All modules plus convection (CAPE threshold 800 J/kg) and
     sedimentation (radius 5 um, density 1000 kg/m^3) on the headline
     workload, F64 and F32 forms, against the same runs without the two
-    modules; launches of 10 steps timed with events, sort every 10 steps."""
+    modules (F64 also with sedimentation alone); launches of 10 steps timed
+    with events, sort every 10 steps."""
     inputs.add_phys_fields(met, seed=31)
     n = int(args.n)
     part = inputs.make_particles(n, 23)
     out = {"workload": f"{n} parcels, 0.3deg grid {met.nx}x{met.ny}x{met.nz}, advect+turb+meso"
                        f"+convection+sedimentation, {nsteps} timed steps"}
     S = args.sort_interval
+    base = mpt.ADVECT | mpt.TURB | mpt.MESO
     for form in ("f64", "f32"):
         math_, dtype = FORMS[form]
-        for phys in (False, True):
-            flags = mpt.ADVECT | mpt.TURB | mpt.MESO | ((mpt.CONV | mpt.SEDI) if phys else 0)
+        runs = [("plain", base), ("phys", base | mpt.CONV | mpt.SEDI)]
+        if form == "f64":
+            runs.insert(1, ("sedi", base | mpt.SEDI))
+        for tag, flags in runs:
             prm = mpt.make_params(math=math_, flags=flags, fuse=args.fuse, conv_cape=800.0,
                                   sedi_radius=5e-6, sedi_density=1000.0)
             ctx = mpt.Context(met, prm, n_max=n, dtype=dtype)
@@ -413,10 +424,19 @@ def run_physics(met, mpt, inputs, torch, args, nsteps=60, warm=10):
             run(warm, nsteps, True)
             torch.cuda.synchronize()
             el = time.perf_counter() - t0
-            key = f"{form}_{'phys' if phys else 'plain'}"
+            key = f"{form}_{tag}"
+            ms = [a.elapsed_time(b) for a, b in ev]
             out[key] = {"particle_steps_per_s": n * nsteps / el,
-                        "step_kernel_ms_avg": float(np.mean([a.elapsed_time(b) for a, b in ev])),
+                        "step_kernel_ms_avg": float(np.mean(ms)),
                         "finite": bool(torch.isfinite(P.lon).all().item())}
+            if key in FLOP_PER_PS_PHYS and args.fuse == 10 and n == 100_000_000 and met.nz == 137:
+                # per launch of 10 steps, as the headline kernel's roofline
+                tf = FLOP_PER_PS_PHYS[key] * n * 10 / (np.mean(ms) * 1e-3) / 1e12
+                gbs = TRAFFIC_BYTES_PER_LAUNCH_PHYS[key] / (np.mean(ms) * 1e-3) / 1e9
+                out[key]["roofline"] = {"flop_per_particle_step": FLOP_PER_PS_PHYS[key],
+                                        "achieved_TFLOPs": tf, "frac_fp64_peak": tf / FP64_PEAK_TFLOPS,
+                                        "traffic_bytes_per_launch": TRAFFIC_BYTES_PER_LAUNCH_PHYS[key],
+                                        "hbm_GBps": gbs, "frac_hbm_peak": gbs / HBM_PEAK_GBS}
             log(f"physics leg {key}: {n * nsteps / el:.3e} particle-steps/s")
             del ctx, P
             torch.cuda.empty_cache()
