@@ -121,3 +121,48 @@ def test_phys_fields_required(mpt, met3):
     with pytest.raises(mpt.MptError, match="STATE"):              # storing u, v, w clears them
         ctx.step(P, 1, 1)
     torch.cuda.synchronize()
+
+
+def test_phys_scenarios_vs_oracle(mpt, met3):
+    """Batched releases take the persistent launch shape of the physics
+    kernel (it walks the released prefix after each sort)."""
+    say("[phys] scenarios, persistent kernel, 120 steps")
+    sc = inputs.Scenarios(sizes=np.array([800, 3000, 1, 1200]),
+                          release_step=np.array([0, 17, 40, 90], np.int32),
+                          lon=np.array([10.0, 100.0, 200.0, 300.0]),
+                          lat=np.array([0.0, 25.0, -30.0, 60.0]),
+                          p=np.array([700.0, 850.0, 500.0, 900.0]),
+                          kind=np.array([0, 1, 0, 1], np.int32))
+    part, scen = inputs.make_scenario_particles(sc, seed=47)
+    g = gpu_run(met3, part, 0, 120, scen=scen, release=sc.release_step, sort_interval=10, fuse=10,
+                flags=ALL, sedi_radius=R_BIG, **KW)
+    r = oracle_run(met3, part, 0, 120, flags=ALL, release=sc.release_step[scen], sedi_r=R_BIG, **KW)
+    compare(g, r, TOL_F64_DEG, TOL_F64_HPA, "phys scenarios F64 120")
+
+
+def test_phys_streamed_equals_all_resident(mpt):
+    """Streamed levels: after each push the newest level's fields are stored
+    again; the run equals the one with every level resident, bit for bit."""
+    import torch
+    met = inputs.add_phys_fields(inputs.make_met_c1(seed=11, nt=4), seed=31)
+    part = inputs.make_particles(5_000, 48, p_lo=100.0, p_hi=990.0)
+    per = 120
+    prm = mpt.make_params(math=0, flags=ALL, sort_interval=10, fuse=10, sedi_radius=R_BIG, **KW)
+    a_ctx = mpt.Context(met, prm, n_max=part.n)
+    a_ctx.upload_met(met)
+    A = mpt.DeviceParticles.from_host(part, math=0)
+    a_ctx.step(A, 0, 3 * per)
+    b_ctx = mpt.Context(met, prm, n_max=part.n, resident=2)
+    b_ctx.upload_met(met)
+    B = mpt.DeviceParticles.from_host(part, math=0)
+    for b in range(3):
+        b_ctx.step(B, per * b, per)
+        if b + 2 < met.nt:
+            lvl = b + 2
+            b_ctx.push_met(*(torch.from_numpy(x[lvl]).cuda() for x in (met.u, met.v, met.w)))
+            with pytest.raises(mpt.MptError, match="STATE"):
+                b_ctx.step(B, per * (b + 1), 1)          # the new level lacks its fields
+            b_ctx.set_met_phys(1, *(torch.from_numpy(np.ascontiguousarray(x[lvl])).cuda()
+                                    for x in (met.temp, met.cape, met.pel, met.ps)))
+    torch.cuda.synchronize()
+    assert_bitwise(by_id(A.to_host()), by_id(B.to_host()))
