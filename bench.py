@@ -530,8 +530,8 @@ def unique_points_per_step(P, met, torch):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}))
-        sys.stderr.write("bench.py: only --gpus 1 is supported (single-GPU build)\n")
+        print(json.dumps({"error": "this benchmark runs on one GPU only; use --gpus 1"}))
+        sys.stderr.write("bench.py: only --gpus 1 is supported (the library runs on one GPU)\n")
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():

@@ -118,7 +118,12 @@ __global__ __launch_bounds__(kBlock) void k_sort_keys(const SortArgs a) {
     const bool valid = i_w + q * 64 + lane < a.n;
     if (!valid) key[q] = 0xFFFFFFFFu;
     uint32_t prev = __shfl_up(key[q], 1);
-    if (lane == 0) prev = q > 0 ? __shfl(key[q - 1], 63) : ~key[q];
+    if (q > 0) {
+      const uint32_t last = __shfl(key[q - 1], 63);   // read with every lane active
+      if (lane == 0) prev = last;
+    } else if (lane == 0) {
+      prev = ~key[q];
+    }
     heads[q] = __ballot(valid && prev != key[q]);
     nvalid += __popcll(__ballot(valid));
   }
@@ -148,17 +153,13 @@ __global__ __launch_bounds__(kBlock) void k_sort_keys(const SortArgs a) {
   for (int q = 0; q < kSortPer; ++q) {
     const int64_t i = i_w + q * 64 + lane;
     const uint64_t le = heads[q] & upto;
-    uint32_t rank;
-    if (le) {
-      const int h = 63 - __clzll((long long)le);
-      rank = __shfl(base[q], h) + (uint32_t)(lane - h);
-    } else {
-      rank = cbase + (uint32_t)(q * 64 + lane - cpos);
-    }
-    if (heads[q]) {
-      const int h = 63 - __clzll((long long)heads[q]);
-      cbase = __shfl(base[q], h);
-      cpos = q * 64 + h;
+    const int h = le ? 63 - __clzll((long long)le) : 0;   // the lane's run head in this group
+    const uint32_t hb = __shfl(base[q], h);                // read with every lane active
+    const uint32_t rank = le ? hb + (uint32_t)(lane - h) : cbase + (uint32_t)(q * 64 + lane - cpos);
+    if (heads[q]) {                   // uniform
+      const int hl = 63 - __clzll((long long)heads[q]);
+      cbase = __shfl(base[q], hl);
+      cpos = q * 64 + hl;
     }
     if (i < a.n) {
       a.keys[i] = key[q];

@@ -740,8 +740,8 @@ __global__ __launch_bounds__(256) void k_surr_x(const StepArgs a, const SurrW W,
 // records the ballot of its parcels that fall back in fb_mask[i / 64]
 // (i0 is a multiple of 64), from which an ordered list is built.
 __global__ __launch_bounds__(256) void k_surr_apply(const StepArgs a, float tau_km, const float *Y,
-                                                    int64_t i0, int64_t cnt, uint32_t *fallbacks,
-                                                    float *err_out, uint64_t *fb_mask) {
+                                                    int64_t i0, int64_t cnt, float *err_out,
+                                                    uint64_t *fb_mask) {
   const int lb = logical_block((int)blockIdx.x, a.per_xcd);
   if (lb >= a.nblk) return;
   const int64_t r = (int64_t)lb * 256 + threadIdx.x;
@@ -783,12 +783,9 @@ __global__ __launch_bounds__(256) void k_surr_apply(const StepArgs a, float tau_
     accept = err <= tau_km && isfinite(err);
   }
   // parcels that fall back keep their state here; the plain step kernel
-  // takes them from the ordered list
+  // takes them from the ordered list (whose scan also gives their count)
   const uint64_t fb = __ballot(valid && !accept);
-  if (l == 0) {
-    fb_mask[i / 64] = fb;
-    if (fb) atomicAdd(fallbacks, (uint32_t)__popcll(fb));
-  }
+  if (l == 0) fb_mask[i / 64] = fb;
   if (!valid || !accept) return;
   const uint32_t id = a.id[i];
   float up = static_cast<const float *>(a.up)[i];
@@ -850,8 +847,12 @@ __global__ void k_fb_counts(const uint64_t *fb_mask, int64_t nw, uint32_t *off) 
 
 // After the exclusive scan of the counts: wave w's parcels that fall back
 // go to list[off[w] ...] in increasing index order.
+// Also adds the block's fallback count (the scan's total) to *fallbacks, from
+// one thread: a per-wave atomic on that one counter serialized the apply
+// kernel.
 __global__ __launch_bounds__(256) void k_fb_expand(const uint64_t *fb_mask, int64_t nw, const uint32_t *off,
-                                                   uint32_t *list) {
+                                                   uint32_t *list, uint32_t *fallbacks) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *fallbacks += off[nw];
   const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   if (w >= nw) return;
   const int l = threadIdx.x & 63;
@@ -932,21 +933,21 @@ hipError_t launch_surr_x(const StepArgs &a, const SurrW &W, const float4 *F, int
 }
 
 hipError_t launch_surr_apply(const StepArgs &a, float tau_km, const float *Y, int64_t i0, int64_t cnt,
-                             uint32_t *fallbacks, float *err_out, uint64_t *fb_mask, hipStream_t s) {
+                             float *err_out, uint64_t *fb_mask, hipStream_t s) {
   const StepArgs c = chunk_args(a, cnt);
   hipLaunchKernelGGL(k_surr_apply, dim3((unsigned)(c.per_xcd * kXcds)), dim3(256), 0, s, c, tau_km, Y, i0,
-                     cnt, fallbacks, err_out, fb_mask);
+                     cnt, err_out, fb_mask);
   return hipGetLastError();
 }
 
 hipError_t launch_surr_fblist(const uint64_t *fb_mask, int64_t n, uint32_t *off, uint32_t *sums,
-                              uint32_t *list, hipStream_t s) {
+                              uint32_t *list, uint32_t *fallbacks, hipStream_t s) {
   const int64_t nw = (n + 63) / 64;
   hipLaunchKernelGGL(k_fb_counts, dim3((unsigned)((nw + 1 + 255) / 256)), dim3(256), 0, s, fb_mask, nw, off);
   const hipError_t e = launch_scan_u32(off, (uint32_t)(nw + 1), sums, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_fb_expand, dim3((unsigned)((nw * 64 + 255) / 256)), dim3(256), 0, s, fb_mask, nw, off,
-                     list);
+                     list, fallbacks);
   return hipGetLastError();
 }
 

@@ -93,7 +93,7 @@ constexpr int kW1Ld = kSurrInPad + 8, kWLd = kSurrHid + 8;
 constexpr int kWiSize = kSurrHid * kW1Ld + 2 * kSurrHid * kWLd + kSurrOutPad * kWLd;
 constexpr int kSurrMaxBatch = 8192;
 constexpr int kSurrStatBlocks = 1024;
-constexpr int64_t kSurrChunk = 1 << 20;          // parcels per stencil / MLP / apply pass
+constexpr int64_t kSurrChunk = 1 << 22;          // parcels per stencil / MLP / apply pass
 
 struct SurrW {
   const uint16_t *wt1, *wt2, *wt3, *wt4;        // forward fragments, [out][in]
@@ -133,12 +133,12 @@ hipError_t launch_surr_x(const StepArgs &a, const SurrW &W, const float4 *F, int
 // multiple of 64); fb_mask[i / 64] gets the wave's ballot of parcels that
 // fall back
 hipError_t launch_surr_apply(const StepArgs &a, float tau_km, const float *Y, int64_t i0, int64_t cnt,
-                             uint32_t *fallbacks, float *err_out, uint64_t *fb_mask, hipStream_t s);
+                             float *err_out, uint64_t *fb_mask, hipStream_t s);
 // ordered fallback list: list[0 .. off[nw]) = indices of the set bits of
 // fb_mask[0 .. nw), nw = ceil(n / 64), in increasing order; off holds nw + 1
 // entries and sums scan_block_sums_len(nw + 1)
 hipError_t launch_surr_fblist(const uint64_t *fb_mask, int64_t n, uint32_t *off, uint32_t *sums,
-                              uint32_t *list, hipStream_t s);
+                              uint32_t *list, uint32_t *fallbacks, hipStream_t s);
 hipError_t launch_surr_train(const SurrW &W, const SurrTrain &T, float *params, float *m, float *v,
                              float lr, float bc1, float bc2, hipStream_t s);
 hipError_t launch_surr_grad(const SurrW &W, const SurrTrain &T, hipStream_t s);

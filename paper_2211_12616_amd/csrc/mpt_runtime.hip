@@ -922,10 +922,10 @@ mpt_status mpt_step_surrogate(mpt_ctx *c, mpt_particles *P, uint32_t step0, int3
       const int64_t cnt = P->n - i0 < c->s_chunk ? P->n - i0 : c->s_chunk;
       if (launch_surr_x(a, W, c->s_f, i0, cnt, c->s_x, s) != hipSuccess ||
           launch_surr_mlp(W, c->s_x, cnt, c->s_y, 4, s) != hipSuccess ||
-          launch_surr_apply(a, c->s_tau, c->s_y, i0, cnt, fallbacks, err_out, c->fb_mask, s) != hipSuccess)
+          launch_surr_apply(a, c->s_tau, c->s_y, i0, cnt, err_out, c->fb_mask, s) != hipSuccess)
         return MPT_ERR_HIP;
     }
-    if (launch_surr_fblist(c->fb_mask, P->n, c->fb_off, c->fb_sums, c->keys, s) != hipSuccess)
+    if (launch_surr_fblist(c->fb_mask, P->n, c->fb_off, c->fb_sums, c->keys, fallbacks, s) != hipSuccess)
       return MPT_ERR_HIP;
     // parcels that fell back: kSurrK plain steps, walking the list
     StepArgs f;
