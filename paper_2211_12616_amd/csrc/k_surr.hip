@@ -193,7 +193,7 @@ __device__ __forceinline__ void stencil81(const StepArgs &a, const Loc<float> &L
 
 __device__ __forceinline__ void surr_locate(const StepArgs &a, double lon, double lat, double p,
                                             double t, Loc<float> &L) {
-  locate_xyz<float>(a, a.plev, a.inv_dp, a.lut, lon, lat, p, L);
+  locate_xyz_g<float>(a, lon, lat, p, L);
   locate_t<float>(a, t, L);
 }
 
@@ -793,7 +793,13 @@ __global__ __launch_bounds__(256) void k_surr_apply(const StepArgs a, float tau_
   float wp = static_cast<const float *>(a.wp)[i];
   const bool meso_on = (a.flags & kMeso) != 0;
   float sg[3] = {0.f, 0.f, 0.f};
-  if (meso_on) meso_sigma<kF32, float>(a, a.plev, a.inv_dp, a.lut, t0 + 0.5 * a.dt, lon, lat, p, sg);
+  if (meso_on) {
+    Cell16<kF32> mc;
+    Loc<float> L0;
+    surr_locate(a, lon, lat, p, t0 + 0.5 * a.dt, L0);
+    load_cell<kF32, float>(a, L0, mc);
+    sigma_cell<kF32, float>(a, mc, L0, sg);
+  }
   lon = lon + (double)(de * 1000.0f * kdeg / c0);
   lat = lat + (double)(dn * 1000.0f * kdeg);
   p = p + (double)dpp;

@@ -267,6 +267,59 @@ __device__ __forceinline__ void locate_xyz(const StepArgs &a, const double *s_pl
   L.fz = (R)((s_plev[k] - pc) * s_idp[k]);
 }
 
+// locate_xyz for tables read from global memory (kernels that visit each
+// parcel once and do not stage them in LDS).  The level table's guess k0 and
+// the four levels and inverse spacings around it are loaded together, which
+// settles up to two steps either way without another round trip (further
+// steps, rare, walk on); same cell and weights as locate_xyz.
+template <typename R>
+__device__ __forceinline__ void locate_xyz_g(const StepArgs &a, double lon, double lat, double p, Loc<R> &L) {
+  const double lam = lon - 360.0 * floor((lon - a.lon0) * (1.0 / 360.0));
+  const double x = (lam - a.lon0) * a.inv_dlon;
+  const double xf = floor(x);
+  int i0 = (int)xf;
+  if (i0 >= a.nx) i0 -= a.nx;
+  if (i0 < 0) i0 += a.nx;
+  L.i0 = i0;
+  L.i1 = (i0 + 1 == a.nx) ? 0 : i0 + 1;
+  L.fx = (R)(x - xf);
+
+  const double phi = fmin(fmax(lat, a.lat0), a.lat_hi);
+  const double y = (phi - a.lat0) * a.inv_dlat;
+  int j = (int)floor(y);
+  j = min(max(j, 0), a.ny - 2);
+  L.j = j;
+  L.fy = (R)(y - (double)j);
+
+  const double pc = fmin(fmax(p, a.p_top), a.p_bot);
+  int b = (int)((__log2f((float)pc) - a.lut_lo) * a.lut_scale);
+  b = min(max(b, 0), kLutBins - 1);
+  const int k0 = a.lut[b];
+  const int top = a.nz - 2;
+  const int km = max(k0 - 1, 0), k1 = min(k0 + 1, a.nz - 1), k2 = min(k0 + 2, a.nz - 1);
+  const double pm = a.plev[km], p0 = a.plev[k0], p1 = a.plev[k1], p2 = a.plev[k2];
+  const double dm = a.inv_dp[km], d0 = a.inv_dp[k0], d1 = a.inv_dp[k1], d2 = a.inv_dp[k2];
+  int k = k0;
+  double pk = p0, dk = d0;
+  if (k < top && p1 >= pc) {
+    k = k0 + 1; pk = p1; dk = d1;
+    if (k < top && p2 >= pc) {
+      k = k0 + 2; pk = p2; dk = d2;
+      while (k < top && a.plev[k + 1] >= pc) ++k;
+      if (k > k0 + 2) { pk = a.plev[k]; dk = a.inv_dp[k]; }
+    }
+  } else if (k > 0 && p0 < pc) {
+    k = k0 - 1; pk = pm; dk = dm;
+    if (k > 0 && pm < pc) {
+      --k;
+      while (k > 0 && a.plev[k] < pc) --k;
+      pk = a.plev[k]; dk = a.inv_dp[k];
+    }
+  }
+  L.k = k;
+  L.fz = (R)((pk - pc) * dk);
+}
+
 // Time-level pair bracketing t and the weight of the later level.  The
 // resident levels are lev_first .. lev_first + nt - 1 (absolute indices,
 // level L at t_met0 + L dt_met), stored in a ring of nt slots starting at
