@@ -130,7 +130,8 @@ typedef struct {
 
 /* Bytes of device workspace needed for this grid and up to n_max parcels
  * (met storage for nt levels, level table, sort scratch).  Returns 0 on
- * invalid arguments. */
+ * invalid arguments.  n_max < 2^32 - 1 (the sort's positions are 32-bit;
+ * mpt_create returns MPT_ERR_UNSUPPORTED beyond). */
 size_t mpt_workspace_bytes(const mpt_grid *grid, const mpt_params *params, int64_t n_max);
 
 /* Create a context on the current HIP device.  dev_workspace: caller-owned

@@ -31,6 +31,8 @@ hipError_t launch_fill_f32(float *dst, float value, int64_t n, hipStream_t strea
 // Parcels per thread in the sort's key kernel (a block covers
 // kSortPer * kBlock parcels).
 constexpr int kSortPer = 4;
+// The sort's ranks, offsets and scatter positions are 32-bit.
+constexpr int64_t kMaxParcels = 0xFFFFFFFFll;
 
 struct SortArgs {
   const double *lon, *lat, *p;

@@ -447,6 +447,7 @@ extern "C" {
 
 size_t mpt_workspace_bytes(const mpt_grid *grid, const mpt_params *params, int64_t n_max) {
   if (check_grid(grid) != MPT_OK || check_params(params, grid) != MPT_OK || n_max < 0) return 0;
+  if (n_max >= kMaxParcels) return 0;
   return layout(grid, n_max).total;
 }
 
@@ -459,6 +460,7 @@ mpt_status mpt_create(const mpt_grid *grid, const mpt_params *params, int64_t n_
   st = check_params(params, grid);
   if (st != MPT_OK) return st;
   if (n_max < 0) return MPT_ERR_ARG;
+  if (n_max >= kMaxParcels) return MPT_ERR_UNSUPPORTED;
   if (!dev_workspace || !aligned(dev_workspace, 256)) return MPT_ERR_ARG;
   const Layout L = layout(grid, n_max);
   if (ws_bytes < L.total) return MPT_ERR_WORKSPACE;

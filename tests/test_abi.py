@@ -116,6 +116,9 @@ def test_workspace_checks():
     h = ctypes.c_void_p()
     assert mpt.lib().mpt_create(ctypes.byref(g), ctypes.byref(p), -1, 0x100000, 1 << 30,
                                 ctypes.byref(h)) == -1                # n_max < 0
+    assert ws_bytes(g, p, 1 << 32) == 0                               # 32-bit sort positions
+    assert mpt.lib().mpt_create(ctypes.byref(g), ctypes.byref(p), 1 << 32, 0x100000, 1 << 30,
+                                ctypes.byref(h)) == -6
 
 
 def test_no_gpu_gives_hip_error():
