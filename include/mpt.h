@@ -367,9 +367,9 @@ mpt_status mpt_surrogate_forward(mpt_ctx *ctx, int64_t n, const float *x, float 
  * of parcel-blocks that fell back to *fallbacks (device uint32).  err_out
  * (device, n floats, or NULL) receives each parcel's error estimate of the
  * last block (for calibrating tau; needs sort_interval == 0).  Needs
- * MPT_MATH_F32, F32 storage, no scenarios, step0 and nsteps multiples of
- * MPT_SURR_K; sorts before each block that contains a multiple of
- * sort_interval. */
+ * MPT_MATH_F32, F32 storage, no scenarios, no MPT_CONV / MPT_SEDI (else
+ * MPT_ERR_UNSUPPORTED), step0 and nsteps multiples of MPT_SURR_K; sorts
+ * before each block that contains a multiple of sort_interval. */
 mpt_status mpt_step_surrogate(mpt_ctx *ctx, mpt_particles *particles, uint32_t step0,
                               int32_t nsteps, uint32_t *fallbacks, float *err_out,
                               void *hip_stream);
