@@ -124,7 +124,11 @@ template <> struct Math<double> {
   }
   // ln of a uniform in (0, 1): always a positive normal number
   static __device__ __forceinline__ double log_(double x) { return m64::ln_pos(x); }
-  static __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
+  // non-negative arguments: Box-Muller radii, variances (0 when a cell's
+  // values are equal), temperatures; below 2^-900 the root is taken as 0
+  static __device__ __forceinline__ double sqrt_(double x) {
+    return x > 0x1p-900 ? m64::sqrt_pos(x) : 0.0;
+  }
   static __device__ __forceinline__ double exp_(double x) { return exp(x); }
   // sin(pi x), cos(pi x) for x in [0, 2] (twice a uniform)
   static __device__ __forceinline__ void sincospi_(double x, double *s, double *c) {

@@ -16,6 +16,52 @@ constexpr double kPiD = 3.14159265358979323846;
 constexpr double kLn2Hi = 0x1.62e42fee00000p-1;
 constexpr double kLn2Lo = 0x1.a39ef35793c76p-33;
 
+// Seeds of 1/x and 1/sqrt(x): the hardware approximations on the device
+// (about 26 good bits); on the host the FP32 operations (24 bits) stand in
+// for them, so the refinements below are exercised from seeds of the same
+// quality.
+__host__ __device__ __forceinline__ double rcp_seed(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_rcp(x);
+#else
+  return (double)(1.0f / (float)x);
+#endif
+}
+__host__ __device__ __forceinline__ double rsq_seed(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_rsq(x);
+#else
+  return (double)(1.0f / sqrtf((float)x));
+#endif
+}
+
+// a / b for b in [1, 4] (no special values): one Newton step on the
+// reciprocal seed, the quotient, one correction by its residual; within
+// 1 ulp (the library division also handles every exponent and special
+// value, at twice the instructions).
+__host__ __device__ __forceinline__ double div_1to4(double a, double b) {
+  double r = rcp_seed(b);
+  r = fma(r, fma(-b, r, 1.0), r);
+  const double q = a * r;
+  return fma(fma(-q, b, a), r, q);
+}
+
+// sqrt(x) for a positive normal x in [2^-900, 2^900] (no scaling, no special
+// values): Goldschmidt iteration from the reciprocal square-root seed,
+// g -> sqrt(x) and h -> 1/(2 sqrt(x)), then two corrections of g by its
+// residual x - g^2; within 1 ulp.
+__host__ __device__ __forceinline__ double sqrt_pos(double x) {
+  const double y = rsq_seed(x);
+  double g = x * y, h = 0.5 * y;
+  const double r = fma(-h, g, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  double d = fma(-g, g, x);
+  g = fma(d, h, g);
+  d = fma(-g, g, x);
+  return fma(d, h, g);
+}
+
 // ln x for a positive normal x.  x = m 2^e with m in [1/sqrt 2, sqrt 2);
 // ln m = 2 atanh(s), s = (m - 1) / (m + 1), |s| <= 0.1716 (m - 1 is exact);
 // atanh s = s (1 + z/3 + z^2/5 + ... + z^10/21), z = s^2 <= 0.0295, whose
@@ -27,7 +73,7 @@ __host__ __device__ __forceinline__ double ln_pos(double x) {
     m = m + m;
     e = e - 1;
   }
-  const double s = (m - 1.0) / (m + 1.0);
+  const double s = div_1to4(m - 1.0, m + 1.0);
   const double z = s * s;
   double q = 1.0 / 21.0;
   q = fma(q, z, 1.0 / 19.0);

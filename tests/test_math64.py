@@ -7,7 +7,10 @@ the argument ranges the step feeds them:
   number around the reduction boundaries;
 * cos of a latitude in degrees, including the poles and a small overshoot
   past them (the midpoint position is not reflected before it is used);
-* sin(pi t), cos(pi t) for t = 2u in [0, 2], including every quarter period.
+* sin(pi t), cos(pi t) for t = 2u in [0, 2], including every quarter period;
+* the square root of Box-Muller radii (-2 ln u) and of variances, and the
+  division inside ln (numerator in [-0.3, 0.42], denominator in [1.7, 2.42]),
+  both refined from reciprocal seeds: within 1 ulp.
 """
 import os
 import shutil
@@ -119,3 +122,27 @@ def test_sincospi_on_twice_a_uniform(m64):
     q = sc[len(k):len(k) + 9][0::2]
     np.testing.assert_array_equal(q[:, 0] + 0.0, [0.0, 1.0, 0.0, -1.0, 0.0])
     np.testing.assert_array_equal(q[:, 1] + 0.0, [1.0, 0.0, -1.0, 0.0, 1.0])
+
+
+def test_sqrt_on_radii_and_variances(m64):
+    rng = np.random.default_rng(8)
+    u = (np.arange(1 << 16, dtype=np.float64) * 256 + 0.5) / 2.0 ** 24
+    x = np.concatenate([-2.0 * np.log(u), 10.0 ** rng.uniform(-12, 6, 200_000),
+                        2.0 ** np.arange(-60.0, 61.0), [1.0, 2.0, 3.0, 4.0, 0.25, 1e-30, 1e30]])
+    got = m64("sqrt", x)
+    ref = np.sqrt(x.astype(LD))
+    assert ulp_err(got, ref).max() <= 1.0
+
+
+def test_division_in_ln_reduction(m64):
+    rng = np.random.default_rng(9)
+    m = np.concatenate([rng.uniform(0.70710678118654752440, 1.4142135623730951, 200_000),
+                        [0.70710678118654752440, 1.0, 1.4142135623730950]])
+    ab = np.empty(2 * len(m))
+    ab[0::2] = m - 1.0
+    ab[1::2] = m + 1.0
+    got = m64("div", ab)
+    ref = (m - 1.0).astype(LD) / (m + 1.0).astype(LD)
+    nz = ref != 0
+    assert ulp_err(got[nz], ref[nz]).max() <= 1.0
+    assert np.all(got[~nz] == 0.0)
