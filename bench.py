@@ -560,7 +560,7 @@ def main():
     for form in forms:
         math_, dtype = FORMS[form]
         log(f"form {form}: upload")
-        params = mpt.make_params(math=math_, sort_interval=0, fuse=args.fuse)
+        params = mpt.make_params(math=math_, sort_interval=0, fuse=args.fuse, presort=1)
         ctx = mpt.Context(met, params, n_max=n, dtype=dtype)
         ctx.upload_met(met)
         P = mpt.DeviceParticles.from_host(part, math=math_)

@@ -107,7 +107,20 @@ typedef struct {
     double conv_cape;          /* MPT_CONV: CAPE threshold [J/kg], finite */
     double sedi_radius;        /* MPT_SEDI: particle radius [m], > 0 */
     double sedi_density;       /* MPT_SEDI: particle density [kg/m^3], > 0 */
+    int32_t presort;           /* 0 or 1, see below */
+    int32_t reserved;          /* must be 0 */
 } mpt_params;
+/* Sort keys inside the step.  Without scenarios, a kernel launch of mpt_step
+ * or mpt_step_graph that ends where a sort follows also computes the sort
+ * keys of its final positions, and that sort skips its own key pass.  With
+ * presort = 1 the last launch of each mpt_step call does the same, and the
+ * keys are kept for the next sort of the same particles (same primary lon
+ * array and count): mpt_sort_particles, or the sort an mpt_step call
+ * starting on a multiple of sort_interval begins with; any other call that
+ * moves or sorts parcels drops them.  A caller that changes positions
+ * itself in between gets a sort by the previous cells: still a permutation
+ * of the whole state, so results do not change (they never depend on the
+ * order). */
 
 /* Parcel state (atm_t, Sec. 4.4, plus the mesoscale state of `cache`).
  * All pointers are device pointers to arrays of n elements.

@@ -58,7 +58,8 @@ class Params(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("sort_interval", ctypes.c_int32),
                 ("math", ctypes.c_int32), ("flags", ctypes.c_uint32), ("fuse", ctypes.c_int32),
                 ("conv_cape", ctypes.c_double), ("sedi_radius", ctypes.c_double),
-                ("sedi_density", ctypes.c_double)]
+                ("sedi_density", ctypes.c_double), ("presort", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class ParticlesC(ctypes.Structure):
@@ -159,11 +160,12 @@ def make_grid(met, dtype: int = DT_F32) -> tuple[Grid, np.ndarray]:
 
 def make_params(dt=180.0, t_start=0.0, turb_dx=50.0, turb_dz=0.1, meso_fh=0.16, meso_fv=0.16,
                 seed=SEED, sort_interval=0, math=MATH_F64, flags=ADVECT | TURB | MESO,
-                fuse=1, conv_cape=500.0, sedi_radius=5e-6, sedi_density=1000.0) -> Params:
+                fuse=1, conv_cape=500.0, sedi_radius=5e-6, sedi_density=1000.0,
+                presort=0) -> Params:
     return Params(dt=dt, t_start=t_start, turb_dx=turb_dx, turb_dz=turb_dz, meso_fh=meso_fh,
                   meso_fv=meso_fv, seed=seed, sort_interval=sort_interval, math=math,
                   flags=flags, fuse=fuse, conv_cape=conv_cape, sedi_radius=sedi_radius,
-                  sedi_density=sedi_density)
+                  sedi_density=sedi_density, presort=presort, reserved=0)
 
 
 def _stream_handle(stream) -> Optional[int]:

@@ -273,12 +273,20 @@ hipError_t launch_scan_u32(uint32_t *data, uint32_t n, uint32_t *block_sums, hip
   return hipGetLastError();
 }
 
-hipError_t launch_sort(const SortArgs &sa, const ScatterArgs &xa, hipStream_t stream) {
-  const uint32_t nb = (uint32_t)scan_block_sums_len(sa.nkeys);
-  unsigned fill_grid = (16u * sa.spread_s + 255) / 256;
+hipError_t launch_clear_spread(uint32_t *spread, uint32_t spread_s, hipStream_t stream) {
+  unsigned fill_grid = (16u * spread_s + 255) / 256;
   if (fill_grid > 4096) fill_grid = 4096;
-  hipLaunchKernelGGL(k_fill_u32, dim3(fill_grid), dim3(256), 0, stream, sa.spread, 16u * sa.spread_s);
-  hipLaunchKernelGGL(k_sort_keys, dim3((unsigned)(sa.per_xcd * kXcds)), dim3(kBlock), 0, stream, sa);
+  hipLaunchKernelGGL(k_fill_u32, dim3(fill_grid), dim3(256), 0, stream, spread, 16u * spread_s);
+  return hipGetLastError();
+}
+
+hipError_t launch_sort(const SortArgs &sa, const ScatterArgs &xa, bool keys_done, hipStream_t stream) {
+  const uint32_t nb = (uint32_t)scan_block_sums_len(sa.nkeys);
+  if (!keys_done) {
+    const hipError_t e = launch_clear_spread(sa.spread, sa.spread_s, stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sort_keys, dim3((unsigned)(sa.per_xcd * kXcds)), dim3(kBlock), 0, stream, sa);
+  }
   hipLaunchKernelGGL(k_unspread, dim3((sa.nkeys + 255) / 256), dim3(256), 0, stream, sa.spread, sa.spread_s,
                      sa.nkeys, sa.hist);
   hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(256), 0, stream, sa.hist, sa.nkeys, sa.block_sums);

@@ -15,11 +15,14 @@
 
 namespace mpt {
 
+// Advances parcel i; lon, lat, p receive its final position.
 template <int F, typename R, bool P>
 __device__ __forceinline__ void step_parcel(const StepArgs &a, const double *s_plev,
                                             const double *s_idp, const uint16_t *s_lut, int64_t i,
-                                            uint32_t step0) {
-  double lon = a.lon[i], lat = a.lat[i], p = a.p[i];
+                                            uint32_t step0, double &lon, double &lat, double &p) {
+  lon = a.lon[i];
+  lat = a.lat[i];
+  p = a.p[i];
   if (!finite3(lon, lat, p)) return;
   const uint32_t id = a.id[i];
   int64_t rel = INT64_MIN;
@@ -113,13 +116,25 @@ __device__ __forceinline__ void step_body(const StepArgs &a) {
     const int64_t c_lo = nchunks * xcd / kXcds, c_hi = nchunks * (xcd + 1) / kXcds;
     for (int64_t c = c_lo + q; c < c_hi; c += nq) {
       const int64_t j = c * kBlock + threadIdx.x;
-      if (j < cnt) step_parcel<F, R, P>(a, s_plev, s_idp, s_lut, (int64_t)a.index[j], step0);
+      double lon, lat, p;
+      if (j < cnt) step_parcel<F, R, P>(a, s_plev, s_idp, s_lut, (int64_t)a.index[j], step0, lon, lat, p);
     }
   } else if constexpr (M == kModeBlock) {
     const int lb = logical_block((int)blockIdx.x, a.per_xcd);
     if (lb >= a.nblk) return;
     const int64_t i = (int64_t)lb * kBlock + threadIdx.x;
-    if (i < a.n) step_parcel<F, R, P>(a, s_plev, s_idp, s_lut, i, step0);
+    double lon = 0.0, lat = 0.0, p = 0.0;
+    const bool valid = i < a.n;
+    if (valid) step_parcel<F, R, P>(a, s_plev, s_idp, s_lut, i, step0, lon, lat, p);
+    if (a.sk) {                           // keys for the sort that follows (uniform)
+      const SortKeyArgs sk = *a.sk;
+      const uint32_t key = valid ? tile_key(a, sk, s_plev, s_lut, lon, lat, p) : 0xFFFFFFFFu;
+      const uint32_t rank = wave_key_rank(sk, key, valid);
+      if (valid) {
+        sk.keys[i] = key;
+        sk.ranks[i] = rank;
+      }
+    }
   } else {
     // persistent: XCD x owns an even share of the chunks of the prefix and
     // its blocks stride through that share
@@ -130,7 +145,8 @@ __device__ __forceinline__ void step_body(const StepArgs &a) {
     const int64_t c_lo = nchunks * xcd / kXcds, c_hi = nchunks * (xcd + 1) / kXcds;
     for (int64_t c = c_lo + q; c < c_hi; c += nq) {
       const int64_t i = c * kBlock + threadIdx.x;
-      if (i < bound) step_parcel<F, R, P>(a, s_plev, s_idp, s_lut, i, step0);
+      double lon, lat, p;
+      if (i < bound) step_parcel<F, R, P>(a, s_plev, s_idp, s_lut, i, step0, lon, lat, p);
     }
   }
 }

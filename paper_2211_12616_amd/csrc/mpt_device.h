@@ -86,6 +86,18 @@ struct StepArgs {
   const float4 *sfc;
   const float *t_scales;
   double conv_cape, sedi_r, sedi_rho;
+  // Sort keys of the final positions (block launches only; null: none).
+  // Device memory, read after the step loop, so its fields hold no scalar
+  // registers during it.
+  const struct SortKeyArgs *sk;
+};
+
+// Where a launch leaves the sort keys: tile key and rank within the key
+// from run-aggregated atomics on the sort's spread counters (key k at
+// (k % 16) * spread_s + k / 16).
+struct SortKeyArgs {
+  uint32_t *keys, *ranks, *spread;
+  uint32_t spread_s, ntx, nty, nkeys;
 };
 
 // Map the hardware block index to a logical block so that each XCD walks a
@@ -734,6 +746,47 @@ __device__ __forceinline__ void sedimentation(const StepArgs &a, const double *s
 
 __device__ __forceinline__ bool finite3(double a, double b, double c) {
   return isfinite(a) && isfinite(b) && isfinite(c);
+}
+
+// ---- sort keys at the end of a launch ----------------------------------------
+
+// Tile key (8 x 8 x 4 cells, lon fastest) of a position, the cell found as
+// locate_xyz finds it; non-finite positions take the last key.
+__device__ __forceinline__ uint32_t tile_key(const StepArgs &a, const SortKeyArgs &sk, const double *s_plev,
+                                             const uint16_t *s_lut, double lon, double lat, double p) {
+  if (!finite3(lon, lat, p)) return sk.nkeys - 1;
+  const double lam = lon - 360.0 * floor((lon - a.lon0) * (1.0 / 360.0));
+  int i0 = (int)floor((lam - a.lon0) * a.inv_dlon);
+  if (i0 >= a.nx) i0 -= a.nx;
+  if (i0 < 0) i0 += a.nx;
+  const double phi = fmin(fmax(lat, a.lat0), a.lat_hi);
+  int j = (int)floor((phi - a.lat0) * a.inv_dlat);
+  j = min(max(j, 0), a.ny - 2);
+  const int k = level_index(a, s_plev, s_lut, fmin(fmax(p, a.p_top), a.p_bot));
+  return ((uint32_t)(k >> 2) * sk.nty + (uint32_t)(j >> 3)) * sk.ntx + (uint32_t)(i0 >> 3);
+}
+
+// Rank of each valid lane's key among the parcels of that key: runs of
+// equal keys in the wave (valid lanes form a prefix) add their length to
+// the key's counter once; a lane's rank is the run's old counter value plus
+// its place in the run.  Every lane must call it.
+__device__ __forceinline__ uint32_t wave_key_rank(const SortKeyArgs &sk, uint32_t key, bool valid) {
+  const int lane = (int)__lane_id();
+  uint32_t prev = __shfl_up(key, 1);
+  if (lane == 0) prev = ~key;
+  const uint64_t heads = __ballot(valid && prev != key);
+  const int nvalid = __popcll(__ballot(valid));
+  const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);   // lanes <= lane
+  uint32_t base = 0;
+  if ((heads >> lane) & 1ull) {
+    const uint64_t above = heads & ~upto;
+    const int end = above ? __ffsll((long long)above) - 1 : nvalid;
+    base = atomicAdd(sk.spread + (key & 15u) * sk.spread_s + (key >> 4), (uint32_t)(end - lane));
+  }
+  const uint64_t le = heads & upto;
+  const int h = le ? 63 - __clzll((long long)le) : 0;
+  const uint32_t hb = __shfl(base, h);                  // every lane active
+  return hb + (uint32_t)(lane - h);
 }
 
 }  // namespace mpt

@@ -76,7 +76,11 @@ struct ScatterArgs {
   int nblk, per_xcd;
 };
 
-hipError_t launch_sort(const SortArgs &sa, const ScatterArgs &xa, hipStream_t stream);
+// keys_done: keys, ranks and the spread counters already hold the keys of
+// the parcels (a step launch computed them); otherwise the key pass runs.
+hipError_t launch_sort(const SortArgs &sa, const ScatterArgs &xa, bool keys_done, hipStream_t stream);
+// Zero the spread counters before a launch that counts keys into them.
+hipError_t launch_clear_spread(uint32_t *spread, uint32_t spread_s, hipStream_t stream);
 
 // Learned k-step advection surrogate (k_surr.hip).
 constexpr int kSurrK = 8;                       // steps per surrogate block

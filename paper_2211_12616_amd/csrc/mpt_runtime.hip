@@ -32,11 +32,17 @@ struct mpt_ctx {
   int32_t *rel_sorted;    // [kMaxScen] release steps in ascending order
   uint32_t *step_dev;     // step index read by graph-replayed kernels
   uint32_t *keys, *ranks, *hist, *spread, *block_sums;
+  SortKeyArgs *sk;        // the same buffers for step launches that leave sort keys
   uint32_t ntx, nty, ntz, ntiles, nkeys;
   // host state
   double plev_h[kMaxLevels];
   uint64_t levels_ready;  // bit l set once level l was stored (nt <= 64)
   uint64_t phys_ready;    // bit l set once slot l has its convection / sedimentation fields
+  // keys of a step's final positions carried to the next sort (presort):
+  // valid for the parcels whose primary lon array and count these are
+  bool keyed;
+  const double *keyed_lon;
+  int64_t keyed_n;
   int32_t nscen;
   // surrogate: bf16 weight copies, normalization, training scratch
   uint16_t *s_wt, *s_wb, *s_wi;
@@ -109,6 +115,7 @@ mpt_status check_params(const mpt_params *p, const mpt_grid *g) {
   if (p->sort_interval < 0 || p->fuse < 1) return MPT_ERR_ARG;
   if (p->math != MPT_MATH_F64 && p->math != MPT_MATH_F32) return MPT_ERR_ARG;
   if (p->flags & ~(uint32_t)(MPT_ADVECT | MPT_TURB | MPT_MESO | MPT_CONV | MPT_SEDI)) return MPT_ERR_ARG;
+  if ((p->presort != 0 && p->presort != 1) || p->reserved != 0) return MPT_ERR_ARG;
   if ((p->flags & MPT_CONV) && !isfinite(p->conv_cape)) return MPT_ERR_ARG;
   if ((p->flags & MPT_SEDI) && !(isfinite(p->sedi_radius) && p->sedi_radius > 0.0 &&
                                  isfinite(p->sedi_density) && p->sedi_density > 0.0))
@@ -118,7 +125,7 @@ mpt_status check_params(const mpt_params *p, const mpt_grid *g) {
 }
 
 struct Layout {
-  size_t met, scales, t_scales, sfc, plev, inv_dp, lut, release, rank, rel_sorted, step_dev, keys, ranks, hist, spread,
+  size_t met, scales, t_scales, sfc, sk, plev, inv_dp, lut, release, rank, rel_sorted, step_dev, keys, ranks, hist, spread,
       block_sums, out_pe, hyb_ab, s_wt, s_wb, s_wi, s_norm, s_bias, s_x, s_y, s_f, fb_mask, fb_off, fb_sums, t_xn, t_h, t_dy, t_dh, t_yp, t_grad, t_part, total;
   uint32_t ntx, nty, ntz, ntiles, nkeys;
   int64_t s_chunk;
@@ -144,6 +151,7 @@ Layout layout(const mpt_grid *g, int64_t n_max) {
   L.scales = off;     off += align_up(sizeof(float) * 3 * g->nz * g->nt);
   L.t_scales = off;   off += align_up(sizeof(float) * g->nz * g->nt);
   L.sfc = off;        off += align_up((size_t)16 * g->nx * g->ny * g->nt);
+  L.sk = off;         off += align_up(sizeof(SortKeyArgs));
   L.plev = off;       off += align_up(sizeof(double) * g->nz);
   L.inv_dp = off;     off += align_up(sizeof(double) * g->nz);
   L.lut = off;        off += align_up(sizeof(uint16_t) * kLutBins);
@@ -262,6 +270,7 @@ void fill_step_args(const mpt_ctx *c, const mpt_particles *P, uint32_t step0, in
   a.rel_sorted = c->rel_sorted;
   a.index = nullptr;
   a.index_count = nullptr;
+  a.sk = nullptr;
   a.sfc = c->sfc;
   a.t_scales = c->t_scales;
   a.conv_cape = q.conv_cape;
@@ -319,7 +328,10 @@ mpt_status check_time(const mpt_ctx *c, uint32_t step0, int64_t nsteps) {
 }
 
 // Sort before step `step` (added to the device step index when dev_step).
-mpt_status do_sort(mpt_ctx *c, mpt_particles *P, uint32_t step, bool dev_step, hipStream_t s) {
+// keys_done: the launch before it left the keys of the parcels' current
+// positions (and their counts) in the context's sort buffers.
+mpt_status do_sort(mpt_ctx *c, mpt_particles *P, uint32_t step, bool dev_step, hipStream_t s,
+                   bool keys_done = false) {
   const mpt_grid &g = c->grid;
   SortArgs sa;
   sa.lon = P->lon; sa.lat = P->lat; sa.p = P->p;
@@ -352,7 +364,7 @@ mpt_status do_sort(mpt_ctx *c, mpt_particles *P, uint32_t step, bool dev_step, h
   const int64_t nblk_x = (P->n + kBlock - 1) / kBlock;
   xa.nblk = (int)nblk_x;
   xa.per_xcd = (int)((nblk_x + kXcds - 1) / kXcds);
-  const mpt_status st = from_hip(launch_sort(sa, xa, s));
+  const mpt_status st = from_hip(launch_sort(sa, xa, keys_done, s));
   if (st != MPT_OK) return st;
   // the sorted state now lives in the *2 set: swap the sets
   double *t;
@@ -370,14 +382,20 @@ mpt_status do_sort(mpt_ctx *c, mpt_particles *P, uint32_t step, bool dev_step, h
 
 // persistent: parcels are in the order the last sort of this call left
 // them (scenario runs only), so the launch may walk the active prefix.
+// keys: the (block-shaped) launch also leaves the sort keys of the final
+// positions for the sort that follows.
 mpt_status run_steps(mpt_ctx *c, const mpt_particles *P, uint32_t step0, int nsteps, uint32_t flags,
-                     bool dev_step, bool persistent, hipStream_t s) {
+                     bool dev_step, bool persistent, hipStream_t s, bool keys = false) {
   StepArgs a;
   fill_step_args(c, P, step0, nsteps, flags, a);
   if (dev_step) a.step_dev = c->step_dev;
   if (persistent && P->scen) {
     a.persistent = 1;
     a.nblk = kPersistentBlocks;
+  }
+  if (keys) {
+    if (launch_clear_spread(c->spread, (c->nkeys + 15) / 16, s) != hipSuccess) return MPT_ERR_HIP;
+    a.sk = c->sk;
   }
   return from_hip(launch_step(c->grid.dtype, c->params.math == MPT_MATH_F64, a, s));
 }
@@ -386,19 +404,30 @@ mpt_status run_steps(mpt_ctx *c, const mpt_particles *P, uint32_t step0, int nst
 // one sort window or starting with its sort: sort at window starts, fused
 // launches of at most params.fuse steps.  Step indices are offsets from the
 // device step index when dev_step.
+// Without scenarios, a launch that ends where a sort follows also leaves
+// the sort keys of its final positions, and that sort skips its key pass;
+// with params.presort the call's last launch does the same and the keys are
+// kept for the next sort of the same parcels (mpt_sort_particles, or the
+// sort the next call starts with).  Graph-captured sequences (dev_step)
+// keep nothing across calls.
 mpt_status enqueue_steps(mpt_ctx *c, mpt_particles *P, int64_t first, int64_t count, bool dev_step,
                          hipStream_t s) {
   const int S = c->params.sort_interval;
   const uint32_t flags = c->params.flags;
+  // keys carried from the previous call hold for a sort this call starts with
+  bool keys_ready = S > 0 && !P->scen && !dev_step && c->keyed && c->keyed_lon == P->lon &&
+                    c->keyed_n == P->n && first % S == 0;
+  c->keyed = false;
   bool sorted = false;
   int64_t cur = first;
   const int64_t end = first + count;
   while (cur < end) {
     if (S > 0 && cur % S == 0) {
-      mpt_status st = do_sort(c, P, (uint32_t)cur, dev_step, s);
+      mpt_status st = do_sort(c, P, (uint32_t)cur, dev_step, s, keys_ready);
       if (st != MPT_OK) return st;
       sorted = true;
     }
+    keys_ready = false;
     int64_t stop = end;
     if (S > 0) {
       const int64_t next_sort = (cur / S + 1) * S;
@@ -406,10 +435,19 @@ mpt_status enqueue_steps(mpt_ctx *c, mpt_particles *P, int64_t first, int64_t co
     }
     if (stop - cur > c->params.fuse) stop = cur + c->params.fuse;
     if (flags) {
-      mpt_status st = run_steps(c, P, (uint32_t)cur, (int)(stop - cur), flags, dev_step, sorted, s);
+      // (the key buffers hold n_max parcels)
+      const bool keys = !P->scen && P->n <= c->n_max &&
+                        (stop < end ? S > 0 && stop % S == 0 : c->params.presort && !dev_step);
+      mpt_status st = run_steps(c, P, (uint32_t)cur, (int)(stop - cur), flags, dev_step, sorted, s, keys);
       if (st != MPT_OK) return st;
+      keys_ready = keys;
     }
     cur = stop;
+  }
+  if (keys_ready) {
+    c->keyed = true;
+    c->keyed_lon = P->lon;
+    c->keyed_n = P->n;
   }
   return MPT_OK;
 }
@@ -486,6 +524,7 @@ mpt_status mpt_create(const mpt_grid *grid, const mpt_params *params, int64_t n_
   c->scales = reinterpret_cast<float *>(ws + L.scales);
   c->t_scales = reinterpret_cast<float *>(ws + L.t_scales);
   c->sfc = reinterpret_cast<float4 *>(ws + L.sfc);
+  c->sk = reinterpret_cast<SortKeyArgs *>(ws + L.sk);
   c->plev = reinterpret_cast<double *>(ws + L.plev);
   c->inv_dp = reinterpret_cast<double *>(ws + L.inv_dp);
   c->lut = reinterpret_cast<uint16_t *>(ws + L.lut);
@@ -541,7 +580,16 @@ mpt_status mpt_create(const mpt_grid *grid, const mpt_params *params, int64_t n_
   }
   c->lut_lo = (float)lo;
   c->lut_scale = (float)scale;
-  if (hipMemcpy(c->plev, c->plev_h, sizeof(double) * grid->nz, hipMemcpyHostToDevice) != hipSuccess ||
+  SortKeyArgs skh;
+  skh.keys = c->keys;
+  skh.ranks = c->ranks;
+  skh.spread = c->spread;
+  skh.spread_s = (c->nkeys + 15) / 16;
+  skh.ntx = c->ntx;
+  skh.nty = c->nty;
+  skh.nkeys = c->nkeys;
+  if (hipMemcpy(c->sk, &skh, sizeof(skh), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->plev, c->plev_h, sizeof(double) * grid->nz, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->inv_dp, idp, sizeof(double) * grid->nz, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->lut, lut, sizeof(uint16_t) * kLutBins, hipMemcpyHostToDevice) != hipSuccess) {
     delete c;
@@ -699,6 +747,7 @@ mpt_status mpt_advect(mpt_ctx *c, const mpt_particles *P, uint32_t step, void *h
   if (st != MPT_OK) return st;
   st = check_time(c, step, 1);
   if (st != MPT_OK) return st;
+  c->keyed = false;                                  // positions move
   if (P->n == 0 || !(c->params.flags & MPT_ADVECT)) return MPT_OK;
   return run_steps(c, P, step, 1, MPT_ADVECT, false, false, static_cast<hipStream_t>(hip_stream));
 }
@@ -709,6 +758,7 @@ mpt_status mpt_diffuse(mpt_ctx *c, const mpt_particles *P, uint32_t step, void *
   if (st != MPT_OK) return st;
   st = check_time(c, step, 1);
   if (st != MPT_OK) return st;
+  c->keyed = false;                                  // positions move
   const uint32_t f = c->params.flags & (MPT_TURB | MPT_MESO);
   if (P->n == 0 || !f) return MPT_OK;
   return run_steps(c, P, step, 1, f, false, false, static_cast<hipStream_t>(hip_stream));
@@ -719,7 +769,9 @@ mpt_status mpt_sort_particles(mpt_ctx *c, mpt_particles *P, void *hip_stream) {
   const mpt_status st = check_particles(c, P, true);
   if (st != MPT_OK) return st;
   if (P->n == 0) return MPT_OK;
-  return do_sort(c, P, 0u, false, static_cast<hipStream_t>(hip_stream));
+  const bool keys_done = c->keyed && !P->scen && c->keyed_lon == P->lon && c->keyed_n == P->n;
+  c->keyed = false;
+  return do_sort(c, P, 0u, false, static_cast<hipStream_t>(hip_stream), keys_done);
 }
 
 mpt_status mpt_step(mpt_ctx *c, mpt_particles *P, uint32_t step0, int32_t nsteps, void *hip_stream) {
@@ -754,6 +806,7 @@ mpt_status mpt_step_graph(mpt_ctx *c, mpt_particles *P, uint32_t step0, int32_t 
   st = check_phys(c);
   if (st != MPT_OK) return st;
   if (P->n == 0 || nsteps == 0) return MPT_OK;
+  c->keyed = false;                                  // replays keep no keys across calls
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   const bool same = c->graph_exec && memcmp(&c->graph_key, P, sizeof(*P)) == 0 &&
                     c->graph_nsteps == 2 * S;
@@ -907,6 +960,7 @@ mpt_status mpt_step_surrogate(mpt_ctx *c, mpt_particles *P, uint32_t step0, int3
   if (P->n == 0 || nsteps == 0) return MPT_OK;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   if (P->n > c->n_max) return MPT_ERR_WORKSPACE;      // the fallback list lives in the key buffer
+  c->keyed = false;
   const SurrW W = loaded_weights(c);
   for (int64_t b0 = step0; b0 < (int64_t)step0 + nsteps; b0 += kSurrK) {
     bool due = false;

@@ -75,7 +75,7 @@ def test_bad_grid_is_rejected(case):
 
 
 @pytest.mark.parametrize("case", ["dt", "turb", "sort", "fuse", "flags", "math", "conv_cape",
-                                  "sedi_radius", "sedi_density"])
+                                  "sedi_radius", "sedi_density", "presort", "reserved"])
 def test_bad_params_are_rejected(case):
     g, plev, p = grid_params()
     if case == "dt":
@@ -97,6 +97,10 @@ def test_bad_params_are_rejected(case):
     elif case == "sedi_density":
         p.flags |= mpt.SEDI
         p.sedi_density = -1.0
+    elif case == "presort":
+        p.presort = 2
+    elif case == "reserved":
+        p.reserved = 1
     else:
         p.math = 3
     assert ws_bytes(g, p) == 0

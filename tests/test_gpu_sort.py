@@ -10,7 +10,7 @@ import pytest
 
 import inputs
 import oracle
-from gpu_common import require_gpu, say
+from gpu_common import by_id, oracle_run, require_gpu, say
 
 pytestmark = pytest.mark.gpu
 
@@ -73,3 +73,90 @@ def test_sort_runs_ragged_and_resorted(mpt, met3, n, math):
         ctx.sort(P)
         torch.cuda.synchronize()
         check_sorted(met3, P.to_host(), part, math)
+
+
+def sorted_by_oracle_keys(met, h, frac=0.0):
+    """The tile keys of the oracle never decrease along the array, except for
+    at most frac of the places (positions within rounding of a boundary)."""
+    keys = oracle.tile_keys(oracle.Met(met), h.lon, h.lat, h.p).astype(np.int64)
+    bad = int(np.sum(np.diff(keys) < 0))
+    assert bad <= frac * len(keys), bad
+    return keys
+
+
+@pytest.mark.parametrize("form", [(0, 0), (1, 0), (1, 1)])
+def test_presort_keys_from_the_step(mpt, met3, form):
+    """presort: the step's last launch leaves the keys of the final positions;
+    the sort that follows uses them instead of its key pass and orders the
+    parcels as that pass would (and moves the whole state with them)."""
+    import torch
+    math, dtype = form
+    say(f"[sort] presort math={math} dtype={dtype}")
+    part = inputs.make_particles(20_011, 61)
+    out = []
+    for presort in (1, 0):
+        ctx = mpt.Context(met3, mpt.make_params(math=math, fuse=10, presort=presort), n_max=part.n, dtype=dtype)
+        ctx.upload_met(met3)
+        P = mpt.DeviceParticles.from_host(part, math=math)
+        ctx.step(P, 0, 10)
+        ctx.sort(P)
+        torch.cuda.synchronize()
+        h = P.to_host()
+        np.testing.assert_array_equal(np.sort(h.id), np.arange(part.n, dtype=np.uint32))
+        out.append((sorted_by_oracle_keys(met3, h), by_id(h)))
+    np.testing.assert_array_equal(out[0][0], out[1][0])        # the same key sequence
+    for f in ("lon", "lat", "p", "up", "vp", "wp"):
+        np.testing.assert_array_equal(getattr(out[0][1], f), getattr(out[1][1], f))
+
+
+def test_sorts_inside_a_call_use_the_launch_keys(mpt, met3):
+    """mpt_step with sort_interval 10: the sort at step 10 takes its keys from
+    the launch that ends there; the parcels leave the call in the order of
+    their cells at step 10 (by the oracle's positions at step 10)."""
+    import torch
+    part = inputs.make_particles(20_000, 62)
+    ctx = mpt.Context(met3, mpt.make_params(math=0, sort_interval=10, fuse=10), n_max=part.n)
+    ctx.upload_met(met3)
+    P = mpt.DeviceParticles.from_host(part, math=0)
+    ctx.step(P, 0, 20)
+    torch.cuda.synchronize()
+    h = P.to_host()
+    at10 = oracle_run(met3, part, 0, 10)                        # ordered by id
+    order10 = at10.subset(h.id.astype(np.int64))
+    sorted_by_oracle_keys(met3, order10, frac=1e-3)
+
+
+def test_presort_keys_of_changed_positions_still_permute(mpt, met3):
+    """Positions changed by the caller between the step and the sort: the sort
+    follows the stale keys, but every parcel's whole state moves together."""
+    import torch
+    part = inputs.make_particles(5_000, 63)
+    ctx = mpt.Context(met3, mpt.make_params(math=0, fuse=10, presort=1), n_max=part.n)
+    ctx.upload_met(met3)
+    P = mpt.DeviceParticles.from_host(part, math=0)
+    ctx.step(P, 0, 10)
+    torch.cuda.synchronize()
+    P.lat.mul_(-1.0)                                            # the caller moves the parcels
+    before = by_id(P.to_host())
+    ctx.sort(P)
+    torch.cuda.synchronize()
+    h = P.to_host()
+    np.testing.assert_array_equal(np.sort(h.id), np.arange(part.n, dtype=np.uint32))
+    for f in ("lon", "lat", "p", "up", "vp", "wp"):
+        np.testing.assert_array_equal(getattr(by_id(h), f), getattr(before, f))
+
+
+def test_presort_keys_dropped_by_other_calls(mpt, met3):
+    """A call that moves the parcels without keys (mpt_advect) drops them:
+    the next sort orders by the current positions."""
+    import torch
+    part = inputs.make_particles(20_000, 64)
+    ctx = mpt.Context(met3, mpt.make_params(math=0, fuse=10, presort=1), n_max=part.n)
+    ctx.upload_met(met3)
+    P = mpt.DeviceParticles.from_host(part, math=0)
+    ctx.step(P, 0, 10)
+    for s in range(10, 40):
+        ctx.advect(P, s)
+    ctx.sort(P)
+    torch.cuda.synchronize()
+    sorted_by_oracle_keys(met3, P.to_host())
