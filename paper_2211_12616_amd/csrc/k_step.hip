@@ -116,8 +116,19 @@ __device__ __forceinline__ void step_body(const StepArgs &a) {
     const int64_t c_lo = nchunks * xcd / kXcds, c_hi = nchunks * (xcd + 1) / kXcds;
     for (int64_t c = c_lo + q; c < c_hi; c += nq) {
       const int64_t j = c * kBlock + threadIdx.x;
-      double lon, lat, p;
-      if (j < cnt) step_parcel<F, R, P>(a, s_plev, s_idp, s_lut, (int64_t)a.index[j], step0, lon, lat, p);
+      double lon = 0.0, lat = 0.0, p = 0.0;
+      const bool valid = j < cnt;
+      const int64_t i = valid ? (int64_t)a.index[j] : 0;
+      if (valid) step_parcel<F, R, P>(a, s_plev, s_idp, s_lut, i, step0, lon, lat, p);
+      if (a.sk) {                         // keys for the sort that follows (uniform)
+        const SortKeyArgs sk = *a.sk;
+        const uint32_t key = valid ? tile_key(a, sk, s_plev, s_lut, lon, lat, p) : 0xFFFFFFFFu;
+        const uint32_t rank = wave_key_rank(sk, key, valid);
+        if (valid) {
+          sk.keys[i] = key;
+          sk.ranks[i] = rank;
+        }
+      }
     }
   } else if constexpr (M == kModeBlock) {
     const int lb = logical_block((int)blockIdx.x, a.per_xcd);

@@ -734,59 +734,11 @@ __global__ __launch_bounds__(256) void k_surr_x(const StepArgs a, const SurrW W,
   }
 }
 
-// Consistency estimate, then acceptance (displacement, then the block's
-// diffusion) or fallback, for parcels i0 .. i0 + cnt - 1 with predictions Y
-// (4 floats per row).  Every wave
-// records the ballot of its parcels that fall back in fb_mask[i / 64]
-// (i0 is a multiple of 64), from which an ordered list is built.
-__global__ __launch_bounds__(256) void k_surr_apply(const StepArgs a, float tau_km, const float *Y,
-                                                    int64_t i0, int64_t cnt, float *err_out,
-                                                    uint64_t *fb_mask) {
-  const int lb = logical_block((int)blockIdx.x, a.per_xcd);
-  if (lb >= a.nblk) return;
-  const int64_t r = (int64_t)lb * 256 + threadIdx.x;
-  const int l = threadIdx.x & 63;
-  if (r - l >= cnt) return;                          // the whole wave is past the chunk
-  const int64_t i = i0 + r;
-  const bool in_range = r < cnt;
-  double lon = 0.0, lat = 0.0, p = 0.0;
-  if (in_range) {
-    lon = a.lon[i];
-    lat = a.lat[i];
-    p = a.p[i];
-  }
-  const bool valid = in_range && finite3(lon, lat, p);
-  const double t0 = a.t_start + (double)a.step0 * a.dt;
+// The accepted block of parcel i: the predicted displacement, then the
+// block's diffusion drawn at once; lon, lat, p receive the final position.
+__device__ __forceinline__ void apply_block(const StepArgs &a, int64_t i, double t0, float de, float dn,
+                                            float dpp, float c0, double &lon, double &lat, double &p) {
   const float kdeg = (float)kDeg;
-  float de = 0.f, dn = 0.f, dpp = 0.f, c0 = 1.f;
-  bool accept = false;
-  if (valid) {
-    const float4 yv = *reinterpret_cast<const float4 *>(Y + r * 4);
-    de = yv.x;
-    dn = yv.y;
-    dpp = yv.z;
-    // consistency estimate: kSurrK dt times the wind at the predicted midpoint
-    c0 = cos_floor<float>(a, lat);
-    const double lonm = lon + (double)(0.5f * de * 1000.0f * kdeg / c0);
-    const double latm = lat + (double)(0.5f * dn * 1000.0f * kdeg);
-    const double pm = p + (double)(0.5f * dpp);
-    Cell16<kF32> cell;
-    Loc<float> Lm;
-    surr_locate(a, lonm, latm, pm, t0 + 0.5 * kSurrK * a.dt, Lm);
-    load_cell<kF32, float>(a, Lm, cell);
-    float wm[3];
-    interp_cell<kF32, float>(a, cell, Lm, wm);
-    const float span = (float)(kSurrK * a.dt) * 1e-3f;
-    const float ee = de - span * wm[0], en = dn - span * wm[1];
-    const float err = sqrtf(ee * ee + en * en);
-    if (err_out) err_out[i] = err;
-    accept = err <= tau_km && isfinite(err);
-  }
-  // parcels that fall back keep their state here; the plain step kernel
-  // takes them from the ordered list (whose scan also gives their count)
-  const uint64_t fb = __ballot(valid && !accept);
-  if (l == 0) fb_mask[i / 64] = fb;
-  if (!valid || !accept) return;
   const uint32_t id = a.id[i];
   float up = static_cast<const float *>(a.up)[i];
   float vp = static_cast<const float *>(a.vp)[i];
@@ -842,6 +794,73 @@ __global__ __launch_bounds__(256) void k_surr_apply(const StepArgs a, float tau_
   static_cast<float *>(a.up)[i] = up;
   static_cast<float *>(a.vp)[i] = vp;
   static_cast<float *>(a.wp)[i] = wp;
+}
+
+// Consistency estimate, then acceptance (displacement, then the block's
+// diffusion) or fallback, for parcels i0 .. i0 + cnt - 1 with predictions Y
+// (4 floats per row).  Every wave
+// records the ballot of its parcels that fall back in fb_mask[i / 64]
+// (i0 is a multiple of 64), from which an ordered list is built.
+__global__ __launch_bounds__(256) void k_surr_apply(const StepArgs a, float tau_km, const float *Y,
+                                                    int64_t i0, int64_t cnt, float *err_out,
+                                                    uint64_t *fb_mask) {
+  const int lb = logical_block((int)blockIdx.x, a.per_xcd);
+  if (lb >= a.nblk) return;
+  const int64_t r = (int64_t)lb * 256 + threadIdx.x;
+  const int l = threadIdx.x & 63;
+  if (r - l >= cnt) return;                          // the whole wave is past the chunk
+  const int64_t i = i0 + r;
+  const bool in_range = r < cnt;
+  double lon = 0.0, lat = 0.0, p = 0.0;
+  if (in_range) {
+    lon = a.lon[i];
+    lat = a.lat[i];
+    p = a.p[i];
+  }
+  const bool valid = in_range && finite3(lon, lat, p);
+  const double t0 = a.t_start + (double)a.step0 * a.dt;
+  const float kdeg = (float)kDeg;
+  float de = 0.f, dn = 0.f, dpp = 0.f, c0 = 1.f;
+  bool accept = false;
+  if (valid) {
+    const float4 yv = *reinterpret_cast<const float4 *>(Y + r * 4);
+    de = yv.x;
+    dn = yv.y;
+    dpp = yv.z;
+    // consistency estimate: kSurrK dt times the wind at the predicted midpoint
+    c0 = cos_floor<float>(a, lat);
+    const double lonm = lon + (double)(0.5f * de * 1000.0f * kdeg / c0);
+    const double latm = lat + (double)(0.5f * dn * 1000.0f * kdeg);
+    const double pm = p + (double)(0.5f * dpp);
+    Cell16<kF32> cell;
+    Loc<float> Lm;
+    surr_locate(a, lonm, latm, pm, t0 + 0.5 * kSurrK * a.dt, Lm);
+    load_cell<kF32, float>(a, Lm, cell);
+    float wm[3];
+    interp_cell<kF32, float>(a, cell, Lm, wm);
+    const float span = (float)(kSurrK * a.dt) * 1e-3f;
+    const float ee = de - span * wm[0], en = dn - span * wm[1];
+    const float err = sqrtf(ee * ee + en * en);
+    if (err_out) err_out[i] = err;
+    accept = err <= tau_km && isfinite(err);
+  }
+  // parcels that fall back keep their state here; the plain step kernel
+  // takes them from the ordered list (whose scan also gives their count)
+  const uint64_t fb = __ballot(valid && !accept);
+  if (l == 0) fb_mask[i / 64] = fb;
+  if (valid && accept) apply_block(a, i, t0, de, dn, dpp, c0, lon, lat, p);
+  if (a.sk) {
+    // keys for the sort that follows: accepted parcels (final position) and
+    // non-finite ones here, fallbacks after their plain steps
+    const SortKeyArgs sk = *a.sk;
+    const bool keyed = in_range && (accept || !valid);
+    const uint32_t key = keyed ? tile_key(a, sk, a.plev, a.lut, lon, lat, p) : 0xFFFFFFFFu;
+    const uint32_t rank = wave_key_rank(sk, key, keyed);
+    if (keyed) {
+      sk.keys[i] = key;
+      sk.ranks[i] = rank;
+    }
+  }
 }
 
 // off[w] = number of set bits of fb_mask[w] for w < nw, off[nw] = 0.

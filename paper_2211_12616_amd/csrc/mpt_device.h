@@ -767,20 +767,21 @@ __device__ __forceinline__ uint32_t tile_key(const StepArgs &a, const SortKeyArg
 }
 
 // Rank of each valid lane's key among the parcels of that key: runs of
-// equal keys in the wave (valid lanes form a prefix) add their length to
-// the key's counter once; a lane's rank is the run's old counter value plus
-// its place in the run.  Every lane must call it.
+// equal keys over consecutive valid lanes (invalid lanes may sit anywhere)
+// add their length to the key's counter once; a lane's rank is the run's
+// old counter value plus its place in the run.  Every lane must call it.
 __device__ __forceinline__ uint32_t wave_key_rank(const SortKeyArgs &sk, uint32_t key, bool valid) {
   const int lane = (int)__lane_id();
-  uint32_t prev = __shfl_up(key, 1);
-  if (lane == 0) prev = ~key;
-  const uint64_t heads = __ballot(valid && prev != key);
-  const int nvalid = __popcll(__ballot(valid));
+  const uint32_t prev = __shfl_up(key, 1);
+  const uint64_t valids = __ballot(valid);
+  const bool prev_valid = lane > 0 && ((valids >> (lane - 1)) & 1ull);
+  const uint64_t heads = __ballot(valid && (!prev_valid || prev != key));
+  const uint64_t breaks = heads | ~valids;               // a run ends before these lanes
   const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);   // lanes <= lane
   uint32_t base = 0;
   if ((heads >> lane) & 1ull) {
-    const uint64_t above = heads & ~upto;
-    const int end = above ? __ffsll((long long)above) - 1 : nvalid;
+    const uint64_t above = breaks & ~upto;
+    const int end = above ? __ffsll((long long)above) - 1 : 64;
     base = atomicAdd(sk.spread + (key & 15u) * sk.spread_s + (key >> 4), (uint32_t)(end - lane));
   }
   const uint64_t le = heads & upto;

@@ -61,6 +61,7 @@ struct mpt_ctx {
   int64_t s_chunk;
   float4 *s_f;                          // FP32 field at a surrogate block's start time
   uint64_t *fb_mask;                    // per wave of 64 parcels: ballot of surrogate fallbacks
+  uint32_t *fb_list;                    // indices of the parcels that fall back (n_max)
   uint32_t *fb_off, *fb_sums;           // its prefix sums (+ total) and scan scratch
   float s_tau;
   int s_loaded;
@@ -126,7 +127,7 @@ mpt_status check_params(const mpt_params *p, const mpt_grid *g) {
 
 struct Layout {
   size_t met, scales, t_scales, sfc, sk, plev, inv_dp, lut, release, rank, rel_sorted, step_dev, keys, ranks, hist, spread,
-      block_sums, out_pe, hyb_ab, s_wt, s_wb, s_wi, s_norm, s_bias, s_x, s_y, s_f, fb_mask, fb_off, fb_sums, t_xn, t_h, t_dy, t_dh, t_yp, t_grad, t_part, total;
+      block_sums, out_pe, hyb_ab, s_wt, s_wb, s_wi, s_norm, s_bias, s_x, s_y, s_f, fb_mask, fb_list, fb_off, fb_sums, t_xn, t_h, t_dy, t_dh, t_yp, t_grad, t_part, total;
   uint32_t ntx, nty, ntz, ntiles, nkeys;
   int64_t s_chunk;
 };
@@ -177,6 +178,7 @@ Layout layout(const mpt_grid *g, int64_t n_max) {
   L.s_f = off;        off += g->dtype == MPT_DT_F32 ? align_up(npts * 16) : 0;   // surrogate needs F32 fields
   const size_t nw = (size_t)((n_max > 0 ? n_max : 0) + 63) / 64;
   L.fb_mask = off;    off += align_up(sizeof(uint64_t) * nw);
+  L.fb_list = off;    off += align_up(sizeof(uint32_t) * (size_t)(n_max > 0 ? n_max : 0));
   L.fb_off = off;     off += align_up(sizeof(uint32_t) * (nw + 1));
   L.fb_sums = off;    off += align_up(sizeof(uint32_t) * scan_block_sums_len((uint32_t)(nw + 1)));
   L.t_xn = off;       off += align_up(sizeof(uint16_t) * kSurrMaxBatch * kSurrInPad);
@@ -550,6 +552,7 @@ mpt_status mpt_create(const mpt_grid *grid, const mpt_params *params, int64_t n_
   c->s_chunk = L.s_chunk;
   c->s_f = reinterpret_cast<float4 *>(ws + L.s_f);
   c->fb_mask = reinterpret_cast<uint64_t *>(ws + L.fb_mask);
+  c->fb_list = reinterpret_cast<uint32_t *>(ws + L.fb_list);
   c->fb_off = reinterpret_cast<uint32_t *>(ws + L.fb_off);
   c->fb_sums = reinterpret_cast<uint32_t *>(ws + L.fb_sums);
   c->t_xn = reinterpret_cast<uint16_t *>(ws + L.t_xn);
@@ -959,19 +962,29 @@ mpt_status mpt_step_surrogate(mpt_ctx *c, mpt_particles *P, uint32_t step0, int3
   if (st != MPT_OK) return st;
   if (P->n == 0 || nsteps == 0) return MPT_OK;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  if (P->n > c->n_max) return MPT_ERR_WORKSPACE;      // the fallback list lives in the key buffer
+  if (P->n > c->n_max) return MPT_ERR_WORKSPACE;      // fallback list and sort keys hold n_max
   c->keyed = false;
   const SurrW W = loaded_weights(c);
-  for (int64_t b0 = step0; b0 < (int64_t)step0 + nsteps; b0 += kSurrK) {
-    bool due = false;
-    for (int64_t q = b0; S > 0 && q < b0 + kSurrK; ++q)
-      if (q % S == 0) due = true;
-    if (due) {
-      st = do_sort(c, P, (uint32_t)b0, false, s);
+  const int64_t end = (int64_t)step0 + nsteps;
+  // a block sorts first when a multiple of sort_interval falls in it; the
+  // block before such a block leaves the sort keys of its final positions
+  // (apply for accepted and non-finite parcels, the plain steps for the rest)
+  auto sort_due = [&](int64_t b) {
+    for (int64_t q = b; S > 0 && q < b + kSurrK; ++q)
+      if (q % S == 0) return true;
+    return false;
+  };
+  bool keys_ready = false;
+  for (int64_t b0 = step0; b0 < end; b0 += kSurrK) {
+    if (sort_due(b0)) {
+      st = do_sort(c, P, (uint32_t)b0, false, s, keys_ready);
       if (st != MPT_OK) return st;
     }
+    const bool keys = b0 + kSurrK < end && sort_due(b0 + kSurrK);
+    if (keys && launch_clear_spread(c->spread, (c->nkeys + 15) / 16, s) != hipSuccess) return MPT_ERR_HIP;
     StepArgs a;
     fill_step_args(c, P, (uint32_t)b0, kSurrK, c->params.flags, a);
+    if (keys) a.sk = c->sk;
     if (launch_surr_tfield(a, c->params.t_start + (double)b0 * c->params.dt, c->s_f, s) != hipSuccess)
       return MPT_ERR_HIP;
     for (int64_t i0 = 0; i0 < P->n; i0 += c->s_chunk) {
@@ -981,16 +994,18 @@ mpt_status mpt_step_surrogate(mpt_ctx *c, mpt_particles *P, uint32_t step0, int3
           launch_surr_apply(a, c->s_tau, c->s_y, i0, cnt, err_out, c->fb_mask, s) != hipSuccess)
         return MPT_ERR_HIP;
     }
-    if (launch_surr_fblist(c->fb_mask, P->n, c->fb_off, c->fb_sums, c->keys, fallbacks, s) != hipSuccess)
+    if (launch_surr_fblist(c->fb_mask, P->n, c->fb_off, c->fb_sums, c->fb_list, fallbacks, s) != hipSuccess)
       return MPT_ERR_HIP;
     // parcels that fell back: kSurrK plain steps, walking the list
     StepArgs f;
     fill_step_args(c, P, (uint32_t)b0, kSurrK, c->params.flags, f);
-    f.index = c->keys;
+    f.index = c->fb_list;
     f.index_count = c->fb_off + (P->n + 63) / 64;
     f.nblk = kPersistentBlocks;
     f.persistent = 1;
+    if (keys) f.sk = c->sk;
     if (launch_step(c->grid.dtype, 0, f, s) != hipSuccess) return MPT_ERR_HIP;
+    keys_ready = keys;
   }
   return MPT_OK;
 }

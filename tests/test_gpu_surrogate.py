@@ -268,3 +268,50 @@ def test_block_diffusion_matches_plain_statistics(mpt, met3, turb):
         ep, es = (hp.up, hp.vp, hp.wp)[q][m], (hs.up, hs.vp, hs.wp)[q][m]
         assert abs(es.var() / ep.var() - 1.0) < 0.05
         assert close(fit(ep, u0[q]), fit(es, u0[q]))
+
+
+def test_sort_keys_from_apply_and_fallback_steps(mpt, met3):
+    """The block before a sort leaves the sort keys: accepted parcels from the
+    apply kernel, fallbacks from their plain steps (tau = the median error,
+    so both kinds share waves).  After steps 0..24 with a sort at 16 the
+    parcels are ordered by their cells at step 16, and every parcel's state
+    equals the unsorted run's bit for bit."""
+    import torch
+    part = inputs.make_particles(20_000, 65)
+    lon, lat, p, step = starts(8192, 10)
+
+    def context(S):
+        c = mpt.Context(met3, mpt.make_params(math=1, sort_interval=S, flags=mpt.ADVECT), n_max=part.n)
+        c.upload_met(met3)
+        x, y = c.surrogate_datagen(*to_dev(lon, lat, p, step))
+        return c, x, y
+
+    c0, x, y = context(0)
+    norm = c0.surrogate_stats(x, y)
+    params = c0.surrogate_init(11)
+    c0.surrogate_load(params, norm, float("inf"))
+    P = mpt.DeviceParticles.from_host(part, math=1, pingpong=False)
+    fb = torch.zeros(1, dtype=torch.int32, device="cuda")
+    err = torch.empty(part.n, dtype=torch.float32, device="cuda")
+    c0.step_surrogate(P, 0, 8, fb, err)
+    tau = float(np.median(err.cpu().numpy()))
+
+    def run(S, nsteps):
+        c, _, _ = context(S)
+        c.surrogate_load(params, norm, tau)
+        Q = mpt.DeviceParticles.from_host(part, math=1)
+        f = torch.zeros(1, dtype=torch.int32, device="cuda")
+        c.step_surrogate(Q, 0, nsteps, f)
+        torch.cuda.synchronize()
+        return Q.to_host(), f.item()
+
+    a, fa = run(16, 24)                   # sorts at 0 and 16 (keys from the block 8..16)
+    at16, _ = run(16, 16)
+    plain, _ = run(0, 24)
+    say(f"[surrogate keys] tau {tau:.3f} km, fallbacks {fa} of {3 * part.n} parcel-blocks")
+    assert 0.2 * 3 * part.n < fa < 0.8 * 3 * part.n
+    np.testing.assert_array_equal(np.sort(a.id), np.arange(part.n, dtype=np.uint32))
+    assert_bitwise(by_id(a), by_id(plain))
+    pos16 = by_id(at16).subset(a.id.astype(np.int64))
+    keys = oracle.tile_keys(oracle.Met(met3), pos16.lon, pos16.lat, pos16.p).astype(np.int64)
+    assert np.sum(np.diff(keys) < 0) <= 1e-3 * part.n
