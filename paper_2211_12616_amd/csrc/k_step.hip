@@ -93,6 +93,21 @@ __device__ __forceinline__ int64_t active_bound(const StepArgs &a, uint32_t last
 
 enum : int { kModeBlock = 0, kModePersistent = 1, kModeIndex = 2 };
 
+// The sort key and rank of parcel i's final position, for the sort that
+// follows the launch.  Every lane of the wave calls it (valid: lane holds a
+// parcel).
+__device__ __forceinline__ void leave_sort_key(const StepArgs &a, const double *s_plev,
+                                               const uint16_t *s_lut, int64_t i, bool valid, double lon,
+                                               double lat, double p) {
+  const SortKeyArgs sk = *a.sk;
+  const uint32_t key = valid ? tile_key(a, sk, s_plev, s_lut, lon, lat, p) : 0xFFFFFFFFu;
+  const uint32_t rank = wave_key_rank(sk, key, valid);
+  if (valid) {
+    sk.keys[i] = key;
+    sk.ranks[i] = rank;
+  }
+}
+
 template <int M, int F, typename R, bool P>
 __device__ __forceinline__ void step_body(const StepArgs &a) {
   __shared__ double s_plev[kMaxLevels];
@@ -120,15 +135,7 @@ __device__ __forceinline__ void step_body(const StepArgs &a) {
       const bool valid = j < cnt;
       const int64_t i = valid ? (int64_t)a.index[j] : 0;
       if (valid) step_parcel<F, R, P>(a, s_plev, s_idp, s_lut, i, step0, lon, lat, p);
-      if (a.sk) {                         // keys for the sort that follows (uniform)
-        const SortKeyArgs sk = *a.sk;
-        const uint32_t key = valid ? tile_key(a, sk, s_plev, s_lut, lon, lat, p) : 0xFFFFFFFFu;
-        const uint32_t rank = wave_key_rank(sk, key, valid);
-        if (valid) {
-          sk.keys[i] = key;
-          sk.ranks[i] = rank;
-        }
-      }
+      if (a.sk) leave_sort_key(a, s_plev, s_lut, i, valid, lon, lat, p);   // uniform
     }
   } else if constexpr (M == kModeBlock) {
     const int lb = logical_block((int)blockIdx.x, a.per_xcd);
@@ -137,15 +144,7 @@ __device__ __forceinline__ void step_body(const StepArgs &a) {
     double lon = 0.0, lat = 0.0, p = 0.0;
     const bool valid = i < a.n;
     if (valid) step_parcel<F, R, P>(a, s_plev, s_idp, s_lut, i, step0, lon, lat, p);
-    if (a.sk) {                           // keys for the sort that follows (uniform)
-      const SortKeyArgs sk = *a.sk;
-      const uint32_t key = valid ? tile_key(a, sk, s_plev, s_lut, lon, lat, p) : 0xFFFFFFFFu;
-      const uint32_t rank = wave_key_rank(sk, key, valid);
-      if (valid) {
-        sk.keys[i] = key;
-        sk.ranks[i] = rank;
-      }
-    }
+    if (a.sk) leave_sort_key(a, s_plev, s_lut, i, valid, lon, lat, p);     // uniform
   } else {
     // persistent: XCD x owns an even share of the chunks of the prefix and
     // its blocks stride through that share
