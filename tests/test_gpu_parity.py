@@ -70,6 +70,48 @@ def test_empty(mpt, met3):
     assert P.n == 0
 
 
+@pytest.mark.parametrize("form", [(0, 0), (1, 0), (1, 1)])
+def test_empty_every_entry_point(mpt, met3, form):
+    """An empty set through every call that moves or orders parcels (with the
+    in-step sort keys, the graph-replayed loop, convection and sedimentation,
+    and the surrogate): each returns success and touches nothing; the
+    surrogate adds no fallbacks."""
+    import torch
+    math, dtype = form
+    part = inputs.make_particles(0, 1)
+    phys = inputs.add_phys_fields(inputs.make_met_c1(seed=11, nt=3), seed=31)
+    flags = oracle.ADVECT | oracle.TURB | oracle.MESO | oracle.CONV | oracle.SEDI
+    for met, fl in ((met3, None), (phys, flags)):
+        kw = {} if fl is None else {"flags": fl}
+        ctx = mpt.Context(met, mpt.make_params(math=math, sort_interval=10, fuse=10, presort=1, **kw),
+                          n_max=16, dtype=dtype)
+        ctx.upload_met(met)
+        P = mpt.DeviceParticles.from_host(part, math=math)
+        ctx.advect(P, 3)
+        ctx.diffuse(P, 3)
+        ctx.step(P, 0, 20)
+        ctx.sort(P)
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            ctx.step_graph(P, 20, 20, s)
+        torch.cuda.synchronize()
+        assert P.n == 0
+    if form != (1, 0):
+        return
+    ctx = mpt.Context(met3, mpt.make_params(math=1, sort_interval=16), n_max=4096)
+    ctx.upload_met(met3)
+    rng = np.random.default_rng(7)
+    x, y = ctx.surrogate_datagen(*(torch.from_numpy(a).cuda() for a in (
+        rng.uniform(0, 360, 1024), rng.uniform(-60, 60, 1024), rng.uniform(100, 900, 1024),
+        rng.integers(0, 200, 1024).astype(np.int32))))
+    ctx.surrogate_load(ctx.surrogate_init(3), ctx.surrogate_stats(x, y), 1.0)
+    P = mpt.DeviceParticles.from_host(part, math=1)
+    fb = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ctx.step_surrogate(P, 0, 64, fb)
+    torch.cuda.synchronize()
+    assert fb.item() == 0 and P.n == 0
+
+
 def test_step_equals_advect_then_diffuse(mpt, met3):
     import torch
     say("step == advect;diffuse bitwise")
