@@ -118,8 +118,9 @@ __device__ __forceinline__ void step_body(const StepArgs &a) {
     s_idp[q] = (q < a.nz - 1) ? a.inv_dp[q] : 0.0;
   }
   for (int q = threadIdx.x; q < kLutBins; q += kBlock) s_lut[q] = a.lut[q];
-  __syncthreads();
   const uint32_t step0 = a.step0 + (a.step_dev ? *a.step_dev : 0u);
+  if constexpr (F != kF32) stage_scale_window(a, met_level(a, a.t_start + (double)step0 * a.dt));
+  __syncthreads();
   if constexpr (M == kModeIndex) {
     // a list of parcel indices in increasing order: XCD x owns an even share
     // of its 256-entry chunks (a region of the sorted parcels) and its
@@ -185,6 +186,11 @@ void k_step_phys_f32(const StepArgs a) {
   step_body<M, F, float, true>(a);
 }
 
+// Dynamic LDS of the R16 kernels: the scale window.
+static size_t scale_window_bytes(const StepArgs &a) {
+  return (size_t)kScaleWin * 3 * (size_t)a.nz * sizeof(float);
+}
+
 template <int M>
 static hipError_t launch_mode(int field, int math_f64, const StepArgs &args, dim3 grid,
                               hipStream_t stream) {
@@ -195,9 +201,9 @@ static hipError_t launch_mode(int field, int math_f64, const StepArgs &args, dim
   } else if (field == kF32) {
     hipLaunchKernelGGL((k_step_f32<M, kF32>), grid, block, 0, stream, args);
   } else if (field == kBF16) {
-    hipLaunchKernelGGL((k_step_f32<M, kBF16>), grid, block, 0, stream, args);
+    hipLaunchKernelGGL((k_step_f32<M, kBF16>), grid, block, scale_window_bytes(args), stream, args);
   } else {
-    hipLaunchKernelGGL((k_step_f32<M, kF16>), grid, block, 0, stream, args);
+    hipLaunchKernelGGL((k_step_f32<M, kF16>), grid, block, scale_window_bytes(args), stream, args);
   }
   return hipGetLastError();
 }
@@ -213,15 +219,17 @@ static hipError_t launch_phys(int field, int math_f64, const StepArgs &args, dim
   } else if (field == kF32) {
     hipLaunchKernelGGL((k_step_phys_f32<M, kF32>), grid, block, 0, stream, args);
   } else if (field == kBF16) {
-    hipLaunchKernelGGL((k_step_phys_f32<M, kBF16>), grid, block, 0, stream, args);
+    hipLaunchKernelGGL((k_step_phys_f32<M, kBF16>), grid, block, scale_window_bytes(args), stream, args);
   } else {
-    hipLaunchKernelGGL((k_step_phys_f32<M, kF16>), grid, block, 0, stream, args);
+    hipLaunchKernelGGL((k_step_phys_f32<M, kF16>), grid, block, scale_window_bytes(args), stream, args);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_step(int field, int math_f64, const StepArgs &args, hipStream_t stream) {
   const dim3 grid((unsigned)(args.persistent ? args.nblk : args.per_xcd * kXcds));
+  // R16 storage: the launch's times must fit the scale window
+  if (field != kF32 && !r16_launch_fits(args.nsteps, args.dt, args.dt_met)) return hipErrorInvalidValue;
   if (args.flags & (kConv | kSedi)) {
     if (args.index) return hipErrorInvalidValue;
     if (args.persistent) return launch_phys<kModePersistent>(field, math_f64, args, grid, stream);

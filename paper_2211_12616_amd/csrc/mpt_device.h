@@ -238,6 +238,7 @@ template <typename R>
 struct Loc {
   int i0, i1, j, k;
   int l, l1;            // storage slots of the earlier and the later time level
+  int la;               // absolute index of the earlier time level
   R fx, fy, fz, ft;
 };
 
@@ -340,12 +341,18 @@ __device__ __forceinline__ void locate_xyz_g(const StepArgs &a, double lon, doub
 // resident levels are lev_first .. lev_first + nt - 1 (absolute indices,
 // level L at t_met0 + L dt_met), stored in a ring of nt slots starting at
 // slot_first; the pair is clamped to the resident window.
-template <typename R>
-__device__ __forceinline__ void locate_t(const StepArgs &a, double t, Loc<R> &L) {
+__device__ __forceinline__ int met_level(const StepArgs &a, double t) {
   double tl = floor((t - a.t_met0) * a.inv_dt_met);
   int l = (int)tl;
   if (tl < (double)a.lev_first) l = a.lev_first;
   if (l > a.lev_first + a.nt - 2) l = a.lev_first + a.nt - 2;
+  return l;
+}
+
+template <typename R>
+__device__ __forceinline__ void locate_t(const StepArgs &a, double t, Loc<R> &L) {
+  const int l = met_level(a, t);
+  L.la = l;
   int s0 = a.slot_first + (l - a.lev_first);
   if (s0 >= a.nt) s0 -= a.nt;
   const int s1 = s0 + 1 == a.nt ? 0 : s0 + 1;
@@ -404,7 +411,32 @@ __device__ __forceinline__ void load_cell(const StepArgs &a, const Loc<R> &L, Ce
   }
 }
 
-// Scales of the (time level, level) slabs a cell touches (R16 storage).
+// R16 storage: the step kernels keep the per-level scales of the met time
+// levels a launch reads in LDS (dynamic shared memory, kScaleWin x 3 x nz
+// floats): absolute level L at window row L % kScaleWin.  A launch whose
+// times span less than one met interval reads at most three consecutive
+// levels (the pair of its first time, and the next one); the host keeps
+// launches of R16 storage that short.
+constexpr int kScaleWin = 3;
+extern __shared__ float s_scale_win[];
+
+// Fills the window with the scales of levels lev .. lev + 2 (those that are
+// resident), lev being the earlier level of the launch's first time.  All
+// threads of the block call it; a barrier must follow before any read.
+__device__ __forceinline__ void stage_scale_window(const StepArgs &a, int lev) {
+  const int row = 3 * a.nz;
+  for (int q = threadIdx.x; q < kScaleWin * row; q += kBlock) {
+    const int d = q / row, r = q - d * row;
+    const int L = lev + d;
+    if (L > a.lev_first + a.nt - 1) continue;
+    int slot = a.slot_first + (L - a.lev_first);
+    if (slot >= a.nt) slot -= a.nt;
+    s_scale_win[(L % kScaleWin) * row + r] = a.scales[(int64_t)slot * row + r];
+  }
+}
+
+// Scales of the (time level, level) slabs a cell touches (R16 storage:
+// from the LDS window).
 template <int F, typename R>
 __device__ __forceinline__ void cell_scales(const StepArgs &a, const Loc<R> &L, float sc[2][2][3]) {
 #pragma unroll
@@ -414,7 +446,7 @@ __device__ __forceinline__ void cell_scales(const StepArgs &a, const Loc<R> &L, 
       if (F == kF32) {
         sc[dl][dk][0] = sc[dl][dk][1] = sc[dl][dk][2] = 1.0f;
       } else {
-        const float *s = a.scales + (int64_t)(dl ? L.l1 : L.l) * 3 * a.nz + (L.k + dk);
+        const float *s = s_scale_win + ((L.la + dl) % kScaleWin) * 3 * a.nz + (L.k + dk);
         sc[dl][dk][0] = s[0];
         sc[dl][dk][1] = s[a.nz];
         sc[dl][dk][2] = s[2 * a.nz];

@@ -122,6 +122,7 @@ mpt_status check_params(const mpt_params *p, const mpt_grid *g) {
                                  isfinite(p->sedi_density) && p->sedi_density > 0.0))
     return MPT_ERR_ARG;
   if (p->math == MPT_MATH_F64 && g->dtype != MPT_DT_F32) return MPT_ERR_UNSUPPORTED;
+  if (g->dtype != MPT_DT_F32 && r16_max_launch(p->dt, g->dt_met) < 1) return MPT_ERR_UNSUPPORTED;
   return MPT_OK;
 }
 
@@ -436,6 +437,10 @@ mpt_status enqueue_steps(mpt_ctx *c, mpt_particles *P, int64_t first, int64_t co
       if (next_sort < stop) stop = next_sort;
     }
     if (stop - cur > c->params.fuse) stop = cur + c->params.fuse;
+    if (c->grid.dtype != MPT_DT_F32) {
+      const int cap = r16_max_launch(c->params.dt, c->grid.dt_met);
+      if (stop - cur > cap) stop = cur + cap;
+    }
     if (flags) {
       // (the key buffers hold n_max parcels)
       const bool keys = !P->scen && P->n <= c->n_max &&

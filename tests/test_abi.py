@@ -112,6 +112,20 @@ def test_f64_with_16bit_storage_unsupported():
     assert create(g, p, nbytes=1 << 30) == -6
 
 
+@pytest.mark.parametrize("dtype", [mpt.DT_BF16, mpt.DT_F16])
+def test_16bit_storage_needs_half_a_step_inside_a_met_interval(dtype):
+    """16-bit storage keeps the scales of at most three met levels per
+    launch: a step whose half spans a whole met interval is unsupported."""
+    g, plev, p = grid_params(dtype=dtype, math=mpt.MATH_F32)
+    p.dt = 2.0 * g.dt_met
+    assert ws_bytes(g, p) == 0
+    assert create(g, p, nbytes=1 << 30) == -6
+    p.dt = 1.9 * g.dt_met
+    assert ws_bytes(g, p) > 0
+    g32, _, p32 = grid_params(math=mpt.MATH_F32, dt=2.0 * g.dt_met)
+    assert ws_bytes(g32, p32) > 0                       # FP32 storage: no limit
+
+
 def test_workspace_checks():
     g, plev, p = grid_params()
     assert create(g, p, ws=0) == -1                                   # null

@@ -248,6 +248,20 @@ def test_r16_form(mpt, met3, kind):
     reduced_precision_checks(met3, deq, part, 1, kind, f"c1 R16 {kind}")
 
 
+@pytest.mark.parametrize("kind", [encode.BF16, encode.F16])
+def test_r16_launches_across_met_levels(mpt, met3, kind):
+    """16-bit storage: the step kernels read the per-level scales of the met
+    levels a launch touches from LDS.  Launches that cross a met level (fuse
+    7: steps 117..123 cross the level at step 120) and long launches cut to
+    fit the window (fuse 200: 120 steps from step 5) equal one-step launches
+    bit for bit."""
+    say(f"[r16] launches across met levels, storage {kind}")
+    part = inputs.make_particles(3000, 29)
+    base = gpu_run(met3, part, 5, 235, math=1, dtype=kind, fuse=1)
+    for fuse in (7, 200):
+        assert_bitwise(base, gpu_run(met3, part, 5, 235, math=1, dtype=kind, fuse=fuse))
+
+
 def test_errors_on_gpu(mpt, met3):
     part = inputs.make_particles(100, 31)
     ctx = mpt.Context(met3, mpt.make_params(sort_interval=10), n_max=100)
