@@ -65,7 +65,10 @@ typedef enum { MPT_MATH_F64 = 0, MPT_MATH_F32 = 1 } mpt_math;
 
 /* Storage of the wind fields.  BF16 / F16 store q = RNE(f / s) with one FP32
  * scale s = max|f| per (variable, level, time level) and decode q * s in
- * FP32.  BF16 and F16 require MPT_MATH_F32. */
+ * FP32.  BF16 and F16 require MPT_MATH_F32 and dt <= 1.998 dt_met (else
+ * MPT_ERR_UNSUPPORTED); their kernel launches advance at most
+ * floor(0.999 dt_met / dt + 1/2) steps whatever fuse says, so that the
+ * times one launch reads span less than one met interval. */
 typedef enum { MPT_DT_F32 = 0, MPT_DT_BF16 = 1, MPT_DT_F16 = 2 } mpt_dtype;
 
 /* Module flags (mpt_params.flags).  MPT_CONV and MPT_SEDI (module_convection
