@@ -262,6 +262,31 @@ def test_r16_launches_across_met_levels(mpt, met3, kind):
         assert_bitwise(base, gpu_run(met3, part, 5, 235, math=1, dtype=kind, fuse=fuse))
 
 
+def test_r16_graph_with_launches_cut_at_the_window(mpt):
+    """The graph-replayed loop with 16-bit storage and a sort interval longer
+    than the launch limit (150 > 120 steps): the captured launches are cut
+    the same way and the replays equal the eager loop bit for bit."""
+    import torch
+    say("[r16] graph, sort interval 150, launches cut to 120 steps")
+    met = inputs.make_met_c1(seed=11, nt=4)
+    part = inputs.make_particles(3000, 30)
+    out = []
+    for graph in (False, True):
+        ctx = mpt.Context(met, mpt.make_params(math=1, sort_interval=150, fuse=150), n_max=part.n,
+                          dtype=encode.BF16)
+        ctx.upload_met(met)
+        P = mpt.DeviceParticles.from_host(part, math=1)
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            if graph:
+                ctx.step_graph(P, 0, 300, s)
+            else:
+                ctx.step(P, 0, 300, s)
+        torch.cuda.synchronize()
+        out.append(by_id(P.to_host()))
+    assert_bitwise(out[0], out[1])
+
+
 def test_errors_on_gpu(mpt, met3):
     part = inputs.make_particles(100, 31)
     ctx = mpt.Context(met3, mpt.make_params(sort_interval=10), n_max=100)
