@@ -379,9 +379,14 @@ struct __attribute__((aligned(8))) RecPair8 {
 // a row are consecutive in memory except across the periodic seam, so one
 // 16-byte load fetches both (half the gather instructions); a parcel on the
 // seam (i0 = nx - 1, i1 = 0) loads the pair ending at i0 and record 0.
+// The wave forms the addresses and issues the loads at raised priority (the
+// step's callers raise it already before the locate), so its gathers are in
+// flight sooner while the other waves of the SIMD compute; it drops back
+// once they are issued.
 template <int F, typename R>
 __device__ __forceinline__ void load_cell(const StepArgs &a, const Loc<R> &L, Cell16<F> &c) {
   using T = typename Rec<F>::T;
+  __builtin_amdgcn_s_setprio(2);
   const T *base = reinterpret_cast<const T *>(a.met);
   const int nxy = a.nx * a.ny;
   const int r0 = L.k * nxy + L.j * a.nx;
@@ -409,6 +414,7 @@ __device__ __forceinline__ void load_cell(const StepArgs &a, const Loc<R> &L, Ce
         }
       }
   }
+  __builtin_amdgcn_s_setprio(0);
 }
 
 // R16 storage: the step kernels keep the per-level scales of the met time
@@ -551,6 +557,7 @@ __device__ __forceinline__ void advect(const StepArgs &a, const double *s_plev, 
   Cell16<F> c;
   R w0[3], w1[3];
   Loc<R> L;
+  __builtin_amdgcn_s_setprio(2);   // locate and gather at raised priority
   locate_xyz<R>(a, s_plev, s_idp, s_lut, lon, lat, p, L);
   locate_t<R>(a, t, L);
   load_cell<F, R>(a, L, c);
@@ -563,6 +570,7 @@ __device__ __forceinline__ void advect(const StepArgs &a, const double *s_plev, 
   const double latm = lat + (double)(hdt * d0lat);
   const double pm = p + (double)(hdt * w0[2]);
 
+  __builtin_amdgcn_s_setprio(2);   // locate and gather at raised priority
   locate_xyz<R>(a, s_plev, s_idp, s_lut, lonm, latm, pm, L);
   locate_t<R>(a, t + 0.5 * a.dt, L);
   load_cell<F, R>(a, L, c);
@@ -622,6 +630,7 @@ __device__ __forceinline__ void meso_sigma(const StepArgs &a, const double *s_pl
                                            double lon, double lat, double p, R sg[3]) {
   Cell16<F> c;
   Loc<R> L;
+  __builtin_amdgcn_s_setprio(2);   // locate and gather at raised priority
   locate_xyz<R>(a, s_plev, s_idp, s_lut, lon, lat, p, L);
   locate_t<R>(a, t_mid, L);
   load_cell<F, R>(a, L, c);
