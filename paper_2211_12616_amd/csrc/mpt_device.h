@@ -8,6 +8,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <type_traits>
 
 #include "mpt_math.h"
 
@@ -680,6 +681,25 @@ __device__ __forceinline__ R interp_temp(const StepArgs &a, const Loc<R> &L) {
   const T *base = reinterpret_cast<const T *>(a.met);
   const int nxy = a.nx * a.ny;
   const int r0 = L.k * nxy + L.j * a.nx;
+  using V = typename std::conditional<F == kF32, float, unsigned short>::type;
+  V raw[2][2][2][2];                  // [dl][dk][dj][di], all loads issued first
+  float sc[2][2];
+#pragma unroll
+  for (int dl = 0; dl < 2; ++dl) {
+    const int slot = dl ? L.l1 : L.l;
+#pragma unroll
+    for (int dk = 0; dk < 2; ++dk) {
+      sc[dl][dk] = F == kF32 ? 1.0f : a.t_scales[slot * a.nz + L.k + dk];
+#pragma unroll
+      for (int dj = 0; dj < 2; ++dj)
+#pragma unroll
+        for (int di = 0; di < 2; ++di) {
+          const T *rec = base + (int64_t)slot * a.level_elems + r0 + dk * nxy + dj * a.nx + (di ? L.i1 : L.i0);
+          raw[dl][dk][dj][di] = reinterpret_cast<const V *>(rec)[3];
+        }
+    }
+  }
+  __builtin_amdgcn_s_setprio(0);      // the callers raise it before the locate
   R cv[2][2][2];
 #pragma unroll
   for (int dk = 0; dk < 2; ++dk)
@@ -690,14 +710,8 @@ __device__ __forceinline__ R interp_temp(const StepArgs &a, const Loc<R> &L) {
         R v[2];
 #pragma unroll
         for (int dl = 0; dl < 2; ++dl) {
-          const int slot = dl ? L.l1 : L.l;
-          const T *rec = base + (int64_t)slot * a.level_elems + r0 + dk * nxy + dj * a.nx + (di ? L.i1 : L.i0);
-          if constexpr (F == kF32) {
-            v[dl] = (R)reinterpret_cast<const float *>(rec)[3];
-          } else {
-            const float sc = a.t_scales[slot * a.nz + L.k + dk];
-            v[dl] = (R)(dec<F>(reinterpret_cast<const unsigned short *>(rec)[3]) * sc);
-          }
+          if constexpr (F == kF32) v[dl] = (R)raw[dl][dk][dj][di];
+          else v[dl] = (R)(dec<F>(raw[dl][dk][dj][di]) * sc[dl][dk]);
         }
         cv[dk][dj][di] = lerp(v[0], v[1], L.ft);
       }
@@ -716,17 +730,24 @@ __device__ __forceinline__ R interp_temp(const StepArgs &a, const Loc<R> &L) {
 template <typename R>
 __device__ __forceinline__ void interp_sfc(const StepArgs &a, const Loc<R> &L, R out[3]) {
   const int64_t nxy = (int64_t)a.nx * a.ny;
-  R cv[2][2][3];
+  float4 r0[2][2], r1[2][2];          // all loads issued first
 #pragma unroll
   for (int dj = 0; dj < 2; ++dj)
 #pragma unroll
     for (int di = 0; di < 2; ++di) {
       const int64_t q = (int64_t)(L.j + dj) * a.nx + (di ? L.i1 : L.i0);
-      const float4 r0 = a.sfc[(int64_t)L.l * nxy + q];
-      const float4 r1 = a.sfc[(int64_t)L.l1 * nxy + q];
-      cv[dj][di][0] = lerp((R)r0.x, (R)r1.x, L.ft);
-      cv[dj][di][1] = lerp((R)r0.y, (R)r1.y, L.ft);
-      cv[dj][di][2] = lerp((R)r0.z, (R)r1.z, L.ft);
+      r0[dj][di] = a.sfc[(int64_t)L.l * nxy + q];
+      r1[dj][di] = a.sfc[(int64_t)L.l1 * nxy + q];
+    }
+  __builtin_amdgcn_s_setprio(0);      // the callers raise it before the locate
+  R cv[2][2][3];
+#pragma unroll
+  for (int dj = 0; dj < 2; ++dj)
+#pragma unroll
+    for (int di = 0; di < 2; ++di) {
+      cv[dj][di][0] = lerp((R)r0[dj][di].x, (R)r1[dj][di].x, L.ft);
+      cv[dj][di][1] = lerp((R)r0[dj][di].y, (R)r1[dj][di].y, L.ft);
+      cv[dj][di][2] = lerp((R)r0[dj][di].z, (R)r1[dj][di].z, L.ft);
     }
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
@@ -748,6 +769,7 @@ __device__ __forceinline__ void convection(const StepArgs &a, const double *s_pl
                                            uint32_t step, double t_mid, double lon, double lat,
                                            double &p) {
   Loc<R> L;
+  __builtin_amdgcn_s_setprio(2);   // locate and gather at raised priority
   locate_xyz<R>(a, s_plev, s_idp, s_lut, lon, lat, p, L);
   locate_t<R>(a, t_mid, L);
   R f[3];
@@ -771,6 +793,7 @@ __device__ __forceinline__ void sedimentation(const StepArgs &a, const double *s
                                               const double *s_idp, const uint16_t *s_lut,
                                               double t_mid, double lon, double lat, double &p) {
   Loc<R> L;
+  __builtin_amdgcn_s_setprio(2);   // locate and gather at raised priority
   locate_xyz<R>(a, s_plev, s_idp, s_lut, lon, lat, p, L);
   locate_t<R>(a, t_mid, L);
   const R T = interp_temp<F, R>(a, L);
