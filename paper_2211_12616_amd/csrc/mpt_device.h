@@ -464,11 +464,44 @@ __device__ __forceinline__ void cell_scales(const StepArgs &a, const Loc<R> &L, 
 // Quadrilinear interpolation, the time weight applied first at each of the
 // 8 corners, then along lon, lat and p.  Equal to interpolating in space at
 // both time levels and then in time (multilinear), up to rounding.
+// BF16 storage: the four corners of a (time level, level) slab share one
+// scale, so each slab is interpolated along lon and lat on the decoded
+// values and scaled once, then time and p follow (4 scale multiplies per
+// variable instead of 16; the same multilinear value up to rounding).  FP16
+// keeps the corner order: its decode and scale are one mixed-precision
+// multiply.
 template <int F, typename R>
 __device__ __forceinline__ void interp_cell(const StepArgs &a, const Cell16<F> &c, const Loc<R> &L,
                                             R out[3]) {
   float sc[2][2][3];
   cell_scales<F, R>(a, L, sc);
+  if constexpr (F == kBF16) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      R yk[2];
+#pragma unroll
+      for (int dk = 0; dk < 2; ++dk) {
+        R yt[2];
+#pragma unroll
+        for (int dl = 0; dl < 2; ++dl) {
+          R v[2][2];
+#pragma unroll
+          for (int dj = 0; dj < 2; ++dj)
+#pragma unroll
+            for (int di = 0; di < 2; ++di) {
+              const typename Rec<F>::T &r = c.r[dl][dk][dj][di];
+              v[dj][di] = (R)dec<F>(q == 0 ? r.x : q == 1 ? r.y : r.z);
+            }
+          const R x0 = lerp(v[0][0], v[0][1], L.fx);
+          const R x1 = lerp(v[1][0], v[1][1], L.fx);
+          yt[dl] = lerp(x0, x1, L.fy) * (R)sc[dl][dk][q];
+        }
+        yk[dk] = lerp(yt[0], yt[1], L.ft);
+      }
+      out[q] = lerp(yk[0], yk[1], L.fz);
+    }
+    return;
+  }
   R cv[2][2][2][3];   // [dk][dj][di][var], time-interpolated
 #pragma unroll
   for (int dk = 0; dk < 2; ++dk)
