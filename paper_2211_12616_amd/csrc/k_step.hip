@@ -112,12 +112,17 @@ template <int M, int F, typename R, bool P>
 __device__ __forceinline__ void step_body(const StepArgs &a) {
   __shared__ double s_plev[kMaxLevels];
   __shared__ double s_idp[kMaxLevels];
-  __shared__ uint16_t s_lut[kLutBins];
+  __shared__ __attribute__((aligned(16))) uint16_t s_lut[kLutBins];
   for (int q = threadIdx.x; q < a.nz; q += kBlock) {
     s_plev[q] = a.plev[q];
     s_idp[q] = (q < a.nz - 1) ? a.inv_dp[q] : 0.0;
   }
-  for (int q = threadIdx.x; q < kLutBins; q += kBlock) s_lut[q] = a.lut[q];
+  static_assert(kLutBins % 8 == 0, "the level table is copied in 16-byte units");
+  {                                   // 16 KB in 16-byte units (the table is 256-byte aligned)
+    const uint4 *src = reinterpret_cast<const uint4 *>(a.lut);
+    uint4 *dst = reinterpret_cast<uint4 *>(s_lut);
+    for (int q = threadIdx.x; q < kLutBins / 8; q += kBlock) dst[q] = src[q];
+  }
   const uint32_t step0 = a.step0 + (a.step_dev ? *a.step_dev : 0u);
   if constexpr (F != kF32) stage_scale_window(a, met_level(a, a.t_start + (double)step0 * a.dt));
   __syncthreads();
