@@ -35,7 +35,7 @@ FP32_PEAK_TFLOPS = 157.3
 # arithmetic as BF16 (decode, scale, interpolate).  HBM bytes per 10-step
 # launch of 1e8 parcels = 2 x FETCH_SIZE + WRITE_SIZE (KiB x 1024; a 1 GiB
 # copy reads FETCH_SIZE = 512 MiB and WRITE_SIZE = 1 GiB).
-FLOP_PER_PS = {"f64": 1154.0, "f32": 669.0, "bf16": 741.0, "f16": 813.0}
+FLOP_PER_PS = {"f64": 1154.0, "f32": 669.0, "bf16": 741.0, "f16": 741.0}
 TRAFFIC_BYTES_PER_LAUNCH = {"f64": (2 * 3.703e6 + 5.975e6) * 1024,
                             "f32": (2 * 3.110e6 + 4.803e6) * 1024,
                             "bf16": (2 * 2.561e6 + 4.804e6) * 1024,

@@ -464,18 +464,16 @@ __device__ __forceinline__ void cell_scales(const StepArgs &a, const Loc<R> &L, 
 // Quadrilinear interpolation, the time weight applied first at each of the
 // 8 corners, then along lon, lat and p.  Equal to interpolating in space at
 // both time levels and then in time (multilinear), up to rounding.
-// BF16 storage: the four corners of a (time level, level) slab share one
+// R16 storage: the four corners of a (time level, level) slab share one
 // scale, so each slab is interpolated along lon and lat on the decoded
 // values and scaled once, then time and p follow (4 scale multiplies per
-// variable instead of 16; the same multilinear value up to rounding).  FP16
-// keeps the corner order: its decode and scale are one mixed-precision
-// multiply.
+// variable instead of 16; the same multilinear value up to rounding).
 template <int F, typename R>
 __device__ __forceinline__ void interp_cell(const StepArgs &a, const Cell16<F> &c, const Loc<R> &L,
                                             R out[3]) {
   float sc[2][2][3];
   cell_scales<F, R>(a, L, sc);
-  if constexpr (F == kBF16) {
+  if constexpr (F != kF32) {
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
       R yk[2];
