@@ -46,7 +46,7 @@ TRAFFIC_BYTES_PER_LAUNCH = {"f64": (2 * 3.703e6 + 5.975e6) * 1024,
 # alone and with both modules.
 FLOP_PER_PS_PHYS = {"f64_sedi": 1375.0, "f64_phys": 1436.0}
 TRAFFIC_BYTES_PER_LAUNCH_PHYS = {"f64_sedi": (2 * 3.679e6 + 4.688e6) * 1024,
-                                 "f64_phys": (2 * 1.616e7 + 4.688e6) * 1024}
+                                 "f64_phys": (2 * 1.677e7 + 4.688e6) * 1024}
 METRIC = "particle-steps/s (advect+diffuse, 1e8 particles, 0.3° grid); surrogate vs plain"
 FORMS = {"f64": (0, 0), "f32": (1, 0), "bf16": (1, 1), "f16": (1, 2)}   # (math, dtype)
 
