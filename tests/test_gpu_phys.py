@@ -166,3 +166,15 @@ def test_phys_streamed_equals_all_resident(mpt):
                                     for x in (met.temp, met.cape, met.pel, met.ps)))
     torch.cuda.synchronize()
     assert_bitwise(by_id(A.to_host()), by_id(B.to_host()))
+
+
+def test_phys_r16_launches_across_met_levels(mpt, met3):
+    """16-bit storage with convection and sedimentation: launches that cross
+    a met level (fuse 7 from step 5: steps 117..123 cross the level at step
+    120) read the scales of three levels from LDS and equal one-step
+    launches bit for bit."""
+    say("[phys] BF16 launches across met levels")
+    part = inputs.make_particles(3000, 49, p_lo=100.0, p_hi=990.0)
+    kw = dict(math=1, dtype=encode.BF16, flags=ALL, sedi_radius=R_BIG, **KW)
+    base = gpu_run(met3, part, 5, 235, fuse=1, **kw)
+    assert_bitwise(base, gpu_run(met3, part, 5, 235, fuse=7, **kw))
