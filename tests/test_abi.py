@@ -200,7 +200,7 @@ def test_surrogate_constants_match_header():
         assert m and int(m.group(1)) == val, name
     # the flat parameter layout: per layer W[in][out] + bias with padded shapes
     from oracle import mlp
-    assert sum(fi * fo + fo for fi, fo in mlp.SHAPES) == mpt.SURR_NPARAM
+    assert sum(fi * fo + fo for fi, fo in mlp.FLAT_SHAPES) == mpt.SURR_NPARAM
 
 
 def test_workspace_includes_surrogate_scratch():

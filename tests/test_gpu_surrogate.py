@@ -1,7 +1,8 @@
 """GPU tests of the learned k-step surrogate (a project addition: the paper
 has no counterpart).  Pins: training inputs and targets against the oracle's
 stencil and its plain 8-step advection; the MLP forward against a numpy
-float32 forward on the same bf16 weights; the gradient against CPU autograd;
+float32 forward on the same bf16 weights; the gradient element by element
+against a numpy backward with the GPU's bf16 roundings;
 training lowers the loss; with tau = 0 every parcel-block falls back to the
 plain scheme, which must then equal the plain F32 step bit for bit.  The
 accepted-surrogate trajectory itself is parity unpinned (it is judged by
@@ -82,8 +83,12 @@ def test_forward_matches_numpy(mpt, ctx):
     assert err.max() <= 1e-2
 
 
-def test_gradient_matches_autograd(mpt, ctx):
-    import torch
+def test_gradient_matches_bf16_reference(mpt, ctx):
+    """The GPU gradient against the numpy backward that rounds the output
+    and hidden gradients to bf16 where the GPU does (oracle/mlp.py, pinned
+    against CPU autograd), element by element for every weight matrix and
+    bias vector, each against its own scale; the padding of the flat array
+    gets exactly zero."""
     lon, lat, p, step = starts(1024, 3)
     x, y = ctx.surrogate_datagen(*to_dev(lon, lat, p, step))
     norm = ctx.surrogate_stats(x, y)
@@ -91,26 +96,23 @@ def test_gradient_matches_autograd(mpt, ctx):
     grad, loss = ctx.surrogate_grad(x, y, norm, params)
     g = grad.cpu().numpy()
     P = params.cpu().numpy()
-    nrm = norm.cpu().numpy()
-    xn = torch.from_numpy(mlp.normalize_inputs(x.cpu().numpy(), nrm))
-    tn = torch.from_numpy(((y.cpu().numpy() - nrm[6:9]) / nrm[9:12]).astype(np.float32))
-    pt = torch.from_numpy(mlp.bf16(P)).requires_grad_(True)
-    h, off = xn, 0
-    for li, (fi, fo) in enumerate(mlp.SHAPES):
-        w = pt[off:off + fi * fo].reshape(fi, fo)
-        off += fi * fo
-        b = pt[off:off + fo]
-        off += fo
-        z = h @ w + b
-        h = torch.relu(z) if li < 3 else z
-    L = ((h[:, :3] - tn) ** 2).mean()
-    L.backward()
-    ga = pt.grad.numpy()
-    cos = float(g @ ga / (np.linalg.norm(g) * np.linalg.norm(ga)))
-    rel = float(np.linalg.norm(g - ga) / np.linalg.norm(ga))
-    say(f"[grad] loss gpu {loss.item():.5f} autograd {L.item():.5f}; cosine {cos:.5f}, rel diff {rel:.3e}")
-    assert abs(loss.item() - L.item()) <= 2e-2 * L.item()
-    assert cos >= 0.995 and rel <= 0.08
+    lref, gref = mlp.grad(P, x.cpu().numpy(), y.cpu().numpy(), norm.cpu().numpy(), round_bf16=True)
+    say(f"[grad] loss gpu {loss.item():.6f} reference {lref:.6f}")
+    assert abs(loss.item() - lref) <= 1e-3 * lref
+    pad = np.ones(g.size, bool)
+    for li, ((ow, ob), (fi, fo), (pi, po)) in enumerate(zip(mlp.flat_offsets(), mlp.SHAPES, mlp.FLAT_SHAPES)):
+        gw = g[ow:ow + pi * po].reshape(pi, po)[:fi, :fo]
+        gb = g[ob:ob + fo]
+        pad[ow:ow + pi * po].reshape(pi, po)[:fi, :fo] = False
+        pad[ob:ob + fo] = False
+        for name, mine, ref in (("W", gw, gref[li][0]), ("b", gb, gref[li][1])):
+            scale = np.abs(ref).max()
+            err = np.abs(mine - ref).max() / scale
+            rel = np.linalg.norm(mine - ref) / np.linalg.norm(ref)
+            say(f"[grad] layer {li + 1} {name}{ref.shape}: max |gpu - ref| / max |ref| = {err:.2e}, "
+                f"relative norm {rel:.2e}")
+            assert err <= 5e-3 and rel <= 5e-3, (li, name)
+    assert np.all(g[pad] == 0.0)
 
 
 def test_training_lowers_loss(mpt, ctx):
