@@ -245,6 +245,23 @@ mpt_status mpt_diffuse(mpt_ctx *ctx, const mpt_particles *particles, uint32_t st
  * step 0; mpt_step sorts before the step it is about to run.) */
 mpt_status mpt_sort_particles(mpt_ctx *ctx, mpt_particles *particles, void *hip_stream);
 
+/* For callers that cannot allocate device memory at the call (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid it): the
+ * same sort as mpt_sort_particles, with its scratch (keys and ranks per
+ * parcel, histogram, counters, scan sums) in a fixed array of the library
+ * that each device holds from the first mpt_create on it until the process
+ * ends (about 40 MiB), instead of the context's workspace.  Allocates
+ * nothing.  Limits: n <= MPT_NOALLOC_SORT_MAX_N (else MPT_ERR_WORKSPACE; n
+ * may exceed the context's n_max) and a grid of at most
+ * MPT_NOALLOC_SORT_MAX_KEYS - 65537 tiles (else MPT_ERR_UNSUPPORTED).  The
+ * context's device must be current (else MPT_ERR_STATE).  Always runs its
+ * own key pass (sort keys a step left are not used, and are dropped).
+ * Every call on one device shares that array: calls that overlap on one
+ * device (other streams, other contexts, other threads) race and give
+ * wrong results; order them on one stream or synchronize between them. */
+enum { MPT_NOALLOC_SORT_MAX_N = 1 << 22, MPT_NOALLOC_SORT_MAX_KEYS = 1 << 20 };
+mpt_status mpt_sort_particles_noalloc(mpt_ctx *ctx, mpt_particles *particles, void *hip_stream);
+
 /* nsteps time steps step0 .. step0+nsteps-1 (advection, turbulent and
  * mesoscale diffusion per params.flags; the time loop of Sec. 4.3), sorting
  * before every step that is a multiple of params.sort_interval (then the

@@ -3,6 +3,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 
 #include "../../include/mpt.h"
@@ -32,6 +33,7 @@ struct mpt_ctx {
   int32_t *rel_sorted;    // [kMaxScen] release steps in ascending order
   uint32_t *step_dev;     // step index read by graph-replayed kernels
   uint32_t *keys, *ranks, *hist, *spread, *block_sums;
+  unsigned char *static_scratch;  // this device's copy of the allocation-free sort's scratch
   SortKeyArgs *sk;        // the same buffers for step launches that leave sort keys
   uint32_t ntx, nty, ntz, ntiles, nkeys;
   // host state
@@ -80,6 +82,42 @@ namespace {
 constexpr int kMaxScen = 65536;
 constexpr int kMaxTimeLevels = 64;
 constexpr int kPersistentBlocks = 2048;   // 256 CUs x 8 blocks
+
+// Scratch of the allocation-free sort (mpt_sort_particles_noalloc): keys
+// and ranks of up to MPT_NOALLOC_SORT_MAX_N parcels, the histogram, its
+// spread counters and the scan's chunk sums for up to
+// MPT_NOALLOC_SORT_MAX_KEYS keys.  One copy per device, held until the
+// process ends; host code reaches it only through the address that
+// hipGetSymbolAddress returns for the current device.
+constexpr size_t kNaKeys = 0;
+constexpr size_t kNaRanks = kNaKeys + sizeof(uint32_t) * (size_t)MPT_NOALLOC_SORT_MAX_N;
+constexpr size_t kNaHist = kNaRanks + sizeof(uint32_t) * (size_t)MPT_NOALLOC_SORT_MAX_N;
+constexpr size_t kNaSpread = kNaHist + sizeof(uint32_t) * (size_t)MPT_NOALLOC_SORT_MAX_KEYS;
+constexpr size_t kNaSums = kNaSpread + sizeof(uint32_t) * (size_t)MPT_NOALLOC_SORT_MAX_KEYS;
+constexpr size_t kNaBytes = kNaSums + sizeof(uint32_t) * ((size_t)MPT_NOALLOC_SORT_MAX_KEYS / 1024 + 1);
+static_assert(MPT_NOALLOC_SORT_MAX_KEYS % 16 == 0, "the spread counters fill 16 rows");
+
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[kMaxDevices];   // per device, set by the first mpt_create on it
+
+// The device address of `scratch` on device dev (current); null when the
+// lookup fails.
+unsigned char *scratch_address(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) {
+      (void)hipGetLastError();          // leave no sticky error for the caller's next call
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = static_cast<unsigned char *>(ptr);
+  }
+  return g_scratch_ptr[dev];
+}
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -281,7 +319,8 @@ void fill_step_args(const mpt_ctx *c, const mpt_particles *P, uint32_t step0, in
   a.sedi_rho = q.sedi_density;
 }
 
-mpt_status check_particles(const mpt_ctx *c, const mpt_particles *P, bool need_pingpong) {
+mpt_status check_particles(const mpt_ctx *c, const mpt_particles *P, bool need_pingpong,
+                           bool need_n_max = true) {
   if (!P) return MPT_ERR_ARG;
   if (P->n < 0) return MPT_ERR_ARG;
   if (P->n > ((int64_t)1 << 31) * kBlock / 2) return MPT_ERR_UNSUPPORTED;
@@ -300,7 +339,7 @@ mpt_status check_particles(const mpt_ctx *c, const mpt_particles *P, bool need_p
     if (c->nscen <= 0) return MPT_ERR_STATE;
   }
   if (need_pingpong) {
-    if (P->n > c->n_max) return MPT_ERR_WORKSPACE;
+    if (need_n_max && P->n > c->n_max) return MPT_ERR_WORKSPACE;
     if (!P->lon2 || !P->lat2 || !P->p2 || !P->id2 || !P->up2 || !P->vp2 || !P->wp2)
       return MPT_ERR_ARG;
     if (!aligned(P->lon2, 8) || !aligned(P->lat2, 8) || !aligned(P->p2, 8) || !aligned(P->id2, 4) ||
@@ -333,8 +372,15 @@ mpt_status check_time(const mpt_ctx *c, uint32_t step0, int64_t nsteps) {
 // Sort before step `step` (added to the device step index when dev_step).
 // keys_done: the launch before it left the keys of the parcels' current
 // positions (and their counts) in the context's sort buffers.
+// Scratch of one sort: keys and ranks per parcel, histogram in key order,
+// its spread counters, scan chunk sums.
+struct SortBufs {
+  uint32_t *keys, *ranks, *hist, *spread, *block_sums;
+};
+
 mpt_status do_sort(mpt_ctx *c, mpt_particles *P, uint32_t step, bool dev_step, hipStream_t s,
-                   bool keys_done = false) {
+                   bool keys_done = false, const SortBufs *bufs = nullptr) {
+  const SortBufs b = bufs ? *bufs : SortBufs{c->keys, c->ranks, c->hist, c->spread, c->block_sums};
   const mpt_grid &g = c->grid;
   SortArgs sa;
   sa.lon = P->lon; sa.lat = P->lat; sa.p = P->p;
@@ -352,13 +398,13 @@ mpt_status do_sort(mpt_ctx *c, mpt_particles *P, uint32_t step, bool dev_step, h
   sa.rank = c->rank;
   sa.step = step;
   sa.step_dev = dev_step ? c->step_dev : nullptr;
-  sa.keys = c->keys; sa.ranks = c->ranks; sa.hist = c->hist; sa.block_sums = c->block_sums;
-  sa.spread = c->spread; sa.spread_s = (c->nkeys + 15) / 16;
+  sa.keys = b.keys; sa.ranks = b.ranks; sa.hist = b.hist; sa.block_sums = b.block_sums;
+  sa.spread = b.spread; sa.spread_s = (c->nkeys + 15) / 16;
   const int64_t nblk = (P->n + kBlock * kSortPer - 1) / (kBlock * kSortPer);
   sa.nblk = (int)nblk;
   sa.per_xcd = (int)((nblk + kXcds - 1) / kXcds);
   ScatterArgs xa;
-  xa.n = P->n; xa.keys = c->keys; xa.ranks = c->ranks; xa.offsets = c->hist;
+  xa.n = P->n; xa.keys = b.keys; xa.ranks = b.ranks; xa.offsets = b.hist;
   xa.lon = P->lon; xa.lat = P->lat; xa.p = P->p; xa.id = P->id;
   xa.up = P->up; xa.vp = P->vp; xa.wp = P->wp; xa.scen = P->scen;
   xa.lon2 = P->lon2; xa.lat2 = P->lat2; xa.p2 = P->p2; xa.id2 = P->id2;
@@ -544,6 +590,7 @@ mpt_status mpt_create(const mpt_grid *grid, const mpt_params *params, int64_t n_
   c->hist = reinterpret_cast<uint32_t *>(ws + L.hist);
   c->spread = reinterpret_cast<uint32_t *>(ws + L.spread);
   c->block_sums = reinterpret_cast<uint32_t *>(ws + L.block_sums);
+  c->static_scratch = scratch_address(dev);
   c->out_pe = reinterpret_cast<double *>(ws + L.out_pe);
   c->hyb_ab = reinterpret_cast<double *>(ws + L.hyb_ab);
   c->ntx = L.ntx; c->nty = L.nty; c->ntz = L.ntz; c->ntiles = L.ntiles; c->nkeys = L.nkeys;
@@ -780,6 +827,24 @@ mpt_status mpt_sort_particles(mpt_ctx *c, mpt_particles *P, void *hip_stream) {
   const bool keys_done = c->keyed && !P->scen && c->keyed_lon == P->lon && c->keyed_n == P->n;
   c->keyed = false;
   return do_sort(c, P, 0u, false, static_cast<hipStream_t>(hip_stream), keys_done);
+}
+
+mpt_status mpt_sort_particles_noalloc(mpt_ctx *c, mpt_particles *P, void *hip_stream) {
+  if (!c) return MPT_ERR_ARG;
+  if (P && P->n > MPT_NOALLOC_SORT_MAX_N) return MPT_ERR_WORKSPACE;
+  if (c->nkeys > (uint32_t)MPT_NOALLOC_SORT_MAX_KEYS) return MPT_ERR_UNSUPPORTED;
+  const mpt_status st = check_particles(c, P, true, /*need_n_max=*/false);
+  if (st != MPT_OK) return st;
+  if (P->n == 0) return MPT_OK;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || !c->static_scratch) return MPT_ERR_HIP;
+  if (dev != c->device) return MPT_ERR_STATE;     // the scratch address is the context's device's
+  c->keyed = false;                    // the keys a step left are not used here
+  unsigned char *base = c->static_scratch;
+  const SortBufs b{reinterpret_cast<uint32_t *>(base + kNaKeys), reinterpret_cast<uint32_t *>(base + kNaRanks),
+                   reinterpret_cast<uint32_t *>(base + kNaHist), reinterpret_cast<uint32_t *>(base + kNaSpread),
+                   reinterpret_cast<uint32_t *>(base + kNaSums)};
+  return do_sort(c, P, 0u, false, static_cast<hipStream_t>(hip_stream), false, &b);
 }
 
 mpt_status mpt_step(mpt_ctx *c, mpt_particles *P, uint32_t step0, int32_t nsteps, void *hip_stream) {
