@@ -109,6 +109,74 @@ __global__ __launch_bounds__(256) void k_pack_sfc(const float *__restrict__ cape
     dst[q] = make_float4(cape[q], pel[q], ps[q], 0.0f);
 }
 
+// Spread table of one pair of time levels (ring slots s0 < earlier, s1):
+// for every cell (k, j, i) with j < ny - 1 and k < nz - 1 the population
+// standard deviation of each variable over the cell's 16 stored values (8
+// corners x 2 levels; R16 decoded with the per-level scales), in FP64, two
+// passes (mean, then squared deviations).  Cells of the last row and level
+// are never read and get 0.  Stored {su, sv, sw, 0} as double (D) or float.
+template <int F, bool D>
+__global__ __launch_bounds__(256) void k_cell_sigma(const void *__restrict__ met, const float *__restrict__ scales,
+                                                    int s0, int s1, int64_t level_elems, int nx, int ny, int nz,
+                                                    void *__restrict__ out) {
+  using T = typename Rec<F>::T;
+  const int npts = nx * ny * nz;                     // < 2^31
+  const int stride = (int)(gridDim.x * blockDim.x);
+  for (int q = (int)(blockIdx.x * blockDim.x + threadIdx.x); q < npts; q += stride) {
+    const int i = q % nx, r = q / nx;
+    const int j = r % ny, k = r / ny;
+    double sg[3] = {0.0, 0.0, 0.0};
+    if (j < ny - 1 && k < nz - 1) {
+      const int i1 = i + 1 == nx ? 0 : i + 1;
+      double x[3][16];
+      int n = 0;
+#pragma unroll
+      for (int dl = 0; dl < 2; ++dl) {
+        const int slot = dl ? s1 : s0;
+        const T *lev = reinterpret_cast<const T *>(met) + (size_t)slot * (size_t)level_elems;
+#pragma unroll
+        for (int dk = 0; dk < 2; ++dk)
+#pragma unroll
+          for (int dj = 0; dj < 2; ++dj)
+#pragma unroll
+            for (int di = 0; di < 2; ++di) {
+              const T v = lev[((k + dk) * ny + j + dj) * nx + (di ? i1 : i)];
+              if constexpr (F == kF32) {
+                x[0][n] = (double)v.x;
+                x[1][n] = (double)v.y;
+                x[2][n] = (double)v.z;
+              } else {
+                const float *sc = scales + (size_t)slot * 3 * nz + (k + dk);
+                x[0][n] = (double)(dec<F>(v.x) * sc[0]);
+                x[1][n] = (double)(dec<F>(v.y) * sc[nz]);
+                x[2][n] = (double)(dec<F>(v.z) * sc[2 * nz]);
+              }
+              ++n;
+            }
+      }
+#pragma unroll
+      for (int var = 0; var < 3; ++var) {
+        double mean = 0.0;
+#pragma unroll
+        for (int m = 0; m < 16; ++m) mean += x[var][m];
+        mean /= 16.0;
+        double ss = 0.0;
+#pragma unroll
+        for (int m = 0; m < 16; ++m) ss += (x[var][m] - mean) * (x[var][m] - mean);
+        ss /= 16.0;
+        sg[var] = sqrt(ss > 0.0 ? ss : 0.0);
+      }
+    }
+    if constexpr (D) {
+      double2 *o = static_cast<double2 *>(out) + 2 * (size_t)q;
+      o[0] = make_double2(sg[0], sg[1]);
+      o[1] = make_double2(sg[2], 0.0);
+    } else {
+      static_cast<float4 *>(out)[q] = make_float4((float)sg[0], (float)sg[1], (float)sg[2], 0.0f);
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void k_fill_f32(float *dst, float value, int64_t n) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) dst[q] = value;
@@ -168,6 +236,20 @@ hipError_t launch_pack_temp(int field, const float *T, float *t_scales, void *ds
 hipError_t launch_pack_sfc(const float *cape, const float *pel, const float *ps, float4 *dst, int64_t nxy,
                            hipStream_t stream) {
   hipLaunchKernelGGL(k_pack_sfc, dim3(grid_for(nxy)), dim3(256), 0, stream, cape, pel, ps, dst, nxy);
+  return hipGetLastError();
+}
+
+hipError_t launch_cell_sigma(int field, bool f64, const void *met, const float *scales, int s0, int s1,
+                             int64_t level_elems, int nx, int ny, int nz, void *out, hipStream_t stream) {
+  const dim3 g(grid_for(level_elems)), b(256);
+  if (field == kF32) {
+    if (f64) hipLaunchKernelGGL((k_cell_sigma<kF32, true>), g, b, 0, stream, met, scales, s0, s1, level_elems, nx, ny, nz, out);
+    else hipLaunchKernelGGL((k_cell_sigma<kF32, false>), g, b, 0, stream, met, scales, s0, s1, level_elems, nx, ny, nz, out);
+  } else if (field == kBF16) {
+    hipLaunchKernelGGL((k_cell_sigma<kBF16, false>), g, b, 0, stream, met, scales, s0, s1, level_elems, nx, ny, nz, out);
+  } else {
+    hipLaunchKernelGGL((k_cell_sigma<kF16, false>), g, b, 0, stream, met, scales, s0, s1, level_elems, nx, ny, nz, out);
+  }
   return hipGetLastError();
 }
 

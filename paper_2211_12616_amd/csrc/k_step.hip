@@ -12,49 +12,59 @@
 // own (k_step_phys_*), so the plain kernels keep their code and registers.
 #include "mpt_device.h"
 #include "mpt_internal.h"
+#include "mpt_stage.h"
 
 namespace mpt {
 
-// Advances parcel i; lon, lat, p receive its final position.
+// Advances parcel i (valid: the thread holds a parcel); lon, lat, p receive
+// its final position.  Every thread of the block calls it and runs the same
+// steps: the advection's winds are staged for the whole block
+// (mpt_stage.h), with barriers inside.
 template <int F, typename R, bool P>
-__device__ __forceinline__ void step_parcel(const StepArgs &a, const double *s_plev,
-                                            const double *s_idp, const uint16_t *s_lut, int64_t i,
-                                            uint32_t step0, double &lon, double &lat, double &p) {
-  lon = a.lon[i];
-  lat = a.lat[i];
-  p = a.p[i];
-  if (!finite3(lon, lat, p)) return;
-  const uint32_t id = a.id[i];
+__device__ __forceinline__ void step_parcel(const StepArgs &a, const StepLds<R> &sm, const uint16_t *s_lut,
+                                            int64_t i, bool valid, uint32_t step0, double &lon, double &lat,
+                                            double &p) {
+  lon = lat = p = 0.0;
+  bool live = false;
+  uint32_t id = 0;
   int64_t rel = INT64_MIN;
-  if (a.scen) rel = a.release[a.scen[i]];
   const bool do_meso = (a.flags & kMeso) != 0;
   R up = 0, vp = 0, wp = 0;
-  if (do_meso) {
-    up = static_cast<const R *>(a.up)[i];
-    vp = static_cast<const R *>(a.vp)[i];
-    wp = static_cast<const R *>(a.wp)[i];
+  if (valid) {
+    lon = a.lon[i];
+    lat = a.lat[i];
+    p = a.p[i];
+    live = finite3(lon, lat, p);
+    if (live) {
+      id = a.id[i];
+      if (a.scen) rel = a.release[a.scen[i]];
+      if (do_meso) {
+        up = static_cast<const R *>(a.up)[i];
+        vp = static_cast<const R *>(a.vp)[i];
+        wp = static_cast<const R *>(a.wp)[i];
+      }
+    }
   }
   bool moved = false;
   for (int s = 0; s < a.nsteps; ++s) {
     const uint32_t step = step0 + (uint32_t)s;
-    if ((int64_t)step < rel) continue;
-    if (!finite3(lon, lat, p)) break;
-    moved = true;
+    const bool act = live && (int64_t)step >= rel && finite3(lon, lat, p);
+    moved = moved || act;
     const double t = a.t_start + (double)step * a.dt;
     if (a.flags & kAdvect) {
-      advect<F, R>(a, s_plev, s_idp, s_lut, t, lon, lat, p);
-      position(a, lon, lat, p);
+      advect_block<F, R>(a, sm, s_lut, act, t, lon, lat, p);
+      if (act) position(a, lon, lat, p);
     }
-    if (a.flags & (kTurb | kMeso)) {
+    if (act && (a.flags & (kTurb | kMeso))) {
       if (a.flags & kTurb) turb<R>(a, id, step, lon, lat, p);
-      if (do_meso) meso<F, R>(a, s_plev, s_idp, s_lut, id, step, t + 0.5 * a.dt, lon, lat, p, up, vp, wp);
+      if (do_meso) meso<F, R>(a, sm.plev, sm.idp, s_lut, id, step, t + 0.5 * a.dt, lon, lat, p, up, vp, wp);
       position(a, lon, lat, p);
     }
     if constexpr (P) {
-      if (a.flags & (kConv | kSedi)) {
+      if (act && (a.flags & (kConv | kSedi))) {
         const double t_mid = t + 0.5 * a.dt;
-        if (a.flags & kConv) convection<F, R>(a, s_plev, s_idp, s_lut, id, step, t_mid, lon, lat, p);
-        if (a.flags & kSedi) sedimentation<F, R>(a, s_plev, s_idp, s_lut, t_mid, lon, lat, p);
+        if (a.flags & kConv) convection<F, R>(a, sm.plev, sm.idp, s_lut, id, step, t_mid, lon, lat, p);
+        if (a.flags & kSedi) sedimentation<F, R>(a, sm.plev, sm.idp, s_lut, t_mid, lon, lat, p);
         position(a, lon, lat, p);
       }
     }
@@ -110,15 +120,14 @@ __device__ __forceinline__ void leave_sort_key(const StepArgs &a, const double *
 
 template <int M, int F, typename R, bool P>
 __device__ __forceinline__ void step_body(const StepArgs &a) {
-  __shared__ double s_plev[kMaxLevels];
-  __shared__ double s_idp[kMaxLevels];
   __shared__ __attribute__((aligned(16))) uint16_t s_lut[kLutBins];
+  const StepLds<R> sm = step_lds<R>(a.nz, F != kF32);
   for (int q = threadIdx.x; q < a.nz; q += kBlock) {
-    s_plev[q] = a.plev[q];
-    s_idp[q] = (q < a.nz - 1) ? a.inv_dp[q] : 0.0;
+    sm.plev[q] = a.plev[q];
+    sm.idp[q] = (q < a.nz - 1) ? a.inv_dp[q] : 0.0;
   }
   static_assert(kLutBins % 8 == 0, "the level table is copied in 16-byte units");
-  {                                   // 16 KB in 16-byte units (the table is 256-byte aligned)
+  {                                   // 8 KB in 16-byte units (the table is 256-byte aligned)
     const uint4 *src = reinterpret_cast<const uint4 *>(a.lut);
     uint4 *dst = reinterpret_cast<uint4 *>(s_lut);
     for (int q = threadIdx.x; q < kLutBins / 8; q += kBlock) dst[q] = src[q];
@@ -135,22 +144,22 @@ __device__ __forceinline__ void step_body(const StepArgs &a) {
     const int xcd = (int)blockIdx.x % kXcds;
     const int q = (int)blockIdx.x / kXcds, nq = (int)gridDim.x / kXcds;
     const int64_t c_lo = nchunks * xcd / kXcds, c_hi = nchunks * (xcd + 1) / kXcds;
-    for (int64_t c = c_lo + q; c < c_hi; c += nq) {
+    for (int64_t c = c_lo + q; c < c_hi; c += nq) {   // uniform over the block
       const int64_t j = c * kBlock + threadIdx.x;
-      double lon = 0.0, lat = 0.0, p = 0.0;
+      double lon, lat, p;
       const bool valid = j < cnt;
       const int64_t i = valid ? (int64_t)a.index[j] : 0;
-      if (valid) step_parcel<F, R, P>(a, s_plev, s_idp, s_lut, i, step0, lon, lat, p);
-      if (a.sk) leave_sort_key(a, s_plev, s_lut, i, valid, lon, lat, p);   // uniform
+      step_parcel<F, R, P>(a, sm, s_lut, i, valid, step0, lon, lat, p);
+      if (a.sk) leave_sort_key(a, sm.plev, s_lut, i, valid, lon, lat, p);   // uniform
     }
   } else if constexpr (M == kModeBlock) {
     const int lb = logical_block((int)blockIdx.x, a.per_xcd);
     if (lb >= a.nblk) return;
     const int64_t i = (int64_t)lb * kBlock + threadIdx.x;
-    double lon = 0.0, lat = 0.0, p = 0.0;
+    double lon, lat, p;
     const bool valid = i < a.n;
-    if (valid) step_parcel<F, R, P>(a, s_plev, s_idp, s_lut, i, step0, lon, lat, p);
-    if (a.sk) leave_sort_key(a, s_plev, s_lut, i, valid, lon, lat, p);     // uniform
+    step_parcel<F, R, P>(a, sm, s_lut, i, valid, step0, lon, lat, p);
+    if (a.sk) leave_sort_key(a, sm.plev, s_lut, i, valid, lon, lat, p);     // uniform
   } else {
     // persistent: XCD x owns an even share of the chunks of the prefix and
     // its blocks stride through that share
@@ -159,10 +168,10 @@ __device__ __forceinline__ void step_body(const StepArgs &a) {
     const int xcd = (int)blockIdx.x % kXcds;
     const int q = (int)blockIdx.x / kXcds, nq = (int)gridDim.x / kXcds;
     const int64_t c_lo = nchunks * xcd / kXcds, c_hi = nchunks * (xcd + 1) / kXcds;
-    for (int64_t c = c_lo + q; c < c_hi; c += nq) {
+    for (int64_t c = c_lo + q; c < c_hi; c += nq) {   // uniform over the block
       const int64_t i = c * kBlock + threadIdx.x;
       double lon, lat, p;
-      if (i < bound) step_parcel<F, R, P>(a, s_plev, s_idp, s_lut, i, step0, lon, lat, p);
+      step_parcel<F, R, P>(a, sm, s_lut, i, i < bound, step0, lon, lat, p);
     }
   }
 }
@@ -191,9 +200,10 @@ void k_step_phys_f32(const StepArgs a) {
   step_body<M, F, float, true>(a);
 }
 
-// Dynamic LDS of the R16 kernels: the scale window.
-static size_t scale_window_bytes(const StepArgs &a) {
-  return (size_t)kScaleWin * 3 * (size_t)a.nz * sizeof(float);
+// Dynamic LDS of the step kernels (mpt_stage.h).
+template <typename R>
+static size_t lds_bytes(int field, const StepArgs &a) {
+  return step_lds_bytes<R>(a.nz, field != kF32);
 }
 
 template <int M>
@@ -202,13 +212,13 @@ static hipError_t launch_mode(int field, int math_f64, const StepArgs &args, dim
   const dim3 block(kBlock);
   if (math_f64) {
     if (field != kF32) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_step_f64<M>, grid, block, 0, stream, args);
+    hipLaunchKernelGGL(k_step_f64<M>, grid, block, lds_bytes<double>(field, args), stream, args);
   } else if (field == kF32) {
-    hipLaunchKernelGGL((k_step_f32<M, kF32>), grid, block, 0, stream, args);
+    hipLaunchKernelGGL((k_step_f32<M, kF32>), grid, block, lds_bytes<float>(field, args), stream, args);
   } else if (field == kBF16) {
-    hipLaunchKernelGGL((k_step_f32<M, kBF16>), grid, block, scale_window_bytes(args), stream, args);
+    hipLaunchKernelGGL((k_step_f32<M, kBF16>), grid, block, lds_bytes<float>(field, args), stream, args);
   } else {
-    hipLaunchKernelGGL((k_step_f32<M, kF16>), grid, block, scale_window_bytes(args), stream, args);
+    hipLaunchKernelGGL((k_step_f32<M, kF16>), grid, block, lds_bytes<float>(field, args), stream, args);
   }
   return hipGetLastError();
 }
@@ -220,13 +230,13 @@ static hipError_t launch_phys(int field, int math_f64, const StepArgs &args, dim
   const dim3 block(kBlock);
   if (math_f64) {
     if (field != kF32) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_step_phys_f64<M>, grid, block, 0, stream, args);
+    hipLaunchKernelGGL(k_step_phys_f64<M>, grid, block, lds_bytes<double>(field, args), stream, args);
   } else if (field == kF32) {
-    hipLaunchKernelGGL((k_step_phys_f32<M, kF32>), grid, block, 0, stream, args);
+    hipLaunchKernelGGL((k_step_phys_f32<M, kF32>), grid, block, lds_bytes<float>(field, args), stream, args);
   } else if (field == kBF16) {
-    hipLaunchKernelGGL((k_step_phys_f32<M, kBF16>), grid, block, scale_window_bytes(args), stream, args);
+    hipLaunchKernelGGL((k_step_phys_f32<M, kBF16>), grid, block, lds_bytes<float>(field, args), stream, args);
   } else {
-    hipLaunchKernelGGL((k_step_phys_f32<M, kF16>), grid, block, scale_window_bytes(args), stream, args);
+    hipLaunchKernelGGL((k_step_phys_f32<M, kF16>), grid, block, lds_bytes<float>(field, args), stream, args);
   }
   return hipGetLastError();
 }

@@ -22,7 +22,7 @@ constexpr double kDeg = 180.0 / (kPi * kREarth);      // metres -> degrees of ar
 constexpr double kG = 9.80665;                        // m s^-2 (box air mass, settling)
 constexpr double kRd = 287.058;                       // gas constant of dry air [J/(kg K)]
 constexpr int kMaxLevels = 512;                       // LDS level table capacity
-constexpr int kLutBins = 8192;                        // level lookup bins over log2(p)
+constexpr int kLutBins = 4096;                        // level lookup bins over log2(p)
 constexpr int kBlock = 256;                           // 4 wave64 per block
 constexpr int kXcds = 8;                              // MI355X: 8 XCDs, 32 CUs each
 
@@ -40,6 +40,11 @@ struct StepArgs {
 
   const void *met;             // packed levels, ring slot s at met + s*level_elems records
   int64_t level_elems;         // nx*ny*nz
+  // Spread of the 16 values of each cell per variable, for the level pair
+  // whose earlier level sits in ring slot s, at sig + s*level_elems records
+  // (cell (k, j, i) at (k*ny + j)*nx + i): {su, sv, sw, 0} as double (FP64
+  // arithmetic) or float; null without mesoscale diffusion.
+  const void *sig;
   const float *scales;         // [nt][3][nz] (R16 storage)
   const double *plev;          // [nz] device
   const double *inv_dp;        // [nz-1] 1 / (plev[k] - plev[k+1])
@@ -463,43 +468,30 @@ __device__ __forceinline__ void cell_scales(const StepArgs &a, const Loc<R> &L, 
 
 // Quadrilinear interpolation, the time weight applied first at each of the
 // 8 corners, then along lon, lat and p.  Equal to interpolating in space at
-// both time levels and then in time (multilinear), up to rounding.
-// R16 storage: the four corners of a (time level, level) slab share one
-// scale, so each slab is interpolated along lon and lat on the decoded
-// values and scaled once, then time and p follow (4 scale multiplies per
-// variable instead of 16; the same multilinear value up to rounding).
+// both time levels and then in time (multilinear), up to rounding.  The
+// staged path (mpt_stage.h) forms the same time-weighted corner values once
+// per grid point and then runs the same spatial part, so both paths give the
+// same bits.
+template <typename R>
+__device__ __forceinline__ void interp_spatial(const R cv[2][2][2][3], const Loc<R> &L, R out[3]) {
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    R yk[2];
+#pragma unroll
+    for (int dk = 0; dk < 2; ++dk) {
+      const R x0 = lerp(cv[dk][0][0][q], cv[dk][0][1][q], L.fx);
+      const R x1 = lerp(cv[dk][1][0][q], cv[dk][1][1][q], L.fx);
+      yk[dk] = lerp(x0, x1, L.fy);
+    }
+    out[q] = lerp(yk[0], yk[1], L.fz);
+  }
+}
+
 template <int F, typename R>
 __device__ __forceinline__ void interp_cell(const StepArgs &a, const Cell16<F> &c, const Loc<R> &L,
                                             R out[3]) {
   float sc[2][2][3];
   cell_scales<F, R>(a, L, sc);
-  if constexpr (F != kF32) {
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      R yk[2];
-#pragma unroll
-      for (int dk = 0; dk < 2; ++dk) {
-        R yt[2];
-#pragma unroll
-        for (int dl = 0; dl < 2; ++dl) {
-          R v[2][2];
-#pragma unroll
-          for (int dj = 0; dj < 2; ++dj)
-#pragma unroll
-            for (int di = 0; di < 2; ++di) {
-              const typename Rec<F>::T &r = c.r[dl][dk][dj][di];
-              v[dj][di] = (R)dec<F>(q == 0 ? r.x : q == 1 ? r.y : r.z);
-            }
-          const R x0 = lerp(v[0][0], v[0][1], L.fx);
-          const R x1 = lerp(v[1][0], v[1][1], L.fx);
-          yt[dl] = lerp(x0, x1, L.fy) * (R)sc[dl][dk][q];
-        }
-        yk[dk] = lerp(yt[0], yt[1], L.ft);
-      }
-      out[q] = lerp(yk[0], yk[1], L.fz);
-    }
-    return;
-  }
   R cv[2][2][2][3];   // [dk][dj][di][var], time-interpolated
 #pragma unroll
   for (int dk = 0; dk < 2; ++dk)
@@ -513,17 +505,7 @@ __device__ __forceinline__ void interp_cell(const StepArgs &a, const Cell16<F> &
 #pragma unroll
         for (int q = 0; q < 3; ++q) cv[dk][dj][di][q] = lerp(v0[q], v1[q], L.ft);
       }
-#pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    R yk[2];
-#pragma unroll
-    for (int dk = 0; dk < 2; ++dk) {
-      const R x0 = lerp(cv[dk][0][0][q], cv[dk][0][1][q], L.fx);
-      const R x1 = lerp(cv[dk][1][0][q], cv[dk][1][1][q], L.fx);
-      yk[dk] = lerp(x0, x1, L.fy);
-    }
-    out[q] = lerp(yk[0], yk[1], L.fz);
-  }
+  interp_spatial<R>(cv, L, out);
 }
 
 // Population standard deviation of the 16 values of each variable, in one
@@ -581,19 +563,14 @@ __device__ __forceinline__ R cos_floor(const StepArgs &a, double lat) {
 // ---- modules -----------------------------------------------------------------------
 
 // Explicit midpoint: x_mid = x + dt/2 f(x, t); x' = x + dt f(x_mid, t + dt/2),
-// f = (u / (R cos lat), v / R, omega) in degrees and hPa per second.
-template <int F, typename R>
-__device__ __forceinline__ void advect(const StepArgs &a, const double *s_plev, const double *s_idp,
-                                       const uint16_t *s_lut, double t, double &lon, double &lat,
-                                       double &p) {
-  Cell16<F> c;
+// f = (u / (R cos lat), v / R, omega) in degrees and hPa per second.  The
+// wind at a point and time comes from `wind(t, lon, lat, p, out)`; the new
+// position goes to (nlon, nlat, np).
+template <typename R, typename Wind>
+__device__ __forceinline__ void midpoint(const StepArgs &a, double t, double lon, double lat, double p,
+                                         Wind &&wind, double &nlon, double &nlat, double &np) {
   R w0[3], w1[3];
-  Loc<R> L;
-  __builtin_amdgcn_s_setprio(2);   // locate and gather at raised priority
-  locate_xyz<R>(a, s_plev, s_idp, s_lut, lon, lat, p, L);
-  locate_t<R>(a, t, L);
-  load_cell<F, R>(a, L, c);
-  interp_cell<F, R>(a, c, L, w0);
+  wind(t, lon, lat, p, w0);
   const R hdt = (R)(0.5 * a.dt);
   const R kdeg = (R)kDeg;
   const R d0lon = w0[0] * kdeg * Math<R>::rcp(cos_floor<R>(a, lat));
@@ -601,18 +578,30 @@ __device__ __forceinline__ void advect(const StepArgs &a, const double *s_plev, 
   const double lonm = lon + (double)(hdt * d0lon);
   const double latm = lat + (double)(hdt * d0lat);
   const double pm = p + (double)(hdt * w0[2]);
-
-  __builtin_amdgcn_s_setprio(2);   // locate and gather at raised priority
-  locate_xyz<R>(a, s_plev, s_idp, s_lut, lonm, latm, pm, L);
-  locate_t<R>(a, t + 0.5 * a.dt, L);
-  load_cell<F, R>(a, L, c);
-  interp_cell<F, R>(a, c, L, w1);
+  wind(t + 0.5 * a.dt, lonm, latm, pm, w1);
   const R fdt = (R)a.dt;
   const R d1lon = w1[0] * kdeg * Math<R>::rcp(cos_floor<R>(a, latm));
   const R d1lat = w1[1] * kdeg;
-  lon = lon + (double)(fdt * d1lon);
-  lat = lat + (double)(fdt * d1lat);
-  p = p + (double)(fdt * w1[2]);
+  nlon = lon + (double)(fdt * d1lon);
+  nlat = lat + (double)(fdt * d1lat);
+  np = p + (double)(fdt * w1[2]);
+}
+
+// Midpoint advection with each wind gathered from global memory.
+template <int F, typename R>
+__device__ __forceinline__ void advect(const StepArgs &a, const double *s_plev, const double *s_idp,
+                                       const uint16_t *s_lut, double t, double &lon, double &lat,
+                                       double &p) {
+  auto wind = [&](double tt, double x, double y, double z, R out[3]) {
+    Cell16<F> c;
+    Loc<R> L;
+    __builtin_amdgcn_s_setprio(2);   // locate and gather at raised priority
+    locate_xyz<R>(a, s_plev, s_idp, s_lut, x, y, z, L);
+    locate_t<R>(a, tt, L);
+    load_cell<F, R>(a, L, c);
+    interp_cell<F, R>(a, c, L, out);
+  };
+  midpoint<R>(a, t, lon, lat, p, wind, lon, lat, p);
 }
 
 // Reflect over the poles, wrap lon to [0, 360), clamp p.  Equal to
@@ -669,6 +658,27 @@ __device__ __forceinline__ void meso_sigma(const StepArgs &a, const double *s_pl
   sigma_cell<F, R>(a, c, L, sg);
 }
 
+// Spread of the cell holding (lon, lat, p) at the time-level pair of t_mid,
+// read from the per-cell table of that pair (one record).
+template <typename R>
+__device__ __forceinline__ void meso_sigma_table(const StepArgs &a, const double *s_plev,
+                                                 const double *s_idp, const uint16_t *s_lut, double t_mid,
+                                                 double lon, double lat, double p, R sg[3]) {
+  Loc<R> L;
+  locate_xyz<R>(a, s_plev, s_idp, s_lut, lon, lat, p, L);
+  locate_t<R>(a, t_mid, L);
+  const int off = (L.k * a.ny + L.j) * a.nx + L.i0;            // < 2^31: nx*ny*nz is
+  if constexpr (sizeof(R) == 8) {
+    const double2 *t = reinterpret_cast<const double2 *>(a.sig) + (size_t)L.l * (size_t)a.level_elems * 2;
+    const double2 x = t[2 * off], y = t[2 * off + 1];
+    sg[0] = x.x; sg[1] = x.y; sg[2] = y.x;
+  } else {
+    const float4 *t = reinterpret_cast<const float4 *>(a.sig) + (size_t)L.l * (size_t)a.level_elems;
+    const float4 x = t[off];
+    sg[0] = x.x; sg[1] = x.y; sg[2] = x.z;
+  }
+}
+
 // AR(1) update of the sub-grid wind with spread sg, then displacement.
 template <typename R>
 __device__ __forceinline__ void meso_apply(const StepArgs &a, const R sg[3], const R xi[3],
@@ -688,15 +698,16 @@ __device__ __forceinline__ void meso_apply(const StepArgs &a, const R sg[3], con
 }
 
 // AR(1) sub-grid wind from the spread of the 16 values of the current cell
-// at the time-level pair of the step's midpoint time, then displacement.
+// at the time-level pair of the step's midpoint time (from the per-cell
+// table), then displacement.
 template <int F, typename R>
 __device__ __forceinline__ void meso(const StepArgs &a, const double *s_plev, const double *s_idp,
                                      const uint16_t *s_lut, uint32_t id, uint32_t step, double t_mid,
                                      double &lon, double &lat, double &p, R &up, R &vp, R &wp) {
+  R sg[3];
+  meso_sigma_table<R>(a, s_plev, s_idp, s_lut, t_mid, lon, lat, p, sg);
   R xi[3];
   normals3<R>(a.seed, id, step, 1u, xi);
-  R sg[3];
-  meso_sigma<F, R>(a, s_plev, s_idp, s_lut, t_mid, lon, lat, p, sg);
   meso_apply<R>(a, sg, xi, lon, lat, p, up, vp, wp);
 }
 

@@ -27,6 +27,10 @@ hipError_t launch_pack_temp(int field, const float *T, float *t_scales, void *ds
 hipError_t launch_pack_sfc(const float *cape, const float *pel, const float *ps, float4 *dst, int64_t nxy,
                            hipStream_t stream);
 hipError_t launch_fill_f32(float *dst, float value, int64_t n, hipStream_t stream);
+// Spread table of the level pair in ring slots s0 (earlier) and s1 into out
+// (level_elems records of {su, sv, sw, 0}: double when f64, else float).
+hipError_t launch_cell_sigma(int field, bool f64, const void *met, const float *scales, int s0, int s1,
+                             int64_t level_elems, int nx, int ny, int nz, void *out, hipStream_t stream);
 
 // Sort (k_sort.hip).
 // Parcels per thread in the sort's key kernel (a block covers

@@ -21,6 +21,8 @@ struct mpt_ctx {
   size_t ws_bytes;
   void *met;              // nt levels
   size_t level_bytes;     // bytes per packed level
+  void *sig;              // [nt][npts] spread records of the level pair starting in each slot
+  size_t sig_rec;         // 32 (FP64 arithmetic) or 16 bytes; 0 without mesoscale diffusion
   int64_t npts;
   float *scales;          // [nt][3][nz]
   float *t_scales;        // [nt][nz] temperature scales (R16 storage)
@@ -165,7 +167,7 @@ mpt_status check_params(const mpt_params *p, const mpt_grid *g) {
 }
 
 struct Layout {
-  size_t met, scales, t_scales, sfc, sk, plev, inv_dp, lut, release, rank, rel_sorted, step_dev, keys, ranks, hist, spread,
+  size_t met, sig, scales, t_scales, sfc, sk, plev, inv_dp, lut, release, rank, rel_sorted, step_dev, keys, ranks, hist, spread,
       block_sums, out_pe, hyb_ab, s_wt, s_wb, s_wi, s_norm, s_bias, s_x, s_y, s_f, fb_mask, fb_list, fb_off, fb_sums, t_xn, t_h, t_dy, t_dh, t_yp, t_grad, t_part, total;
   uint32_t ntx, nty, ntz, ntiles, nkeys;
   int64_t s_chunk;
@@ -178,7 +180,14 @@ int64_t surr_chunk(int64_t n_max) {
   return c < kSurrChunk ? c : kSurrChunk;
 }
 
-Layout layout(const mpt_grid *g, int64_t n_max) {
+// Bytes per spread record: {su, sv, sw, 0} as double or float; none
+// without mesoscale diffusion.
+size_t sig_rec_bytes(const mpt_params *p) {
+  if (!(p->flags & MPT_MESO)) return 0;
+  return p->math == MPT_MATH_F64 ? 32 : 16;
+}
+
+Layout layout(const mpt_grid *g, const mpt_params *p, int64_t n_max) {
   Layout L;
   const size_t npts = (size_t)g->nx * g->ny * g->nz;
   L.ntx = (uint32_t)((g->nx + 7) / 8);
@@ -188,6 +197,7 @@ Layout layout(const mpt_grid *g, int64_t n_max) {
   L.nkeys = L.ntiles + kMaxScen + 1;
   size_t off = 0;
   L.met = off;        off += align_up(npts * rec_bytes(g->dtype) * g->nt);
+  L.sig = off;        off += align_up(npts * sig_rec_bytes(p) * g->nt);
   L.scales = off;     off += align_up(sizeof(float) * 3 * g->nz * g->nt);
   L.t_scales = off;   off += align_up(sizeof(float) * g->nz * g->nt);
   L.sfc = off;        off += align_up((size_t)16 * g->nx * g->ny * g->nt);
@@ -246,6 +256,7 @@ void fill_step_args(const mpt_ctx *c, const mpt_particles *P, uint32_t step0, in
   a.n = P->n;
   a.met = c->met;
   a.level_elems = c->npts;
+  a.sig = c->sig;
   a.scales = c->scales;
   a.plev = c->plev;
   a.inv_dp = c->inv_dp;
@@ -539,7 +550,7 @@ extern "C" {
 size_t mpt_workspace_bytes(const mpt_grid *grid, const mpt_params *params, int64_t n_max) {
   if (check_grid(grid) != MPT_OK || check_params(params, grid) != MPT_OK || n_max < 0) return 0;
   if (n_max >= kMaxParcels) return 0;
-  return layout(grid, n_max).total;
+  return layout(grid, params, n_max).total;
 }
 
 mpt_status mpt_create(const mpt_grid *grid, const mpt_params *params, int64_t n_max,
@@ -553,7 +564,7 @@ mpt_status mpt_create(const mpt_grid *grid, const mpt_params *params, int64_t n_
   if (n_max < 0) return MPT_ERR_ARG;
   if (n_max >= kMaxParcels) return MPT_ERR_UNSUPPORTED;
   if (!dev_workspace || !aligned(dev_workspace, 256)) return MPT_ERR_ARG;
-  const Layout L = layout(grid, n_max);
+  const Layout L = layout(grid, params, n_max);
   if (ws_bytes < L.total) return MPT_ERR_WORKSPACE;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return MPT_ERR_HIP;
@@ -574,6 +585,8 @@ mpt_status mpt_create(const mpt_grid *grid, const mpt_params *params, int64_t n_
   c->npts = (int64_t)grid->nx * grid->ny * grid->nz;
   c->level_bytes = (size_t)c->npts * rec_bytes(grid->dtype);
   c->met = ws + L.met;
+  c->sig_rec = sig_rec_bytes(params);
+  c->sig = c->sig_rec ? ws + L.sig : nullptr;
   c->scales = reinterpret_cast<float *>(ws + L.scales);
   c->t_scales = reinterpret_cast<float *>(ws + L.t_scales);
   c->sfc = reinterpret_cast<float4 *>(ws + L.sfc);
@@ -681,6 +694,25 @@ mpt_status pack_level(mpt_ctx *c, int slot, const float *u, const float *v, cons
   return MPT_OK;
 }
 
+// Spread tables of the level pairs that include resident level `pos`
+// (0 .. nt-1 from the oldest): pairs (pos-1, pos) and (pos, pos+1), when both
+// of their levels are stored.  A pair's table sits in the slot of its
+// earlier level.
+mpt_status update_sigma(mpt_ctx *c, int pos, hipStream_t s) {
+  if (!c->sig) return MPT_OK;
+  const int nt = c->grid.nt;
+  for (int q = pos - 1; q <= pos; ++q) {
+    if (q < 0 || q > nt - 2) continue;
+    const int s0 = (c->slot_first + q) % nt, s1 = (s0 + 1) % nt;
+    if (!(c->levels_ready & (1ull << s0)) || !(c->levels_ready & (1ull << s1))) continue;
+    void *out = static_cast<unsigned char *>(c->sig) + c->sig_rec * (size_t)c->npts * (size_t)s0;
+    if (launch_cell_sigma(c->grid.dtype, c->sig_rec == 32, c->met, c->scales, s0, s1, c->npts, c->grid.nx,
+                          c->grid.ny, c->grid.nz, out, s) != hipSuccess)
+      return MPT_ERR_HIP;
+  }
+  return MPT_OK;
+}
+
 // The convection / sedimentation fields must be stored on every resident
 // level when the step uses them.
 mpt_status check_phys(const mpt_ctx *c) {
@@ -718,7 +750,7 @@ mpt_status mpt_init_met(mpt_ctx *c, int32_t level, const float *u, const float *
   const mpt_status st = pack_level(c, slot, u, v, w, s);
   if (st != MPT_OK) return st;
   c->levels_ready |= 1ull << slot;
-  return MPT_OK;
+  return update_sigma(c, level, s);
 }
 
 mpt_status mpt_push_met(mpt_ctx *c, const float *u, const float *v, const float *w, void *hip_stream) {
@@ -733,7 +765,7 @@ mpt_status mpt_push_met(mpt_ctx *c, const float *u, const float *v, const float 
   c->lev_first += 1;
   c->slot_first = c->slot_first + 1 == c->grid.nt ? 0 : c->slot_first + 1;
   drop_graph(c);                        // captured launches hold the old window
-  return MPT_OK;
+  return update_sigma(c, c->grid.nt - 1, static_cast<hipStream_t>(hip_stream));
 }
 
 

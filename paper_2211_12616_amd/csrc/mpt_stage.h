@@ -1,0 +1,242 @@
+// mpt_stage.h -- LDS-staged winds for the step kernels.
+//
+// Parcels are sorted by tiles of 8 x 8 x 4 cells (lon fastest), so the 256
+// parcels of a block sit in one tile or in two tiles next to each other in
+// longitude.  For each of the two wind evaluations of a midpoint step the
+// whole block
+//   1. finds the bounding box of the cells its active parcels occupy (wave
+//      reductions, then over the four waves through LDS);
+//   2. if the box's grid points fit the LDS capacity: loads them from the
+//      two time levels with coalesced loads along longitude, weights them in
+//      time once per point (the evaluation time is the block's), and stores
+//      u, v, w as three planes in LDS;
+//   3. lets each parcel read its 8 corners from LDS and interpolate in
+//      space.
+// A box that does not fit (parcels not sorted, a block spanning the end of a
+// tile row, a sparse set) makes the whole block gather its 16 records per
+// parcel from global memory instead: the decision is uniform over the block,
+// so no wave runs both paths.  Both paths weight each corner in time first
+// and then interpolate along lon, lat and p with the same operations, so they
+// give the same bits.
+//
+// Every thread of the block must take part in each evaluation (two barriers
+// each), also threads without an active parcel.
+#pragma once
+
+#include "mpt_device.h"
+
+namespace mpt {
+
+// Capacity of the staged box in grid points: 3 x 4 B (FP32 values) or
+// 3 x 8 B (FP64) per point.
+template <typename R> struct BoxCap;
+template <> struct BoxCap<float> { static constexpr int value = 2048; };
+template <> struct BoxCap<double> { static constexpr int value = 1536; };
+
+__host__ __device__ constexpr size_t round16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+// Dynamic LDS of the step kernels, in this order: the R16 scale window
+// (kScaleWin x 3 x nz floats; it starts the dynamic region), the level
+// pressures and inverse spacings (nz doubles each), the box (u, v, w planes
+// of BoxCap values each) and the reduction slots (4 waves x 8 ints).
+template <typename R>
+__host__ __device__ constexpr size_t step_lds_bytes(int nz, bool r16) {
+  return (r16 ? round16((size_t)kScaleWin * 3 * nz * sizeof(float)) : 0) + round16((size_t)2 * nz * sizeof(double)) +
+         round16((size_t)3 * BoxCap<R>::value * sizeof(R)) + (size_t)(kBlock / 64) * 8 * sizeof(int);
+}
+
+template <typename R>
+struct StepLds {
+  double *plev, *idp;
+  R *bu, *bv, *bw;
+  int *red;
+};
+
+template <typename R>
+__device__ __forceinline__ StepLds<R> step_lds(int nz, bool r16) {
+  unsigned char *base = reinterpret_cast<unsigned char *>(s_scale_win);
+  size_t off = r16 ? round16((size_t)kScaleWin * 3 * nz * sizeof(float)) : 0;
+  StepLds<R> sm;
+  sm.plev = reinterpret_cast<double *>(base + off);
+  sm.idp = sm.plev + nz;
+  off += round16((size_t)2 * nz * sizeof(double));
+  sm.bu = reinterpret_cast<R *>(base + off);
+  sm.bv = sm.bu + BoxCap<R>::value;
+  sm.bw = sm.bv + BoxCap<R>::value;
+  off += round16((size_t)3 * BoxCap<R>::value * sizeof(R));
+  sm.red = reinterpret_cast<int *>(base + off);
+  return sm;
+}
+
+// The staged box (uniform over the block): grid columns gi .. gi + bi - 1
+// (mod nx), rows j0 .. j0 + bj - 1, levels k0 .. k0 + bk - 1.
+struct Box {
+  int gi, j0, k0, bi, bj, bk;
+  bool ok;
+};
+
+// ceil(2^32 / b) for 2 <= b <= 2^11, so that q / b == umulhi(q, m) for every
+// q < 2^11 (the error q (m - 2^32/b) / 2^32 < 2^-21 stays below 1/b).  The
+// FP64 quotient is correctly rounded and its error (<= 2^-21) is below the
+// distance 1/b of a non-integer quotient from the next integer.
+__device__ __forceinline__ uint32_t div_magic(int b) {
+  return (uint32_t)ceil(4294967296.0 / (double)b);
+}
+
+// Bounding box of the cells of the active lanes of the block.  Longitude is
+// periodic: the extent is measured both as it is and with the columns
+// shifted by half the circle, and the shorter one is taken (a block on the
+// seam has a short shifted extent).  Ends with a barrier.
+template <typename R>
+__device__ __forceinline__ Box block_box(const StepArgs &a, const StepLds<R> &sm, bool act, const Loc<R> &L) {
+  constexpr int big = 0x7fffffff;
+  const int h = a.nx >> 1;
+  int is = L.i0 + h;
+  if (is >= a.nx) is -= a.nx;
+  int v[8] = {act ? L.i0 : big, act ? -L.i0 : big, act ? is : big, act ? -is : big,
+              act ? L.j : big,  act ? -L.j : big,  act ? L.k : big, act ? -L.k : big};
+#pragma unroll
+  for (int q = 0; q < 8; ++q) v[q] = __ockl_wfred_min_i32(v[q]);
+  const int w = (int)threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    int4 *r = reinterpret_cast<int4 *>(sm.red) + 2 * w;
+    r[0] = make_int4(v[0], v[1], v[2], v[3]);
+    r[1] = make_int4(v[4], v[5], v[6], v[7]);
+  }
+  __syncthreads();
+  int m[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) m[q] = big;
+#pragma unroll
+  for (int ww = 0; ww < kBlock / 64; ++ww) {
+    const int4 *r = reinterpret_cast<const int4 *>(sm.red) + 2 * ww;
+    const int4 x = r[0], y = r[1];
+    m[0] = min(m[0], x.x); m[1] = min(m[1], x.y); m[2] = min(m[2], x.z); m[3] = min(m[3], x.w);
+    m[4] = min(m[4], y.x); m[5] = min(m[5], y.y); m[6] = min(m[6], y.z); m[7] = min(m[7], y.w);
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) m[q] = __builtin_amdgcn_readfirstlane(m[q]);
+  Box b;
+  b.ok = false;
+  b.gi = b.j0 = b.k0 = 0;
+  b.bi = b.bj = b.bk = 2;
+  if (m[0] == big) return b;                          // no active parcel
+  const int ea = -m[1] - m[0], eb = -m[3] - m[2];    // column extents, plain and shifted
+  int gi = m[0], ext = ea;
+  if (eb < ea) {
+    gi = m[2] - h;
+    if (gi < 0) gi += a.nx;
+    ext = eb;
+  }
+  b.gi = gi;
+  b.bi = ext + 2;                                     // corners i0 and i0 + 1
+  b.j0 = m[4];
+  b.bj = -m[5] - m[4] + 2;
+  b.k0 = m[6];
+  b.bk = -m[7] - m[6] + 2;
+  const int64_t npts = (int64_t)b.bi * b.bj * b.bk;
+  b.ok = b.bi <= a.nx && npts <= BoxCap<R>::value;
+  return b;
+}
+
+// Loads the box's points from the two time levels of L (slots l, l1; R16:
+// decoded with the scales of levels la and la + 1 from the window), weights
+// them in time with L.ft and stores u, v, w in LDS.  Point q of the box is
+// column q % bi, row (q / bi) % bj, level q / (bi bj); consecutive threads
+// take consecutive columns, so each row is one coalesced run.
+template <int F, typename R>
+__device__ __forceinline__ void stage_box(const StepArgs &a, const StepLds<R> &sm, const Box &b, const Loc<R> &L) {
+  using T = typename Rec<F>::T;
+  const T *lev0 = reinterpret_cast<const T *>(a.met) + (size_t)L.l * (size_t)a.level_elems;
+  const T *lev1 = reinterpret_cast<const T *>(a.met) + (size_t)L.l1 * (size_t)a.level_elems;
+  const int npts = b.bi * b.bj * b.bk;
+  const uint32_t mi = __builtin_amdgcn_readfirstlane(div_magic(b.bi));
+  const uint32_t mj = __builtin_amdgcn_readfirstlane(div_magic(b.bj));
+  const float *sw0 = s_scale_win + (L.la % kScaleWin) * 3 * a.nz;
+  const float *sw1 = s_scale_win + ((L.la + 1) % kScaleWin) * 3 * a.nz;
+  for (int q = (int)threadIdx.x; q < npts; q += kBlock) {
+    const int r = (int)__umulhi((uint32_t)q, mi);
+    const int ii = q - r * b.bi;
+    const int kk = (int)__umulhi((uint32_t)r, mj);
+    const int jj = r - kk * b.bj;
+    int gi = b.gi + ii;
+    if (gi >= a.nx) gi -= a.nx;
+    const int k = b.k0 + kk;
+    const int off = (k * a.ny + b.j0 + jj) * a.nx + gi;   // < 2^31: nx*ny*nz is
+    const T r0 = lev0[off], r1 = lev1[off];
+    float sc0[3] = {1.0f, 1.0f, 1.0f}, sc1[3] = {1.0f, 1.0f, 1.0f};
+    if constexpr (F != kF32) {
+      sc0[0] = sw0[k]; sc0[1] = sw0[a.nz + k]; sc0[2] = sw0[2 * a.nz + k];
+      sc1[0] = sw1[k]; sc1[1] = sw1[a.nz + k]; sc1[2] = sw1[2 * a.nz + k];
+    }
+    R v0[3], v1[3];
+    Fetch<F, R>::get(r0, sc0, v0);
+    Fetch<F, R>::get(r1, sc1, v1);
+    sm.bu[q] = lerp(v0[0], v1[0], L.ft);
+    sm.bv[q] = lerp(v0[1], v1[1], L.ft);
+    sm.bw[q] = lerp(v0[2], v1[2], L.ft);
+  }
+}
+
+// The 8 time-weighted corners of L's cell from the staged box, then the
+// spatial interpolation.
+template <typename R>
+__device__ __forceinline__ void interp_box(const StepArgs &a, const StepLds<R> &sm, const Box &b, const Loc<R> &L,
+                                           R out[3]) {
+  int ci = L.i0 - b.gi;
+  if (ci < 0) ci += a.nx;
+  const int sj = b.bi, sk = b.bi * b.bj;
+  const int base = (L.k - b.k0) * sk + (L.j - b.j0) * sj + ci;
+  R cv[2][2][2][3];
+#pragma unroll
+  for (int dk = 0; dk < 2; ++dk)
+#pragma unroll
+    for (int dj = 0; dj < 2; ++dj)
+#pragma unroll
+      for (int di = 0; di < 2; ++di) {
+        const int q = base + dk * sk + dj * sj + di;
+        cv[dk][dj][di][0] = sm.bu[q];
+        cv[dk][dj][di][1] = sm.bv[q];
+        cv[dk][dj][di][2] = sm.bw[q];
+      }
+  interp_spatial<R>(cv, L, out);
+}
+
+// Wind at (lon, lat, p, t) for the active lanes; every thread of the block
+// calls it.  Staged through LDS when the block's box fits, else gathered.
+template <int F, typename R>
+__device__ __forceinline__ void wind_block(const StepArgs &a, const StepLds<R> &sm, const uint16_t *s_lut, bool act,
+                                           double t, double lon, double lat, double p, R out[3]) {
+  Loc<R> L;
+  locate_xyz<R>(a, sm.plev, sm.idp, s_lut, lon, lat, p, L);
+  locate_t<R>(a, t, L);
+  const Box b = block_box<R>(a, sm, act, L);
+  if (b.ok) stage_box<F, R>(a, sm, b, L);
+  __syncthreads();
+  if (b.ok) {
+    if (act) interp_box<R>(a, sm, b, L, out);
+  } else if (act) {
+    Cell16<F> c;
+    load_cell<F, R>(a, L, c);
+    interp_cell<F, R>(a, c, L, out);
+  }
+}
+
+// Midpoint advection of the block's active lanes (positions of the others
+// are left alone); every thread of the block calls it.
+template <int F, typename R>
+__device__ __forceinline__ void advect_block(const StepArgs &a, const StepLds<R> &sm, const uint16_t *s_lut, bool act,
+                                             double t, double &lon, double &lat, double &p) {
+  auto wind = [&](double tt, double x, double y, double z, R out[3]) {
+    wind_block<F, R>(a, sm, s_lut, act, tt, x, y, z, out);
+  };
+  double nlon, nlat, np;
+  midpoint<R>(a, t, lon, lat, p, wind, nlon, nlat, np);
+  if (act) {
+    lon = nlon;
+    lat = nlat;
+    p = np;
+  }
+}
+
+}  // namespace mpt
