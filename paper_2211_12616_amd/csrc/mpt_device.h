@@ -172,14 +172,18 @@ template <> struct Math<float> {
   static __device__ __forceinline__ float uni(uint32_t x) {
     return ((float)(x >> 8) + 0.5f) * (1.0f / 16777216.0f);
   }
-  static __device__ __forceinline__ float log_(float x) { return __logf(x); }
-  static __device__ __forceinline__ float sqrt_(float x) { return __fsqrt_rn(x); }
+  // hardware log2 and square root (within 1 ulp, no denormal scaling): the
+  // arguments are uniforms >= 2^-25, Box-Muller radii and spreads (the
+  // spreads' zero maps to zero)
+  static __device__ __forceinline__ float log_(float x) { return __builtin_amdgcn_logf(x) * 0.693147180559945309f; }
+  static __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
   static __device__ __forceinline__ float exp_(float x) { return __expf(x); }
   static __device__ __forceinline__ void sincospi_(float x, float *s, float *c) {
     __sincosf(x * (float)kPi, s, c);
   }
   static __device__ __forceinline__ float cospi_(float x) { return __cosf(x * (float)kPi); }
-  static __device__ __forceinline__ float rcp(float x) { return __frcp_rn(x); }
+  // hardware reciprocal (within 1 ulp): x in [cos 89.999 deg, 1]
+  static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 };
 
 // Three standard normals for (id, step, purpose): Box-Muller on one Philox

@@ -537,8 +537,8 @@ SurrW surr_weights(const mpt_ctx *c, const float *params, const float *norm) {
 }
 
 void drop_graph(mpt_ctx *c) {
-  if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
-  if (c->graph) hipGraphDestroy(c->graph);
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
   c->graph_exec = nullptr;
   c->graph = nullptr;
 }
@@ -924,12 +924,12 @@ mpt_status mpt_step_graph(mpt_ctx *c, mpt_particles *P, uint32_t step0, int32_t 
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(s, &g);
     if (st != MPT_OK || e != hipSuccess || !g) {
-      if (g) hipGraphDestroy(g);
+      if (g) (void)hipGraphDestroy(g);
       return st != MPT_OK ? st : MPT_ERR_HIP;
     }
     hipGraphExec_t x = nullptr;
     if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) {
-      hipGraphDestroy(g);
+      (void)hipGraphDestroy(g);
       return MPT_ERR_HIP;
     }
     c->graph = g;

@@ -21,6 +21,8 @@
 //
 // Every thread of the block must take part in each evaluation (two barriers
 // each), also threads without an active parcel.
+//
+// block_ref_column gives the column the first box is measured from.
 #pragma once
 
 #include "mpt_device.h"
@@ -75,68 +77,88 @@ struct Box {
   bool ok;
 };
 
-// ceil(2^32 / b) for 2 <= b <= 2^11, so that q / b == umulhi(q, m) for every
-// q < 2^11 (the error q (m - 2^32/b) / 2^32 < 2^-21 stays below 1/b).  The
-// FP64 quotient is correctly rounded and its error (<= 2^-21) is below the
-// distance 1/b of a non-integer quotient from the next integer.
-__device__ __forceinline__ uint32_t div_magic(int b) {
-  return (uint32_t)ceil(4294967296.0 / (double)b);
-}
+// Division by a box extent b (2 <= b <= kMaxExtent) of indices q < 2^11:
+// q / b == umulhi(q, ceil(2^32 / b)) (the error q (m - 2^32/b) / 2^32 < 2^-21
+// stays below 1/b, the distance of a non-integer quotient from the next
+// integer).  The magic numbers come from a constant table (scalar loads).
+constexpr int kMaxExtent = 256;
+struct DivMagic {
+  uint32_t m[kMaxExtent + 1];
+  constexpr DivMagic() : m() {
+    for (int b = 2; b <= kMaxExtent; ++b) m[b] = (uint32_t)((0x100000000ull + (uint64_t)b - 1) / (uint64_t)b);
+  }
+};
+__constant__ constexpr DivMagic kDivMagic{};
 
-// Bounding box of the cells of the active lanes of the block.  Longitude is
-// periodic: the extent is measured both as it is and with the columns
-// shifted by half the circle, and the shorter one is taken (a block on the
-// seam has a short shifted extent).  Ends with a barrier.
+// Bounding box of the cells of the active lanes of the block.  Columns are
+// measured from iref, a column near the block (uniform: the start of the
+// block's previous box), the short way round the circle.  Each wave reduces
+// its active lanes' offsets (min of the values and of their negatives, in
+// each direction); the four waves' results meet in LDS, every lane combines
+// them and the box goes to scalar registers.  iref becomes the new box's
+// first column.  Contains the block's first barrier of the evaluation.
 template <typename R>
-__device__ __forceinline__ Box block_box(const StepArgs &a, const StepLds<R> &sm, bool act, const Loc<R> &L) {
+__device__ __forceinline__ Box block_box(const StepArgs &a, const StepLds<R> &sm, bool act, const Loc<R> &L,
+                                         int &iref) {
   constexpr int big = 0x7fffffff;
   const int h = a.nx >> 1;
-  int is = L.i0 + h;
-  if (is >= a.nx) is -= a.nx;
-  int v[8] = {act ? L.i0 : big, act ? -L.i0 : big, act ? is : big, act ? -is : big,
-              act ? L.j : big,  act ? -L.j : big,  act ? L.k : big, act ? -L.k : big};
-#pragma unroll
-  for (int q = 0; q < 8; ++q) v[q] = __ockl_wfred_min_i32(v[q]);
+  int di = L.i0 - iref;
+  if (di > h) di -= a.nx;
+  else if (di < -h) di += a.nx;
+  const int v0 = __ockl_wfred_min_i32(act ? di : big), v1 = __ockl_wfred_min_i32(act ? -di : big);
+  const int v2 = __ockl_wfred_min_i32(act ? L.j : big), v3 = __ockl_wfred_min_i32(act ? -L.j : big);
+  const int v4 = __ockl_wfred_min_i32(act ? L.k : big), v5 = __ockl_wfred_min_i32(act ? -L.k : big);
   const int w = (int)threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
     int4 *r = reinterpret_cast<int4 *>(sm.red) + 2 * w;
-    r[0] = make_int4(v[0], v[1], v[2], v[3]);
-    r[1] = make_int4(v[4], v[5], v[6], v[7]);
+    r[0] = make_int4(v0, v1, v2, v3);
+    r[1] = make_int4(v4, v5, 0, 0);
   }
   __syncthreads();
-  int m[8];
+  int m[6];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) m[q] = big;
+  for (int q = 0; q < 6; ++q) m[q] = big;
 #pragma unroll
   for (int ww = 0; ww < kBlock / 64; ++ww) {
     const int4 *r = reinterpret_cast<const int4 *>(sm.red) + 2 * ww;
     const int4 x = r[0], y = r[1];
     m[0] = min(m[0], x.x); m[1] = min(m[1], x.y); m[2] = min(m[2], x.z); m[3] = min(m[3], x.w);
-    m[4] = min(m[4], y.x); m[5] = min(m[5], y.y); m[6] = min(m[6], y.z); m[7] = min(m[7], y.w);
+    m[4] = min(m[4], y.x); m[5] = min(m[5], y.y);
   }
 #pragma unroll
-  for (int q = 0; q < 8; ++q) m[q] = __builtin_amdgcn_readfirstlane(m[q]);
+  for (int q = 0; q < 6; ++q) m[q] = __builtin_amdgcn_readfirstlane(m[q]);
   Box b;
   b.ok = false;
   b.gi = b.j0 = b.k0 = 0;
   b.bi = b.bj = b.bk = 2;
   if (m[0] == big) return b;                          // no active parcel
-  const int ea = -m[1] - m[0], eb = -m[3] - m[2];    // column extents, plain and shifted
-  int gi = m[0], ext = ea;
-  if (eb < ea) {
-    gi = m[2] - h;
-    if (gi < 0) gi += a.nx;
-    ext = eb;
-  }
+  int gi = iref + m[0];
+  if (gi < 0) gi += a.nx;
+  else if (gi >= a.nx) gi -= a.nx;
+  iref = gi;
   b.gi = gi;
-  b.bi = ext + 2;                                     // corners i0 and i0 + 1
-  b.j0 = m[4];
-  b.bj = -m[5] - m[4] + 2;
-  b.k0 = m[6];
-  b.bk = -m[7] - m[6] + 2;
-  const int64_t npts = (int64_t)b.bi * b.bj * b.bk;
-  b.ok = b.bi <= a.nx && npts <= BoxCap<R>::value;
+  b.bi = -m[1] - m[0] + 2;                            // corners i0 and i0 + 1
+  b.j0 = m[2];
+  b.bj = -m[3] - m[2] + 2;
+  b.k0 = m[4];
+  b.bk = -m[5] - m[4] + 2;
+  b.ok = b.bi <= a.nx && b.bi <= kMaxExtent && b.bj <= kMaxExtent && b.bi * b.bj * b.bk <= BoxCap<R>::value;
   return b;
+}
+
+// A column near the block's parcels, the same in every thread: the column of
+// the block's first parcel (index i_first), or 0 when that parcel has no
+// finite longitude (any column is correct; a far one makes the first box
+// miss and the block gather instead).
+__device__ __forceinline__ int block_ref_column(const StepArgs &a, int64_t i_first, bool valid) {
+  if (!valid) return 0;
+  const double lon = a.lon[i_first];
+  if (!isfinite(lon)) return 0;
+  const double lam = lon - 360.0 * floor((lon - a.lon0) * (1.0 / 360.0));
+  int i0 = (int)floor((lam - a.lon0) * a.inv_dlon);
+  if (i0 >= a.nx) i0 -= a.nx;
+  if (i0 < 0) i0 += a.nx;
+  return __builtin_amdgcn_readfirstlane(i0);
 }
 
 // Loads the box's points from the two time levels of L (slots l, l1; R16:
@@ -150,31 +172,46 @@ __device__ __forceinline__ void stage_box(const StepArgs &a, const StepLds<R> &s
   const T *lev0 = reinterpret_cast<const T *>(a.met) + (size_t)L.l * (size_t)a.level_elems;
   const T *lev1 = reinterpret_cast<const T *>(a.met) + (size_t)L.l1 * (size_t)a.level_elems;
   const int npts = b.bi * b.bj * b.bk;
-  const uint32_t mi = __builtin_amdgcn_readfirstlane(div_magic(b.bi));
-  const uint32_t mj = __builtin_amdgcn_readfirstlane(div_magic(b.bj));
+  const uint32_t mi = kDivMagic.m[b.bi];
+  const uint32_t mj = kDivMagic.m[b.bj];
   const float *sw0 = s_scale_win + (L.la % kScaleWin) * 3 * a.nz;
   const float *sw1 = s_scale_win + ((L.la + 1) % kScaleWin) * 3 * a.nz;
-  for (int q = (int)threadIdx.x; q < npts; q += kBlock) {
-    const int r = (int)__umulhi((uint32_t)q, mi);
-    const int ii = q - r * b.bi;
-    const int kk = (int)__umulhi((uint32_t)r, mj);
-    const int jj = r - kk * b.bj;
-    int gi = b.gi + ii;
-    if (gi >= a.nx) gi -= a.nx;
-    const int k = b.k0 + kk;
-    const int off = (k * a.ny + b.j0 + jj) * a.nx + gi;   // < 2^31: nx*ny*nz is
-    const T r0 = lev0[off], r1 = lev1[off];
-    float sc0[3] = {1.0f, 1.0f, 1.0f}, sc1[3] = {1.0f, 1.0f, 1.0f};
-    if constexpr (F != kF32) {
-      sc0[0] = sw0[k]; sc0[1] = sw0[a.nz + k]; sc0[2] = sw0[2 * a.nz + k];
-      sc1[0] = sw1[k]; sc1[1] = sw1[a.nz + k]; sc1[2] = sw1[2 * a.nz + k];
+  // two points per thread and pass, so that four loads are in flight
+  for (int q0 = (int)threadIdx.x; q0 < npts; q0 += 2 * kBlock) {
+    T r0[2], r1[2];
+    int kq[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int q = min(q0 + u * kBlock, npts - 1);   // a duplicate of the last point is harmless
+      const int r = (int)__umulhi((uint32_t)q, mi);
+      const int ii = q - r * b.bi;
+      const int kk = (int)__umulhi((uint32_t)r, mj);
+      const int jj = r - kk * b.bj;
+      int gi = b.gi + ii;
+      if (gi >= a.nx) gi -= a.nx;
+      kq[u] = b.k0 + kk;
+      const int off = (kq[u] * a.ny + b.j0 + jj) * a.nx + gi;   // < 2^31: nx*ny*nz is
+      r0[u] = lev0[off];
+      r1[u] = lev1[off];
     }
-    R v0[3], v1[3];
-    Fetch<F, R>::get(r0, sc0, v0);
-    Fetch<F, R>::get(r1, sc1, v1);
-    sm.bu[q] = lerp(v0[0], v1[0], L.ft);
-    sm.bv[q] = lerp(v0[1], v1[1], L.ft);
-    sm.bw[q] = lerp(v0[2], v1[2], L.ft);
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int q = q0 + u * kBlock;
+      const int k = kq[u];
+      float sc0[3] = {1.0f, 1.0f, 1.0f}, sc1[3] = {1.0f, 1.0f, 1.0f};
+      if constexpr (F != kF32) {
+        sc0[0] = sw0[k]; sc0[1] = sw0[a.nz + k]; sc0[2] = sw0[2 * a.nz + k];
+        sc1[0] = sw1[k]; sc1[1] = sw1[a.nz + k]; sc1[2] = sw1[2 * a.nz + k];
+      }
+      R v0[3], v1[3];
+      Fetch<F, R>::get(r0[u], sc0, v0);
+      Fetch<F, R>::get(r1[u], sc1, v1);
+      if (q < npts) {
+        sm.bu[q] = lerp(v0[0], v1[0], L.ft);
+        sm.bv[q] = lerp(v0[1], v1[1], L.ft);
+        sm.bw[q] = lerp(v0[2], v1[2], L.ft);
+      }
+    }
   }
 }
 
@@ -206,11 +243,11 @@ __device__ __forceinline__ void interp_box(const StepArgs &a, const StepLds<R> &
 // calls it.  Staged through LDS when the block's box fits, else gathered.
 template <int F, typename R>
 __device__ __forceinline__ void wind_block(const StepArgs &a, const StepLds<R> &sm, const uint16_t *s_lut, bool act,
-                                           double t, double lon, double lat, double p, R out[3]) {
+                                           double t, double lon, double lat, double p, int &iref, R out[3]) {
   Loc<R> L;
   locate_xyz<R>(a, sm.plev, sm.idp, s_lut, lon, lat, p, L);
   locate_t<R>(a, t, L);
-  const Box b = block_box<R>(a, sm, act, L);
+  const Box b = block_box<R>(a, sm, act, L, iref);
   if (b.ok) stage_box<F, R>(a, sm, b, L);
   __syncthreads();
   if (b.ok) {
@@ -223,12 +260,12 @@ __device__ __forceinline__ void wind_block(const StepArgs &a, const StepLds<R> &
 }
 
 // Midpoint advection of the block's active lanes (positions of the others
-// are left alone); every thread of the block calls it.
+// are left alone); every thread of the block calls it with the same iref.
 template <int F, typename R>
 __device__ __forceinline__ void advect_block(const StepArgs &a, const StepLds<R> &sm, const uint16_t *s_lut, bool act,
-                                             double t, double &lon, double &lat, double &p) {
+                                             double t, double &lon, double &lat, double &p, int &iref) {
   auto wind = [&](double tt, double x, double y, double z, R out[3]) {
-    wind_block<F, R>(a, sm, s_lut, act, tt, x, y, z, out);
+    wind_block<F, R>(a, sm, s_lut, act, tt, x, y, z, iref, out);
   };
   double nlon, nlat, np;
   midpoint<R>(a, t, lon, lat, p, wind, nlon, nlat, np);
