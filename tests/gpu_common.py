@@ -12,6 +12,22 @@ import oracle
 
 TOL_F64_DEG, TOL_F64_HPA = 1e-9, 1e-7
 TOL_R32_DEG, TOL_R32_HPA = 1e-4, 0.05
+CONT = oracle.ADVECT | oracle.TURB       # the part of the step continuous in the position
+
+# Full-physics trajectories of the FP32-arithmetic forms on the 0.3 deg grid
+# over 240 steps: the fraction of parcels beyond the tolerance (nearly all
+# of them mesoscale-cell flips, the rest rounding drift within twice the
+# tolerance, as test_gpu_c2.explain_flips shows) is bounded by twice the
+# largest fraction measured for the three forms at 1e5 parcels (F32 1.7e-4,
+# BF16 1.5e-4, FP16 0.9e-4).
+FLIP_FRAC_0P3 = 3.4e-4
+# One flip changes the AR(1) state by at most sqrt(1 - r^2) f max|d sigma|
+# max|xi| = 0.182 x 0.16 x 20 m/s x 5.9 = 3.4 m/s, which moves the parcel by
+# at most 3.4 m/s x dt / (1 - r) = 37 km (0.33 deg) while it decays; with the
+# wind differences along two trajectories that far apart (up to ~5 m/s over
+# the remaining 12 h, ~200 km) a flagged parcel stays within 2.5 deg, and
+# its pressure within the vertical analogue, 25 hPa.
+FLIP_CEILING_DEG, FLIP_CEILING_HPA = 2.5, 25.0
 
 
 def require_gpu():
@@ -64,7 +80,8 @@ def compare(gpu, ref, tol_deg, tol_hpa, label=""):
     d = oracle.chord_deg(gpu.lon, gpu.lat, ref.lon, ref.lat)
     dp = np.abs(gpu.p - ref.p)
     say(f"[{label}] n={len(d)} max chord {d.max():.3e} deg  p99 {np.percentile(d, 99):.3e}  "
-        f"max |dp| {dp.max():.3e} hPa")
+        f"max |dp| {dp.max():.3e} hPa  beyond ({tol_deg:g} deg, {tol_hpa:g} hPa): "
+        f"{int(np.sum((d > tol_deg) | (dp > tol_hpa)))}")
     assert np.all(np.isfinite(gpu.lon)) == np.all(np.isfinite(ref.lon))
     assert d.max() <= tol_deg, (label, d.max(), int(np.argmax(d)))
     assert dp.max() <= tol_hpa, (label, dp.max(), int(np.argmax(dp)))
