@@ -28,18 +28,18 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
-# Per-unit figures of the step kernel, from rocprofv3 --pmc runs of this
-# workload (profiles/k_step_<form>_1e8_0p3deg.md): FLOP per parcel-step =
-# 64 x SQ_INSTS_VALU_FLOPS_FP64 (F64 form) or _FP32 (the FP32-arithmetic
-# forms) per launch / parcel-steps per launch; the FP16 form does the same
-# arithmetic as BF16 (decode, scale, interpolate).  HBM bytes per 10-step
-# launch of 1e8 parcels = 2 x FETCH_SIZE + WRITE_SIZE (KiB x 1024; a 1 GiB
-# copy reads FETCH_SIZE = 512 MiB and WRITE_SIZE = 1 GiB).
-FLOP_PER_PS = {"f64": 1154.0, "f32": 669.0, "bf16": 741.0, "f16": 741.0}
-TRAFFIC_BYTES_PER_LAUNCH = {"f64": (2 * 3.703e6 + 5.975e6) * 1024,
-                            "f32": (2 * 3.110e6 + 4.803e6) * 1024,
-                            "bf16": (2 * 2.561e6 + 4.804e6) * 1024,
-                            "f16": (2 * 2.560e6 + 4.804e6) * 1024}
+# Algorithmic FLOP of one parcel-step (all modules): the FP64-pipe operations
+# the method needs -- two locates, two 16-corner quadrilinear interpolations
+# of three winds, the spread of 16 values per wind, two Philox blocks with
+# Box-Muller, cos(lat) three times -- estimated at 800-1000; the upper end is
+# taken, so the fraction is not flattered.  The same count prices every
+# arithmetic form.
+FLOP_PER_PS = 1000.0
+# HBM bytes per 10-step launch of 1e8 parcels = 2 x FETCH_SIZE + WRITE_SIZE
+# (KiB x 1024; a 1 GiB copy reads FETCH_SIZE = 512 MiB and WRITE_SIZE =
+# 1 GiB) from rocprofv3 --pmc runs of this workload on the current step
+# kernels (profiles/k_step_<form>_1e8_0p3deg.md); None where not measured.
+TRAFFIC_BYTES_PER_LAUNCH = {"f64": None, "f32": None, "bf16": None, "f16": None}
 # The convection / sedimentation kernel, F64 form, same workload
 # (profiles/k_step_phys_1e8_0p3deg.md): FP64 FLOP per parcel-step and HBM
 # bytes per 10-step launch (2 x FETCH_SIZE + WRITE_SIZE), with sedimentation
@@ -62,7 +62,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--n", type=float, default=1e8)
     ap.add_argument("--form", default="f64", choices=list(FORMS))
-    ap.add_argument("--extra-forms", default="f32,bf16",
+    ap.add_argument("--extra-forms", default="f32,bf16,f16",
                     help="comma list of other forms timed on the same workload ('' = none)")
     ap.add_argument("--sort-interval", type=int, default=10)
     ap.add_argument("--fuse", type=int, default=10)
@@ -75,8 +75,12 @@ def parse():
                     help="also run a plain device copy of known size (counter calibration)")
     ap.add_argument("--scenarios", action="store_true",
                     help="also run the batched release workload (16 scenarios, 480 steps)")
-    ap.add_argument("--surrogate", action="store_true",
-                    help="also train and run the learned 8-step surrogate (480 steps)")
+    ap.add_argument("--no-surrogate", dest="surrogate", action="store_false",
+                    help="skip the learned 8-step surrogate leg (trained here, then 480 steps against plain)")
+    ap.add_argument("--no-c3", dest="c3", action="store_false",
+                    help="skip the 16-bit storage precision report (240 steps, sampled ids vs the FP64 oracle)")
+    ap.add_argument("--hbm-steps", type=int, default=10,
+                    help="one-step launches of the F64 form timed against the HBM roofline (0 = skip)")
     ap.add_argument("--ml2pl", action="store_true",
                     help="also time the model-level -> pressure-level regridding of one time level")
     ap.add_argument("--stream-met", action="store_true",
@@ -216,7 +220,7 @@ def run_surrogate(met, mpt, inputs, torch, args, nsteps=480):
     ctxs.step_surrogate(S, 0, nsteps, fb)
     torch.cuda.synchronize()
     t_surr = time.perf_counter() - t0
-    hs = S.to_host()
+    ids_s, pos_s = _by_id_gpu(S, torch)
     del S
     torch.cuda.empty_cache()
     ctxp = mpt.Context(met, mpt.make_params(math=1, sort_interval=16, fuse=8), n_max=n)
@@ -227,12 +231,11 @@ def run_surrogate(met, mpt, inputs, torch, args, nsteps=480):
     ctxp.step(Pp, 0, nsteps)
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
-    hp = Pp.to_host()
-    del Pp
+    ids_p, pos_p = _by_id_gpu(Pp, torch)
+    del Pp, ctxp, ctxs
     torch.cuda.empty_cache()
-    oa, ob = np.argsort(hs.id), np.argsort(hp.id)
-    d = _chord_km(hs.lon[oa], hs.lat[oa], hp.lon[ob], hp.lat[ob])
-    del hs, hp
+    d = _chord_km_gpu(pos_s, pos_p, torch)
+    del pos_s, pos_p
     # the learned part alone: advection only, same parcels and steps
     adv = {}
     for name in ("surr", "plain"):
@@ -247,12 +250,10 @@ def run_surrogate(met, mpt, inputs, torch, args, nsteps=480):
         else:
             ctxa.step(A, 0, nsteps)
         torch.cuda.synchronize()
-        h = A.to_host()
-        adv[name] = h
+        adv[name] = _by_id_gpu(A, torch)[1]
         del A, ctxa
         torch.cuda.empty_cache()
-    oa, ob = np.argsort(adv["surr"].id), np.argsort(adv["plain"].id)
-    da = _chord_km(adv["surr"].lon[oa], adv["surr"].lat[oa], adv["plain"].lon[ob], adv["plain"].lat[ob])
+    da = _chord_km_gpu(adv["surr"], adv["plain"], torch)
     del adv
     blocks = n * (nsteps // K)
     return {"workload": "learned 8-step surrogate, 1e8 parcels, 0.3deg grid, 480 steps, FP32 fields, "
@@ -264,14 +265,33 @@ def run_surrogate(met, mpt, inputs, torch, args, nsteps=480):
             "surrogate_particle_steps_per_s": n * nsteps / t_surr,
             "plain_f32_particle_steps_per_s": n * nsteps / t_plain,
             "speedup_vs_plain_f32": t_plain / t_surr,
-            "error_vs_plain_km": {"p50": float(np.percentile(d, 50)), "p99": float(np.percentile(d, 99)),
-                                  "max": float(d.max()),
-                                  "note": "accepted blocks draw their diffusion at once, independently of "
-                                          "the plain scheme's per-step draws"},
+            "error_vs_plain_km": {"p50": d[0], "p99": d[1], "max": d[2],
+                                  "note": "all modules; accepted blocks run the plain steps' diffusion "
+                                          "draws with the spread of the block's first cell"},
             "advect_only": {"fallback_rate": adv_fb,
-                            "error_vs_plain_km": {"p50": float(np.percentile(da, 50)),
-                                                  "p99": float(np.percentile(da, 99)),
-                                                  "max": float(da.max())}}}
+                            "error_vs_plain_km": {"p50": da[0], "p99": da[1], "max": da[2]}}}
+
+
+def _by_id_gpu(P, torch):
+    """(ids, positions [n, 3] lon, lat, p) of a device particle set, ordered by id."""
+    o = torch.argsort(P.id.to(torch.int64) & 0xFFFFFFFF)
+    return P.id[o], torch.stack([P.lon[o], P.lat[o], P.p[o]], 1)
+
+
+def _chord_km_gpu(a, b, torch):
+    """p50, p99, max of the great-circle chord distance [km] between two
+    position sets ordered by id (FP64 on the GPU)."""
+    r = math.pi / 180.0
+
+    def xyz(x):
+        lo, la = x[:, 0] * r, x[:, 1] * r
+        return torch.stack([torch.cos(la) * torch.cos(lo), torch.cos(la) * torch.sin(lo), torch.sin(la)], 1)
+
+    c = torch.linalg.norm(xyz(a) - xyz(b), dim=1)
+    d = 2.0 * torch.arcsin(torch.clamp(c / 2.0, max=1.0)) * 6371.0
+    q = torch.quantile(d[torch.randperm(len(d), device=d.device)[:(1 << 24) - 1]].float(),
+                       torch.tensor([0.5, 0.99], device=d.device))
+    return float(q[0]), float(q[1]), float(d.max())
 
 
 def run_ml2pl(met, mpt, inputs, torch, args, reps=5):
@@ -528,6 +548,51 @@ def unique_points_per_step(P, met, torch):
     return int(bitmap.sum().item())
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def run_c3(met, mpt, inputs, torch, part, form, nsample=2000, nsteps=240):
+    """Config 3: 16-bit storage of the headline workload over 240 steps (all
+    modules, sort every 10, 10 steps per launch), position error of a seeded
+    id sample against the FP64 oracle on the original FP32 fields."""
+    import oracle
+    math_, dtype = FORMS[form]
+    n = part.n
+    ctx = mpt.Context(met, mpt.make_params(math=math_, sort_interval=10, fuse=10), n_max=n, dtype=dtype,
+                      resident=3)
+    ctx.upload_met(met)
+    P = mpt.DeviceParticles.from_host(part, math=math_)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(P, 0, nsteps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    rng = np.random.Generator(np.random.PCG64(323))
+    sample = np.sort(rng.choice(n, nsample, replace=False))
+    ids = P.id.to(torch.int64) & 0xFFFFFFFF
+    where = torch.empty(n, dtype=torch.int64, device="cuda")
+    where[ids] = torch.arange(n, device="cuda")
+    loc = where[torch.from_numpy(sample).cuda()]
+    lon, lat = P.lon[loc].cpu().numpy(), P.lat[loc].cpu().numpy()
+    level_bytes = ctx.met_level_bytes()
+    del P, ctx, where, ids, loc
+    torch.cuda.empty_cache()
+    r = part.subset(sample)
+    oracle.run(oracle.Met(met), oracle.ctl(dt=180.0), r, 0, nsteps)
+    km = oracle.chord_deg(lon, lat, r.lon, r.lat) * math.pi * 6371.0 / 180.0
+    return {"steps": nsteps, "sample": f"{nsample} seeded ids of the {n} parcels",
+            "km_vs_fp64_oracle_on_fp32_fields": {"mean": float(km.mean()), "p99": float(np.percentile(km, 99)),
+                                                  "max": float(km.max())},
+            "met_level_bytes": level_bytes, "particle_steps_per_s_240": n * nsteps / el}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -545,8 +610,11 @@ def main():
     n = int(args.n)
     W, K = args.warmup, args.steps
     dt = 180.0
-    total = W + K
-    nt = int(math.ceil(total * dt / inputs.DT_MET)) + 1
+    total = W + K + max(0, args.hbm_steps)
+    nt_timed = int(math.ceil(total * dt / inputs.DT_MET)) + 1
+    nt = nt_timed
+    if args.c3:
+        nt = max(nt, 3)
     if args.scenarios or args.surrogate or args.stream_met:
         nt = max(nt, int(math.ceil(480 * dt / inputs.DT_MET)) + 1)
     t0 = time.time()
@@ -558,17 +626,18 @@ def main():
 
     forms = [args.form] + [f for f in args.extra_forms.split(",") if f and f != args.form]
     results = {}
+    hbm_leg = None
     for form in forms:
         math_, dtype = FORMS[form]
         log(f"form {form}: upload")
         params = mpt.make_params(math=math_, sort_interval=0, fuse=args.fuse, presort=1)
-        ctx = mpt.Context(met, params, n_max=n, dtype=dtype)
+        ctx = mpt.Context(met, params, n_max=n, dtype=dtype, resident=nt_timed)
         ctx.upload_met(met)
         P = mpt.DeviceParticles.from_host(part, math=math_)
         stream = torch.cuda.current_stream()
         S = args.sort_interval
 
-        def run(step0, nsteps, ev=None):
+        def run(step0, nsteps, ev=None, fuse=args.fuse):
             s = step0
             end = step0 + nsteps
             while s < end:
@@ -580,7 +649,7 @@ def main():
                     if ev is not None:
                         ev["sort"][-1][1].record(stream)
                 stop = min(end, (s // S + 1) * S) if S > 0 else end
-                stop = min(stop, s + args.fuse)
+                stop = min(stop, s + fuse)
                 if ev is not None:
                     ev["step"].append(([torch.cuda.Event(enable_timing=True) for _ in range(2)],
                                        stop - s))
@@ -604,11 +673,25 @@ def main():
         step_ms = [a.elapsed_time(b) for (a, b), _ in ev["step"]]
         step_steps = [k for _, k in ev["step"]]
         sort_ms = [a.elapsed_time(b) for a, b in ev["sort"]]
-        h = P.to_host() if form == args.form else None
-        ok = bool(np.all(np.isfinite(P.lon.cpu().numpy())))
+        ok = bool(torch.isfinite(P.lon).all().item())
         results[form] = dict(elapsed=elapsed, step_ms=step_ms, step_steps=step_steps,
-                             sort_ms=sort_ms, unique_pts=pts, ok=ok, host=h)
+                             sort_ms=sort_ms, unique_pts=pts, ok=ok)
         log(f"form {form}: {n * K / elapsed:.3e} particle-steps/s, {1e3 * elapsed / K:.3f} ms/step")
+        if form == "f64" and args.hbm_steps > 0:
+            # one step per launch: the state is read and written every step,
+            # the per-step form priced against HBM
+            ev1 = {"sort": [], "step": []}
+            run(W + K, args.hbm_steps, ev1, fuse=1)
+            torch.cuda.synchronize()
+            ms1 = [a.elapsed_time(b) for (a, b), _ in ev1["step"]]
+            field_b = pts * 2 * 12 / n
+            gbs = n * (100.0 + field_b) / (float(np.mean(ms1)) * 1e-3) / 1e9
+            hbm_leg = {"form": "F64", "steps_per_launch": 1, "launches": len(ms1),
+                       "avg_launch_ms": float(np.mean(ms1)),
+                       "algorithmic_bytes_per_particle_step": 100.0 + field_b,
+                       "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                       "particle_steps_per_s": n / (float(np.mean(ms1)) * 1e-3)}
+            log(f"form f64, one step per launch: {np.mean(ms1):.3f} ms, {gbs:.0f} GB/s algorithmic")
         del ctx, P
         torch.cuda.empty_cache()
 
@@ -618,17 +701,14 @@ def main():
     rec_b = 12 if dtype == 0 else 6
     field_b = main_r["unique_pts"] * 2 * rec_b / n
     durations = main_r["step_ms"]
+    ksteps = main_r["step_steps"]
     avg_ms = float(np.mean(durations))
-    # the dominant kernel is bound by its vector ALU (FP64 for the F64 form):
-    # algorithmic FLOP per launch = FLOP per parcel-step x parcel-steps
-    flop_ps = FLOP_PER_PS[args.form]
+    # the dominant kernel is bound by its vector ALU: algorithmic FLOP per
+    # launch = FLOP per parcel-step x parcel-steps of that launch
     peak = FP64_PEAK_TFLOPS if math_ == 0 else FP32_PEAK_TFLOPS
-    achieved_tf = float(np.mean([flop_ps * n * k / (d * 1e-3) / 1e12
-                                 for k, d in zip(main_r["step_steps"], durations)]))
-    hbm_gbs = float(np.mean([n * (state_b + field_b * k) / (d * 1e-3) / 1e9
-                             for k, d in zip(main_r["step_steps"], durations)]))
-    traffic = TRAFFIC_BYTES_PER_LAUNCH.get(args.form) if (n == 100_000_000 and args.fuse == 10
-                                                          and args.nz == 137) else None
+    achieved_tf = float(np.mean([FLOP_PER_PS * n * k / (d * 1e-3) / 1e12 for k, d in zip(ksteps, durations)]))
+    hbm_gbs = float(np.mean([n * (state_b + field_b * k) / (d * 1e-3) / 1e9 for k, d in zip(ksteps, durations)]))
+    traffic = TRAFFIC_BYTES_PER_LAUNCH.get(args.form) if (n == 100_000_000 and args.nz == 137) else None
     value = n * K / main_r["elapsed"]
     line = {
         "metric": METRIC,
@@ -647,21 +727,35 @@ def main():
                                "dt=180s, sort every 10 steps",
                    "n_particles": n, "grid": f"{args.nx}x{args.ny}x{args.nz}",
                    "form": args.form.upper(), "sort_interval": args.sort_interval,
-                   "fuse": args.fuse, "met_levels": nt},
+                   "fuse": args.fuse, "met_levels": nt_timed},
         "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved_tf / peak, "traffic": traffic,
-                     "kernel": "k_step", "avg_launch_ms": avg_ms,
-                     "flop_per_particle_step": flop_ps,
-                     "steps_per_launch": args.fuse,
+                     "kernel": "k_step_f64<0>" if math_ == 0 else f"k_step_f32<0, {dtype}>",
+                     "avg_launch_ms": avg_ms, "launches": len(durations),
+                     "flop_per_particle_step": FLOP_PER_PS,
+                     "steps_per_launch": ksteps,
                      "hbm_algorithmic_GBps": hbm_gbs,
                      "hbm_frac": hbm_gbs / HBM_PEAK_GBS,
-                     "algorithmic_bytes_per_particle_step": state_b / args.fuse + field_b},
+                     "algorithmic_bytes_per_particle_step": state_b * len(ksteps) / sum(ksteps) + field_b},
         "sort_ms_avg": float(np.mean(main_r["sort_ms"])) if main_r["sort_ms"] else None,
         "forms": {f: {"particle_steps_per_s": n * K / r["elapsed"],
                       "step_kernel_ms_avg": float(np.mean(r["step_ms"])),
+                      "steps_per_launch": r["step_steps"],
                       "sort_ms_avg": float(np.mean(r["sort_ms"])) if r["sort_ms"] else None,
                       "finite": r["ok"]} for f, r in results.items()},
     }
+    if hbm_leg is not None:
+        line["hbm_per_step_form"] = hbm_leg
+
+    if args.c3:
+        c3 = {}
+        for form in ("bf16", "f16"):
+            log(f"c3: {form} storage, 240 steps, sampled ids vs the FP64 oracle")
+            c3[form] = run_c3(met, mpt, inputs, torch, part, form)
+            if form in results and "f32" in results:
+                c3[form]["speedup_vs_f32_timed"] = results["f32"]["elapsed"] / results[form]["elapsed"]
+        c3["f32_met_level_bytes"] = 16 * args.nx * args.ny * args.nz
+        line["c3"] = c3
 
     if args.cpu_seconds > 0:
         import oracle
@@ -679,10 +773,19 @@ def main():
         tc = time.perf_counter()
         oracle.run(m, c, sample, 0, steps_cpu, nthreads=nthreads)
         tcpu = time.perf_counter() - tc
+        # one thread, a sample sized for about a fifth of the time
+        m1 = int(max(200, m_cpu / max(1, nthreads) / 5))
+        s1 = part.subset(np.arange(0, m1))
+        t1 = time.perf_counter()
+        oracle.run(m, c, s1, 0, steps_cpu, nthreads=1)
+        t1 = time.perf_counter() - t1
         line["cpu_baseline"] = {"value": m_cpu * steps_cpu / tcpu, "unit": "particle-steps/s",
                                 "cores": nthreads, "kind": "oracle",
                                 "sample": f"ids 0..{m_cpu - 1} of the same workload, steps 0..{steps_cpu - 1} "
-                                          f"(all modules, FP64), {tcpu:.1f} s wall"}
+                                          f"(all modules, FP64), {tcpu:.1f} s wall",
+                                "single_thread": {"value": m1 * steps_cpu / t1, "sample": f"ids 0..{m1 - 1}, "
+                                                  f"steps 0..{steps_cpu - 1}, {t1:.1f} s wall"},
+                                "cpu_model": cpu_model()}
     extras = {}
     if args.scenarios:
         log("scenario workload")
@@ -706,7 +809,7 @@ def main():
         torch.cuda.empty_cache()
     if args.surrogate:
         log("surrogate workload")
-        extras["surrogate"] = run_surrogate(met, mpt, inputs, torch, args)
+        line["surrogate"] = run_surrogate(met, mpt, inputs, torch, args)
         torch.cuda.empty_cache()
     if extras:
         line["extras"] = extras

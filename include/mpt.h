@@ -392,11 +392,12 @@ mpt_status mpt_surrogate_forward(mpt_ctx *ctx, int64_t n, const float *x, float 
 /* nsteps steps in blocks of MPT_SURR_K: per parcel, predict the block's
  * advection, estimate its error as the distance [km] between the
  * prediction and MPT_SURR_K*dt times the wind at the predicted midpoint; if
- * at most tau, apply it plus the block's turbulent and mesoscale diffusion
- * drawn at once from their distribution over MPT_SURR_K steps (mesoscale
- * spread of the block-start cell; Philox purposes 2, 3, 4 at the block's
- * first step, so the noise is not the plain steps' draws); otherwise run
- * MPT_SURR_K plain steps (those parcels, in increasing index order).  Adds the number
+ * at most tau, apply it plus the turbulent and mesoscale diffusion of the
+ * block's MPT_SURR_K steps with the plain steps' random numbers (Philox
+ * counters (id, step, 0) and (id, step, 1) of each step) and the mesoscale
+ * spread of the block-start cell, summed and converted at the displaced
+ * position; otherwise run MPT_SURR_K plain steps (those parcels, in
+ * increasing index order).  Adds the number
  * of parcel-blocks that fell back to *fallbacks (device uint32).  err_out
  * (device, n floats, or NULL) receives each parcel's error estimate of the
  * last block (for calibrating tau; needs sort_interval == 0).  Needs

@@ -669,8 +669,9 @@ __global__ void k_surr_adam(float *params, const float *grad, float *m, float *v
 // A block of kSurrK steps runs over chunks of parcels in three passes:
 // stencil rows (k_surr_x), MLP (k_surr_mlp), then the consistency estimate
 // and either acceptance (displacement plus the block's turbulent and
-// mesoscale diffusion, drawn at once with the block-start spread) or a place
-// in the list of parcels that take kSurrK plain steps (k_surr_apply).
+// mesoscale diffusion with the plain steps' draws and the block-start
+// spread) or a place in the list of parcels that take kSurrK plain steps
+// (k_surr_apply).
 
 // The FP32 field at time t (all points): F = lerp(level l, level l + 1, ft)
 // per component with the (l, ft) a parcel at time t computes.
@@ -735,7 +736,13 @@ __global__ __launch_bounds__(256) void k_surr_x(const StepArgs a, const SurrW W,
 }
 
 // The accepted block of parcel i: the predicted displacement, then the
-// block's diffusion drawn at once; lon, lat, p receive the final position.
+// turbulent and mesoscale diffusion of the block's kSurrK steps with the
+// random numbers the plain steps draw (Philox counters (id, step, 0) and
+// (id, step, 1) for each step of the block) and the mesoscale spread of the
+// cell holding the parcel at the block's start (at the first step's middle
+// time); the summed displacement is converted to degrees and hPa at the
+// displaced position, then one position fix.  lon, lat, p receive the final
+// position.
 __device__ __forceinline__ void apply_block(const StepArgs &a, int64_t i, double t0, float de, float dn,
                                             float dpp, float c0, double &lon, double &lat, double &p) {
   const float kdeg = (float)kDeg;
@@ -746,41 +753,39 @@ __device__ __forceinline__ void apply_block(const StepArgs &a, int64_t i, double
   const bool meso_on = (a.flags & kMeso) != 0;
   float sg[3] = {0.f, 0.f, 0.f};
   if (meso_on) {
-    Cell16<kF32> mc;
     Loc<float> L0;
     surr_locate(a, lon, lat, p, t0 + 0.5 * a.dt, L0);
-    load_cell<kF32, float>(a, L0, mc);
-    sigma_cell<kF32, float>(a, mc, L0, sg);
+    const float4 x = reinterpret_cast<const float4 *>(a.sig)[(size_t)L0.l * (size_t)a.level_elems +
+                                                             (size_t)((L0.k * a.ny + L0.j) * a.nx + L0.i0)];
+    sg[0] = x.x; sg[1] = x.y; sg[2] = x.z;
   }
   lon = lon + (double)(de * 1000.0f * kdeg / c0);
   lat = lat + (double)(dn * 1000.0f * kdeg);
   p = p + (double)dpp;
   position(a, lon, lat, p);
-  // the block's turbulent and mesoscale diffusion, drawn at once from its
-  // distribution with the spread held at its block-start value (normals
-  // of purposes 2, 3, 4 at the block's first step)
   if (a.flags & (kTurb | kMeso)) {
     float ex = 0.f, ny = 0.f, dz = 0.f, dpm = 0.f;     // m east, m north, m up; hPa
-    if (a.flags & kTurb) {
-      float xi[3];
-      normals3<float>(a.seed, id, a.step0, 2u, xi);
-      ex = (float)a.agg_sh * xi[0];
-      ny = (float)a.agg_sh * xi[1];
-      dz = (float)a.agg_sz * xi[2];
-    }
-    if (meso_on) {
-      float n1[3], n2[3];
-      normals3<float>(a.seed, id, a.step0, 3u, n1);
-      normals3<float>(a.seed, id, a.step0, 4u, n2);
-      const float A = (float)a.agg_a, rk = (float)a.agg_rk, fdt = (float)a.dt;
-      const float l11 = (float)a.agg_l11, l21 = (float)a.agg_l21, l22 = (float)a.agg_l22;
-      const float cu = (float)a.rs_fh * sg[0], cv = (float)a.rs_fh * sg[1], cw = (float)a.rs_fv * sg[2];
-      ex += fdt * (A * up + cu * l11 * n1[0]);
-      ny += fdt * (A * vp + cv * l11 * n1[1]);
-      dpm = fdt * (A * wp + cw * l11 * n1[2]);
-      up = rk * up + cu * (l21 * n1[0] + l22 * n2[0]);
-      vp = rk * vp + cv * (l21 * n1[1] + l22 * n2[1]);
-      wp = rk * wp + cw * (l21 * n1[2] + l22 * n2[2]);
+    const float r = (float)a.r_ar, fdt = (float)a.dt;
+    const float cu = (float)a.rs_fh * sg[0], cv = (float)a.rs_fh * sg[1], cw = (float)a.rs_fv * sg[2];
+    for (int s = 0; s < kSurrK; ++s) {
+      const uint32_t step = a.step0 + (uint32_t)s;
+      if (a.flags & kTurb) {
+        float xi[3];
+        normals3<float>(a.seed, id, step, 0u, xi);
+        ex += (float)a.sig_h * xi[0];
+        ny += (float)a.sig_h * xi[1];
+        dz += (float)a.sig_z * xi[2];
+      }
+      if (meso_on) {
+        float xi[3];
+        normals3<float>(a.seed, id, step, 1u, xi);
+        up = fma(r, up, cu * xi[0]);
+        vp = fma(r, vp, cv * xi[1]);
+        wp = fma(r, wp, cw * xi[2]);
+        ex += up * fdt;
+        ny += vp * fdt;
+        dpm += wp * fdt;
+      }
     }
     const float c1 = cos_floor<float>(a, lat);
     lon = lon + (double)(ex * kdeg / c1);

@@ -81,11 +81,6 @@ struct StepArgs {
   const uint32_t *index_count;
   // Resident met levels: absolute index of the oldest and its ring slot.
   int32_t lev_first, slot_first;
-  // Diffusion of a k-step surrogate block drawn at once (spread frozen):
-  // turbulence sqrt(k) sig_h, sqrt(k) sig_z; AR(1) sums A = r + ... + r^k,
-  // r^k, and the Cholesky factor (l11, l21, l22) of the covariance of
-  // (sum_j B_j xi_j, sum_j r^(k-1-j) xi_j), B_j = 1 + r + ... + r^(k-1-j).
-  double agg_sh, agg_sz, agg_a, agg_rk, agg_l11, agg_l21, agg_l22;
   // Convection and sedimentation: surface records {cape, pel, ps, 0} per
   // (ring slot, j, i); temperature scales per (ring slot, level) for R16
   // storage; CAPE threshold, particle radius and density.

@@ -279,33 +279,6 @@ void fill_step_args(const mpt_ctx *c, const mpt_particles *P, uint32_t step0, in
   a.r_ar = r;
   a.rs_fh = rs * q.meso_fh;
   a.rs_fv = rs * q.meso_fv;
-  {
-    // block aggregates of kSurrK steps (surrogate acceptance)
-    const int K = kSurrK;
-    double A = 0.0, rk = 1.0, s11 = 0.0, s22 = 0.0, s12 = 0.0;
-    for (int m = 1; m <= K; ++m) {
-      rk *= r;
-      A += rk;
-    }
-    for (int jj = 0; jj < K; ++jj) {
-      double B = 0.0, pw = 1.0;
-      for (int m = 0; m <= K - 1 - jj; ++m) {
-        B += pw;
-        pw *= r;
-      }
-      const double e = pow(r, K - 1 - jj);
-      s11 += B * B;
-      s22 += e * e;
-      s12 += B * e;
-    }
-    a.agg_sh = sqrt((double)K) * a.sig_h;
-    a.agg_sz = sqrt((double)K) * a.sig_z;
-    a.agg_a = A;
-    a.agg_rk = rk;
-    a.agg_l11 = sqrt(s11);
-    a.agg_l21 = s12 / a.agg_l11;
-    a.agg_l22 = sqrt(fmax(s22 - a.agg_l21 * a.agg_l21, 0.0));
-  }
   a.cos_cap = cos(89.999 * kPi / 180.0);
   a.seed = q.seed;
   a.step0 = step0;
