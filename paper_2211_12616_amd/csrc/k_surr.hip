@@ -13,6 +13,7 @@
 // the activations in LDS and the weights read from global memory.
 #include "mpt_device.h"
 #include "mpt_internal.h"
+#include "mpt_stage.h"
 
 namespace mpt {
 
@@ -105,15 +106,11 @@ __device__ __forceinline__ f32x4 mlp16(const uint16_t *xs, int ldx, const SurrW 
 // levels around the cell.  The values of one level shift c come out
 // together, in ascending c: sink(c + 1, g) with g[(b+1)*9 + (a+1)*3 + var];
 // the input index of a value is var*27 + (c+1)*9 + (b+1)*3 + (a+1).
-// kTime: the values are interpolated between the time-level pair of L;
-// otherwise f0 is the field already interpolated to the parcel's time (one
-// load per point instead of two, the same values: k_surr_tfield applies the
-// same interpolation).
-template <bool kTime, class Sink>
-__device__ __forceinline__ void stencil81(const StepArgs &a, const Loc<float> &L, const float4 *f0, Sink sink) {
-  const float4 *base = reinterpret_cast<const float4 *>(a.met);
-  const float4 *lev0 = kTime ? base + (int64_t)L.l * a.level_elems : f0;
-  const float4 *lev1 = base + (int64_t)L.l1 * a.level_elems;
+// The values of grid point (k, j, i) come from src(k, j, i, v): the
+// time-interpolated field (global memory or an LDS box) or the two met
+// levels of L interpolated in time on the spot.
+template <class Src, class Sink>
+__device__ __forceinline__ void stencil81(const StepArgs &a, const Loc<float> &L, Src src, Sink sink) {
   int ic[4], jr[4], kr[4], pb[3], pc[3];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -134,22 +131,9 @@ __device__ __forceinline__ void stencil81(const StepArgs &a, const Loc<float> &L
     float xprev[3][3], xcur[3][3];       // [a][var] at the previous / current row slot
 #pragma unroll
     for (int qj = 0; qj < 4; ++qj) {
-      const int64_t r = ((int64_t)kr[qk] * a.ny + jr[qj]) * a.nx;
       float v[4][3];
 #pragma unroll
-      for (int qi = 0; qi < 4; ++qi) {
-        const float4 r0 = lev0[r + ic[qi]];
-        if constexpr (kTime) {
-          const float4 r1 = lev1[r + ic[qi]];
-          v[qi][0] = lerp(r0.x, r1.x, L.ft);
-          v[qi][1] = lerp(r0.y, r1.y, L.ft);
-          v[qi][2] = lerp(r0.z, r1.z, L.ft);
-        } else {
-          v[qi][0] = r0.x;
-          v[qi][1] = r0.y;
-          v[qi][2] = r0.z;
-        }
-      }
+      for (int qi = 0; qi < 4; ++qi) src(kr[qk], jr[qj], ic[qi], v[qi]);
 #pragma unroll
       for (int s = 0; s < 3; ++s)
 #pragma unroll
@@ -208,7 +192,16 @@ __global__ __launch_bounds__(256) void k_surr_datagen(const StepArgs a, int64_t 
   Loc<float> L;
   surr_locate(a, lo, la, pp, t0, L);
   float *xr = x + i * kSurrIn;
-  stencil81<true>(a, L, nullptr, [&](int sc, const float (&g)[27]) {
+  const float4 *lev0 = reinterpret_cast<const float4 *>(a.met) + (int64_t)L.l * a.level_elems;
+  const float4 *lev1 = reinterpret_cast<const float4 *>(a.met) + (int64_t)L.l1 * a.level_elems;
+  auto src = [&](int k, int j, int ii, float (&v)[3]) {
+    const int64_t q = ((int64_t)k * a.ny + j) * a.nx + ii;
+    const float4 r0 = lev0[q], r1 = lev1[q];
+    v[0] = lerp(r0.x, r1.x, L.ft);
+    v[1] = lerp(r0.y, r1.y, L.ft);
+    v[2] = lerp(r0.z, r1.z, L.ft);
+  };
+  stencil81(a, L, src, [&](int sc, const float (&g)[27]) {
 #pragma unroll
     for (int j = 0; j < 27; ++j) xr[(j % 3) * 27 + sc * 9 + j / 3] = g[j];
   });
@@ -689,15 +682,22 @@ __global__ __launch_bounds__(256) void k_surr_tfield(const StepArgs a, double t,
 
 // Stencil inputs of parcels i0 .. i0 + cnt - 1 at the block's start time,
 // normalized, as bf16 rows of 96 in the MLP's input order; a parcel with a
-// non-finite position gets a zero row.  Rows are staged in LDS (stores
-// between the gathers would hold up the waits for them, as the memory
-// counter covers both) and the block's 256 consecutive rows leave in one
+// non-finite position gets a zero row.  The block's 256 parcels (sorted by
+// tile) read their 4 x 4 x 4 stencil points from an LDS box: the bounding
+// box of their cells (mpt_stage.h) widened by one point below and two
+// above in each direction (rows and levels clamped to the grid), loaded
+// from the field at the block's start time with coalesced loads; a box that
+// does not fit makes the block read the points from global memory.  Rows
+// are staged in LDS and the block's 256 consecutive rows leave in one
 // coalesced copy.
 constexpr int kRowLd = kSurrInPad / 8 + 1;      // 16-byte units per staged row (padded)
+constexpr int kSurrBoxCap = 1536;               // grid points of the stencil box
 
 __global__ __launch_bounds__(256) void k_surr_x(const StepArgs a, const SurrW W, const float4 *F,
                                                 int64_t i0, int64_t cnt, uint16_t *X) {
   __shared__ bf16x8 srow[256 * kRowLd];
+  __shared__ float bu[kSurrBoxCap], bv[kSurrBoxCap], bw[kSurrBoxCap];
+  __shared__ __attribute__((aligned(16))) int red[(kBlock / 64) * 8];
   const int lb = logical_block((int)blockIdx.x, a.per_xcd);
   if (lb >= a.nblk) return;                       // uniform over the block
   const int64_t r0 = (int64_t)lb * 256;
@@ -711,18 +711,65 @@ __global__ __launch_bounds__(256) void k_surr_x(const StepArgs a, const SurrW W,
     p = a.p[i0 + r];
     valid = finite3(lon, lat, p);
   }
+  Loc<float> L;
+  surr_locate(a, lon, lat, p, a.t_start + (double)a.step0 * a.dt, L);
+  StepLds<float> sm;
+  sm.red = red;
+  int iref = block_ref_column(a, i0 + r0, true);
+  const Box b = block_box<float>(a, sm, valid, L, iref);
+  // stencil points of the box's cells
+  int gs = b.gi - 1;
+  if (gs < 0) gs += a.nx;
+  const int ni = b.bi + 2;
+  const int js = max(b.j0 - 1, 0), ks = max(b.k0 - 1, 0);
+  const int nj = min(b.j0 + b.bj, a.ny - 1) - js + 1, nk = min(b.k0 + b.bk, a.nz - 1) - ks + 1;
+  const bool staged = ni <= a.nx && ni <= kMaxExtent && nj <= kMaxExtent && ni * nj * nk <= kSurrBoxCap;
+  if (staged) {
+    const int npts = ni * nj * nk;
+    const uint32_t mi = kDivMagic.m[ni], mj = kDivMagic.m[nj];
+    for (int q = (int)threadIdx.x; q < npts; q += 256) {
+      const int rr = (int)__umulhi((uint32_t)q, mi);
+      const int ii = q - rr * ni;
+      const int kk = (int)__umulhi((uint32_t)rr, mj);
+      const int jj = rr - kk * nj;
+      int gi = gs + ii;
+      if (gi >= a.nx) gi -= a.nx;
+      const float4 v = F[((ks + kk) * a.ny + js + jj) * a.nx + gi];
+      bu[q] = v.x;
+      bv[q] = v.y;
+      bw[q] = v.z;
+    }
+  }
+  __syncthreads();
   if (valid) {
     float inv[3];
 #pragma unroll
     for (int v = 0; v < 3; ++v) inv[v] = 1.0f / W.norm[3 + v];
-    Loc<float> L;
-    surr_locate(a, lon, lat, p, a.t_start + (double)a.step0 * a.dt, L);
-    stencil81<false>(a, L, F, [&](int sc, const float (&g)[27]) {
+    auto sink = [&](int sc, const float (&g)[27]) {
       bf16x8 t[4];
       pack_ktile(g, inv, W.norm, t);
 #pragma unroll
       for (int c8 = 0; c8 < 4; ++c8) mine[4 * sc + c8] = t[c8];
-    });
+    };
+    if (staged) {
+      auto src = [&](int k, int j, int ii, float (&v)[3]) {
+        int li = ii - gs;
+        if (li < 0) li += a.nx;
+        const int q = ((k - ks) * nj + (j - js)) * ni + li;
+        v[0] = bu[q];
+        v[1] = bv[q];
+        v[2] = bw[q];
+      };
+      stencil81(a, L, src, sink);
+    } else {
+      auto src = [&](int k, int j, int ii, float (&v)[3]) {
+        const float4 f = F[((int64_t)k * a.ny + j) * a.nx + ii];
+        v[0] = f.x;
+        v[1] = f.y;
+        v[2] = f.z;
+      };
+      stencil81(a, L, src, sink);
+    }
   } else {
 #pragma unroll
     for (int c = 0; c < kSurrInPad / 8; ++c) mine[c] = frag8_zero();

@@ -158,16 +158,40 @@ def test_tau_zero_falls_back_to_plain_bitwise(mpt, met3):
     assert_bitwise(plain, by_id(P.to_host()))
 
 
-@pytest.mark.parametrize("n", [20_011, (1 << 20) + 777])
-def test_accepted_block_moves_by_the_forward_of_the_stencil(mpt, met3, n):
+def stencil_boxes_fit(met, part, cap=1536):
+    """Fraction of 256-parcel blocks (in the given order) whose stencil box
+    (cells' bounding box widened by one point below and two above, longitude
+    the short way round, rows and levels clamped) has at most cap points."""
+    m = oracle.Met(met)
+    idx, _ = oracle.locate(m, part.lon, part.lat, part.p, 0.0)
+    fit = []
+    for b in range(0, part.n, 256):
+        i0, j, k = idx[b:b + 256, 0], idx[b:b + 256, 1], idx[b:b + 256, 2]
+        ext = min(np.ptp(i0), np.ptp((i0 + met.nx // 2) % met.nx))
+        nj = min(j.max() + 2, met.ny - 1) - max(j.min() - 1, 0) + 1
+        nk = min(k.max() + 2, met.nz - 1) - max(k.min() - 1, 0) + 1
+        fit.append((ext + 4) * nj * nk <= cap)
+    return float(np.mean(fit))
+
+
+@pytest.mark.parametrize("n,presorted", [(20_011, False), ((1 << 20) + 777, False), ((1 << 20) + 777, True)])
+def test_accepted_block_moves_by_the_forward_of_the_stencil(mpt, met3, n, presorted):
     """Advection only, tau = inf: every parcel-block is accepted and moves by
     the MLP's displacement for the oracle's stencil at its start (forward
     pass pinned above), followed by the position fix.  n crosses the
     1 Mi-parcel pass size (the workspace of a context this large holds one
-    pass) with a ragged tail."""
+    pass) with a ragged tail.  Parcels in random order read their stencil
+    points from global memory; ordered by tile (presorted) nearly every
+    block reads them from its LDS box."""
     import torch
-    say(f"[accepted] n = {n}")
+    say(f"[accepted] n = {n}, presorted {presorted}")
     part = inputs.make_particles(n, 62)
+    if presorted:
+        keys = oracle.tile_keys(oracle.Met(met3), part.lon, part.lat, part.p)
+        part = part.subset(np.argsort(keys, kind="stable"))
+        frac = stencil_boxes_fit(met3, part)
+        say(f"[accepted] {frac:.4f} of the blocks fit the stencil box")
+        assert frac >= 0.95
     c = mpt.Context(met3, mpt.make_params(math=1, sort_interval=0, flags=mpt.ADVECT), n_max=n)
     c.upload_met(met3)
     lon, lat, p, step = starts(8192, 8)
