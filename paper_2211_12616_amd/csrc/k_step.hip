@@ -22,7 +22,7 @@ namespace mpt {
 // (mpt_stage.h), with barriers inside.
 template <int F, typename R, bool P>
 __device__ __forceinline__ void step_parcel(const StepArgs &a, const StepLds<R> &sm, const uint16_t *s_lut,
-                                            int64_t i, bool valid, uint32_t step0, int iref0, double &lon,
+                                            int64_t i, bool valid, uint32_t step0, BoxRef ref, double &lon,
                                             double &lat, double &p) {
   lon = lat = p = 0.0;
   bool live = false;
@@ -46,14 +46,13 @@ __device__ __forceinline__ void step_parcel(const StepArgs &a, const StepLds<R> 
     }
   }
   bool moved = false;
-  int iref = iref0;                               // uniform: the staged boxes' reference column
   for (int s = 0; s < a.nsteps; ++s) {
     const uint32_t step = step0 + (uint32_t)s;
     const bool act = live && (int64_t)step >= rel && finite3(lon, lat, p);
     moved = moved || act;
     const double t = a.t_start + (double)step * a.dt;
     if (a.flags & kAdvect) {
-      advect_block<F, R>(a, sm, s_lut, act, t, lon, lat, p, iref);
+      advect_block<F, R>(a, sm, s_lut, act, t, lon, lat, p, ref);
       if (act) position(a, lon, lat, p);
     }
     if (act && (a.flags & (kTurb | kMeso))) {
@@ -151,8 +150,8 @@ __device__ __forceinline__ void step_body(const StepArgs &a) {
       const bool valid = j < cnt;
       const int64_t i = valid ? (int64_t)a.index[j] : 0;
       const int64_t j0 = c * kBlock;
-      const int iref = block_ref_column(a, j0 < cnt ? (int64_t)a.index[j0] : 0, j0 < cnt);
-      step_parcel<F, R, P>(a, sm, s_lut, i, valid, step0, iref, lon, lat, p);
+      const BoxRef ref = block_ref(a, sm.plev, s_lut, j0 < cnt ? (int64_t)a.index[j0] : 0, j0 < cnt);
+      step_parcel<F, R, P>(a, sm, s_lut, i, valid, step0, ref, lon, lat, p);
       if (a.sk) leave_sort_key(a, sm.plev, s_lut, i, valid, lon, lat, p);   // uniform
     }
   } else if constexpr (M == kModeBlock) {
@@ -161,8 +160,8 @@ __device__ __forceinline__ void step_body(const StepArgs &a) {
     const int64_t i = (int64_t)lb * kBlock + threadIdx.x;
     double lon, lat, p;
     const bool valid = i < a.n;
-    const int iref = block_ref_column(a, (int64_t)lb * kBlock, true);
-    step_parcel<F, R, P>(a, sm, s_lut, i, valid, step0, iref, lon, lat, p);
+    const BoxRef ref = block_ref(a, sm.plev, s_lut, (int64_t)lb * kBlock, true);
+    step_parcel<F, R, P>(a, sm, s_lut, i, valid, step0, ref, lon, lat, p);
     if (a.sk) leave_sort_key(a, sm.plev, s_lut, i, valid, lon, lat, p);     // uniform
   } else {
     // persistent: XCD x owns an even share of the chunks of the prefix and
@@ -175,8 +174,8 @@ __device__ __forceinline__ void step_body(const StepArgs &a) {
     for (int64_t c = c_lo + q; c < c_hi; c += nq) {   // uniform over the block
       const int64_t i = c * kBlock + threadIdx.x;
       double lon, lat, p;
-      const int iref = block_ref_column(a, c * kBlock, true);
-      step_parcel<F, R, P>(a, sm, s_lut, i, i < bound, step0, iref, lon, lat, p);
+      const BoxRef ref = block_ref(a, sm.plev, s_lut, c * kBlock, true);
+      step_parcel<F, R, P>(a, sm, s_lut, i, i < bound, step0, ref, lon, lat, p);
     }
   }
 }

@@ -697,7 +697,7 @@ __global__ __launch_bounds__(256) void k_surr_x(const StepArgs a, const SurrW W,
                                                 int64_t i0, int64_t cnt, uint16_t *X) {
   __shared__ bf16x8 srow[256 * kRowLd];
   __shared__ float bu[kSurrBoxCap], bv[kSurrBoxCap], bw[kSurrBoxCap];
-  __shared__ __attribute__((aligned(16))) int red[(kBlock / 64) * 8];
+  __shared__ __attribute__((aligned(16))) int red[kRedInts];
   const int lb = logical_block((int)blockIdx.x, a.per_xcd);
   if (lb >= a.nblk) return;                       // uniform over the block
   const int64_t r0 = (int64_t)lb * 256;
@@ -715,8 +715,8 @@ __global__ __launch_bounds__(256) void k_surr_x(const StepArgs a, const SurrW W,
   surr_locate(a, lon, lat, p, a.t_start + (double)a.step0 * a.dt, L);
   StepLds<float> sm;
   sm.red = red;
-  int iref = block_ref_column(a, i0 + r0, true);
-  const Box b = block_box<float>(a, sm, valid, L, iref);
+  BoxRef ref = block_ref(a, a.plev, a.lut, i0 + r0, true);
+  const Box b = block_box<float>(a, sm, valid, L, ref);
   // stencil points of the box's cells
   int gs = b.gi - 1;
   if (gs < 0) gs += a.nx;

@@ -22,7 +22,7 @@
 // Every thread of the block must take part in each evaluation (two barriers
 // each), also threads without an active parcel.
 //
-// block_ref_column gives the column the first box is measured from.
+// block_ref gives the reference cell the first box is measured from.
 #pragma once
 
 #include "mpt_device.h"
@@ -37,14 +37,18 @@ template <> struct BoxCap<double> { static constexpr int value = 1536; };
 
 __host__ __device__ constexpr size_t round16(size_t x) { return (x + 15) & ~(size_t)15; }
 
+// Reduction slots of the box exchange: 8 ints per wave for the exact
+// bounds, then 2 per wave for the offset masks.
+constexpr int kRedInts = (kBlock / 64) * 8 + (kBlock / 64) * 2 + 8;
+
 // Dynamic LDS of the step kernels, in this order: the R16 scale window
 // (kScaleWin x 3 x nz floats; it starts the dynamic region), the level
 // pressures and inverse spacings (nz doubles each), the box (u, v, w planes
-// of BoxCap values each) and the reduction slots (4 waves x 8 ints).
+// of BoxCap values each) and the reduction slots.
 template <typename R>
 __host__ __device__ constexpr size_t step_lds_bytes(int nz, bool r16) {
   return (r16 ? round16((size_t)kScaleWin * 3 * nz * sizeof(float)) : 0) + round16((size_t)2 * nz * sizeof(double)) +
-         round16((size_t)3 * BoxCap<R>::value * sizeof(R)) + (size_t)(kBlock / 64) * 8 * sizeof(int);
+         round16((size_t)3 * BoxCap<R>::value * sizeof(R)) + (size_t)kRedInts * sizeof(int);
 }
 
 template <typename R>
@@ -90,16 +94,22 @@ struct DivMagic {
 };
 __constant__ constexpr DivMagic kDivMagic{};
 
-// Bounding box of the cells of the active lanes of the block.  Columns are
-// measured from iref, a column near the block (uniform: the start of the
-// block's previous box), the short way round the circle.  Each wave reduces
-// its active lanes' offsets (min of the values and of their negatives, in
-// each direction); the four waves' results meet in LDS, every lane combines
-// them and the box goes to scalar registers.  iref becomes the new box's
-// first column.  Contains the block's first barrier of the evaluation.
+// Reference cell of the block's boxes (uniform): the start of the previous
+// box, or at a launch's start the origin of the first parcel's tile.
+struct BoxRef {
+  int i, j, k;
+};
+
+// Exact bounding box of the cells of the active lanes of the block.
+// Columns are measured from ref.i, the short way round the circle.  Each
+// wave reduces its active lanes' offsets (min of the values and of their
+// negatives, in each direction); the four waves' results meet in LDS, every
+// lane combines them and the box goes to scalar registers.  ref becomes
+// the new box's start.  Contains a barrier.
 template <typename R>
-__device__ __forceinline__ Box block_box(const StepArgs &a, const StepLds<R> &sm, bool act, const Loc<R> &L,
-                                         int &iref) {
+__device__ __forceinline__ Box block_box_exact(const StepArgs &a, const StepLds<R> &sm, bool act, const Loc<R> &L,
+                                               BoxRef &ref) {
+  int iref = ref.i;
   constexpr int big = 0x7fffffff;
   const int h = a.nx >> 1;
   int di = L.i0 - iref;
@@ -135,7 +145,6 @@ __device__ __forceinline__ Box block_box(const StepArgs &a, const StepLds<R> &sm
   int gi = iref + m[0];
   if (gi < 0) gi += a.nx;
   else if (gi >= a.nx) gi -= a.nx;
-  iref = gi;
   b.gi = gi;
   b.bi = -m[1] - m[0] + 2;                            // corners i0 and i0 + 1
   b.j0 = m[2];
@@ -143,22 +152,93 @@ __device__ __forceinline__ Box block_box(const StepArgs &a, const StepLds<R> &sm
   b.k0 = m[4];
   b.bk = -m[5] - m[4] + 2;
   b.ok = b.bi <= a.nx && b.bi <= kMaxExtent && b.bj <= kMaxExtent && b.bi * b.bj * b.bk <= BoxCap<R>::value;
+  ref.i = b.gi;
+  ref.j = b.j0;
+  ref.k = b.k0;
   return b;
 }
 
-// A column near the block's parcels, the same in every thread: the column of
-// the block's first parcel (index i_first), or 0 when that parcel has no
-// finite longitude (any column is correct; a far one makes the first box
-// miss and the block gather instead).
-__device__ __forceinline__ int block_ref_column(const StepArgs &a, int64_t i_first, bool valid) {
-  if (!valid) return 0;
-  const double lon = a.lon[i_first];
-  if (!isfinite(lon)) return 0;
+// Bounding box of the cells of the active lanes of the block, from one-hot
+// masks of each lane's offsets from the reference cell (columns -3 .. 27,
+// rows and levels -3 .. 11; bit 0 marks an offset outside), ORed over the
+// wave and over the four waves through LDS: two reductions instead of six.
+// A block with an offset outside those ranges (the first box after a sort
+// for a block that spans a tile-row end, parcels far apart) takes the exact
+// bounds instead.  ref becomes the new box's start.  Contains the block's
+// first barrier of the evaluation (two when the exact bounds are needed).
+template <typename R>
+__device__ __forceinline__ Box block_box(const StepArgs &a, const StepLds<R> &sm, bool act, const Loc<R> &L,
+                                         BoxRef &ref) {
+  const int h = a.nx >> 1;
+  int di = L.i0 - ref.i;
+  if (di > h) di -= a.nx;
+  else if (di < -h) di += a.nx;
+  const int dj = L.j - ref.j, dk = L.k - ref.k;
+  uint32_t mi = 0, mjk = 0;
+  if (act) {
+    mi = (uint32_t)(di + 3) < 31u ? 2u << (di + 3) : 1u;
+    const uint32_t mj = (uint32_t)(dj + 3) < 15u ? 2u << (dj + 3) : 1u;
+    const uint32_t mk = (uint32_t)(dk + 3) < 15u ? 2u << (dk + 3) : 1u;
+    mjk = mj | (mk << 16);
+  }
+  mi = __ockl_wfred_or_u32(mi);
+  mjk = __ockl_wfred_or_u32(mjk);
+  int *slots = sm.red + (kBlock / 64) * 8;
+  const int w = (int)threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) reinterpret_cast<int2 *>(slots)[w] = make_int2((int)mi, (int)mjk);
+  __syncthreads();
+  const int4 x = reinterpret_cast<const int4 *>(slots)[0], y = reinterpret_cast<const int4 *>(slots)[1];
+  const uint32_t MI = __builtin_amdgcn_readfirstlane((uint32_t)(x.x | x.z | y.x | y.z));
+  const uint32_t MJK = __builtin_amdgcn_readfirstlane((uint32_t)(x.y | x.w | y.y | y.w));
+  Box b;
+  b.ok = false;
+  b.gi = b.j0 = b.k0 = 0;
+  b.bi = b.bj = b.bk = 2;
+  if (MI == 0) return b;                              // no active parcel
+  const uint32_t MJ = MJK & 0xFFFFu, MK = MJK >> 16;
+  if (((MI | MJ | MK) & 1u) || a.nx > 0xFFFF || a.ny > 0xFFFF) return block_box_exact<R>(a, sm, act, L, ref);
+  const int lo_i = __builtin_ctz(MI) - 4, hi_i = 27 - __builtin_clz(MI);
+  const int lo_j = __builtin_ctz(MJ) - 4, hi_j = 27 - __builtin_clz(MJ);
+  const int lo_k = __builtin_ctz(MK) - 4, hi_k = 27 - __builtin_clz(MK);
+  int gi = ref.i + lo_i;
+  if (gi < 0) gi += a.nx;
+  else if (gi >= a.nx) gi -= a.nx;
+  b.gi = gi;
+  b.bi = hi_i - lo_i + 2;                             // corners i0 and i0 + 1
+  b.j0 = ref.j + lo_j;
+  b.bj = hi_j - lo_j + 2;
+  b.k0 = ref.k + lo_k;
+  b.bk = hi_k - lo_k + 2;
+  b.ok = b.bi <= a.nx && b.bi * b.bj * b.bk <= BoxCap<R>::value;
+  ref.i = b.gi;
+  ref.j = b.j0;
+  ref.k = b.k0;
+  return b;
+}
+
+// The reference cell of a block's first box, the same in every thread: the
+// origin of the tile (8 x 8 x 4 cells) holding the block's first parcel
+// (index i_first), or cell (0, 0, 0) when there is none or it is not
+// finite (any reference is correct; a far one sends the first box to the
+// exact bounds).  plev, lut: the level table and its lookup (LDS or global).
+__device__ __forceinline__ BoxRef block_ref(const StepArgs &a, const double *plev, const uint16_t *lut,
+                                            int64_t i_first, bool valid) {
+  BoxRef r{0, 0, 0};
+  if (!valid) return r;
+  const double lon = a.lon[i_first], lat = a.lat[i_first], p = a.p[i_first];
+  if (!finite3(lon, lat, p)) return r;
   const double lam = lon - 360.0 * floor((lon - a.lon0) * (1.0 / 360.0));
   int i0 = (int)floor((lam - a.lon0) * a.inv_dlon);
   if (i0 >= a.nx) i0 -= a.nx;
   if (i0 < 0) i0 += a.nx;
-  return __builtin_amdgcn_readfirstlane(i0);
+  const double phi = fmin(fmax(lat, a.lat0), a.lat_hi);
+  int j = (int)floor((phi - a.lat0) * a.inv_dlat);
+  j = min(max(j, 0), a.ny - 2);
+  const int k = level_index(a, plev, lut, fmin(fmax(p, a.p_top), a.p_bot));
+  r.i = __builtin_amdgcn_readfirstlane(i0 & ~7);
+  r.j = __builtin_amdgcn_readfirstlane(j & ~7);
+  r.k = __builtin_amdgcn_readfirstlane(k & ~3);
+  return r;
 }
 
 // Loads the box's points from the two time levels of L (slots l, l1; R16:
@@ -243,11 +323,11 @@ __device__ __forceinline__ void interp_box(const StepArgs &a, const StepLds<R> &
 // calls it.  Staged through LDS when the block's box fits, else gathered.
 template <int F, typename R>
 __device__ __forceinline__ void wind_block(const StepArgs &a, const StepLds<R> &sm, const uint16_t *s_lut, bool act,
-                                           double t, double lon, double lat, double p, int &iref, R out[3]) {
+                                           double t, double lon, double lat, double p, BoxRef &ref, R out[3]) {
   Loc<R> L;
   locate_xyz<R>(a, sm.plev, sm.idp, s_lut, lon, lat, p, L);
   locate_t<R>(a, t, L);
-  const Box b = block_box<R>(a, sm, act, L, iref);
+  const Box b = block_box<R>(a, sm, act, L, ref);
   if (b.ok) stage_box<F, R>(a, sm, b, L);
   __syncthreads();
   if (b.ok) {
@@ -260,12 +340,12 @@ __device__ __forceinline__ void wind_block(const StepArgs &a, const StepLds<R> &
 }
 
 // Midpoint advection of the block's active lanes (positions of the others
-// are left alone); every thread of the block calls it with the same iref.
+// are left alone); every thread of the block calls it with the same ref.
 template <int F, typename R>
 __device__ __forceinline__ void advect_block(const StepArgs &a, const StepLds<R> &sm, const uint16_t *s_lut, bool act,
-                                             double t, double &lon, double &lat, double &p, int &iref) {
+                                             double t, double &lon, double &lat, double &p, BoxRef &ref) {
   auto wind = [&](double tt, double x, double y, double z, R out[3]) {
-    wind_block<F, R>(a, sm, s_lut, act, tt, x, y, z, iref, out);
+    wind_block<F, R>(a, sm, s_lut, act, tt, x, y, z, ref, out);
   };
   double nlon, nlat, np;
   midpoint<R>(a, t, lon, lat, p, wind, nlon, nlat, np);
