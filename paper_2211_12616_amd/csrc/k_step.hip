@@ -16,14 +16,29 @@
 
 namespace mpt {
 
-// Advances parcel i (valid: the thread holds a parcel); lon, lat, p receive
+// The launch arguments re-read from the kernel-argument segment (the step
+// kernels take one StepArgs, the segment's first explicit argument, at
+// offset 0).  The pointer is opaque to the compiler, so the values loaded
+// through it are scalar loads placed where they are used, not values held
+// in scalar registers across the whole kernel (there are more of them than
+// registers, and the rest would go to VGPR lanes).
+__device__ __forceinline__ const StepArgs &reload_args() {
+  using CP = const __attribute__((address_space(4))) StepArgs *;
+  CP q = (CP)__builtin_amdgcn_kernarg_segment_ptr();
+  asm volatile("" : "+s"(q));
+  return *(const StepArgs *)q;
+}
+
+// Advances parcel i (valid: the thread holds a parcel) with the launch's
+// arguments (reload_args); lon, lat, p receive
 // its final position.  Every thread of the block calls it and runs the same
 // steps: the advection's winds are staged for the whole block
 // (mpt_stage.h), with barriers inside.
 template <int F, typename R, bool P>
-__device__ __forceinline__ void step_parcel(const StepArgs &a, const StepLds<R> &sm, const uint16_t *s_lut,
+__device__ __forceinline__ void step_parcel(const StepLds<R> &sm, const uint16_t *s_lut,
                                             int64_t i, bool valid, uint32_t step0, BoxRef ref, double &lon,
                                             double &lat, double &p) {
+  const StepArgs &a = reload_args();
   lon = lat = p = 0.0;
   bool live = false;
   uint32_t id = 0;
@@ -46,7 +61,9 @@ __device__ __forceinline__ void step_parcel(const StepArgs &a, const StepLds<R> 
     }
   }
   bool moved = false;
-  for (int s = 0; s < a.nsteps; ++s) {
+  const int nsteps = a.nsteps;
+  for (int s = 0; s < nsteps; ++s) {
+    const StepArgs &a = reload_args();
     const uint32_t step = step0 + (uint32_t)s;
     const bool act = live && (int64_t)step >= rel && finite3(lon, lat, p);
     moved = moved || act;
@@ -70,13 +87,14 @@ __device__ __forceinline__ void step_parcel(const StepArgs &a, const StepLds<R> 
     }
   }
   if (!moved) return;
-  a.lon[i] = lon;
-  a.lat[i] = lat;
-  a.p[i] = p;
+  const StepArgs &b = reload_args();
+  b.lon[i] = lon;
+  b.lat[i] = lat;
+  b.p[i] = p;
   if (do_meso) {
-    static_cast<R *>(a.up)[i] = up;
-    static_cast<R *>(a.vp)[i] = vp;
-    static_cast<R *>(a.wp)[i] = wp;
+    static_cast<R *>(b.up)[i] = up;
+    static_cast<R *>(b.vp)[i] = vp;
+    static_cast<R *>(b.wp)[i] = wp;
   }
 }
 
@@ -151,8 +169,9 @@ __device__ __forceinline__ void step_body(const StepArgs &a) {
       const int64_t i = valid ? (int64_t)a.index[j] : 0;
       const int64_t j0 = c * kBlock;
       const BoxRef ref = block_ref(a, sm.plev, s_lut, j0 < cnt ? (int64_t)a.index[j0] : 0, j0 < cnt);
-      step_parcel<F, R, P>(a, sm, s_lut, i, valid, step0, ref, lon, lat, p);
-      if (a.sk) leave_sort_key(a, sm.plev, s_lut, i, valid, lon, lat, p);   // uniform
+      step_parcel<F, R, P>(sm, s_lut, i, valid, step0, ref, lon, lat, p);
+      const StepArgs &b = reload_args();
+      if (b.sk) leave_sort_key(b, sm.plev, s_lut, i, valid, lon, lat, p);   // uniform
     }
   } else if constexpr (M == kModeBlock) {
     const int lb = logical_block((int)blockIdx.x, a.per_xcd);
@@ -161,8 +180,9 @@ __device__ __forceinline__ void step_body(const StepArgs &a) {
     double lon, lat, p;
     const bool valid = i < a.n;
     const BoxRef ref = block_ref(a, sm.plev, s_lut, (int64_t)lb * kBlock, true);
-    step_parcel<F, R, P>(a, sm, s_lut, i, valid, step0, ref, lon, lat, p);
-    if (a.sk) leave_sort_key(a, sm.plev, s_lut, i, valid, lon, lat, p);     // uniform
+    step_parcel<F, R, P>(sm, s_lut, i, valid, step0, ref, lon, lat, p);
+    const StepArgs &b = reload_args();
+    if (b.sk) leave_sort_key(b, sm.plev, s_lut, i, valid, lon, lat, p);     // uniform
   } else {
     // persistent: XCD x owns an even share of the chunks of the prefix and
     // its blocks stride through that share
@@ -175,7 +195,7 @@ __device__ __forceinline__ void step_body(const StepArgs &a) {
       const int64_t i = c * kBlock + threadIdx.x;
       double lon, lat, p;
       const BoxRef ref = block_ref(a, sm.plev, s_lut, c * kBlock, true);
-      step_parcel<F, R, P>(a, sm, s_lut, i, i < bound, step0, ref, lon, lat, p);
+      step_parcel<F, R, P>(sm, s_lut, i, i < bound, step0, ref, lon, lat, p);
     }
   }
 }
