@@ -62,24 +62,27 @@ __device__ __forceinline__ void step_parcel(const StepLds<R> &sm, const uint16_t
   }
   bool moved = false;
   const int nsteps = a.nsteps;
+  TimeTable tt;
   for (int s = 0; s < nsteps; ++s) {
     const StepArgs &a = reload_args();
     const uint32_t step = step0 + (uint32_t)s;
+    const int e = 2 * (s % kTimeTableSteps);
+    if (e == 0) tt = time_table(a, step);            // uniform
+    const TimeLoc T0 = time_at(tt, e), T1 = time_at(tt, e + 1);
     const bool act = live && (int64_t)step >= rel && finite3(lon, lat, p);
     moved = moved || act;
-    const double t = a.t_start + (double)step * a.dt;
     if (a.flags & kAdvect) {
-      advect_block<F, R>(a, sm, s_lut, act, t, lon, lat, p, ref);
+      advect_block<F, R>(a, sm, s_lut, act, T0, T1, lon, lat, p, ref);
       if (act) position(a, lon, lat, p);
     }
     if (act && (a.flags & (kTurb | kMeso))) {
       if (a.flags & kTurb) turb<R>(a, id, step, lon, lat, p);
-      if (do_meso) meso<F, R>(a, sm.plev, sm.idp, s_lut, id, step, t + 0.5 * a.dt, lon, lat, p, up, vp, wp);
+      if (do_meso) meso<F, R>(a, sm.plev, sm.idp, s_lut, id, step, T1, lon, lat, p, up, vp, wp);
       position(a, lon, lat, p);
     }
     if constexpr (P) {
       if (act && (a.flags & (kConv | kSedi))) {
-        const double t_mid = t + 0.5 * a.dt;
+        const double t_mid = a.t_start + (double)step * a.dt + 0.5 * a.dt;
         if (a.flags & kConv) convection<F, R>(a, sm.plev, sm.idp, s_lut, id, step, t_mid, lon, lat, p);
         if (a.flags & kSedi) sedimentation<F, R>(a, sm.plev, sm.idp, s_lut, t_mid, lon, lat, p);
         position(a, lon, lat, p);

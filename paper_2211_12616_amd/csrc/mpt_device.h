@@ -354,16 +354,64 @@ __device__ __forceinline__ int met_level(const StepArgs &a, double t) {
   return l;
 }
 
-template <typename R>
-__device__ __forceinline__ void locate_t(const StepArgs &a, double t, Loc<R> &L) {
+// The time part of a location: storage slots of the level pair, absolute
+// index of the earlier level, weight of the later one.
+struct TimeLoc {
+  int l, l1, la;
+  double ft;
+};
+
+__device__ __forceinline__ TimeLoc time_loc(const StepArgs &a, double t) {
+  TimeLoc T;
   const int l = met_level(a, t);
-  L.la = l;
+  T.la = l;
   int s0 = a.slot_first + (l - a.lev_first);
   if (s0 >= a.nt) s0 -= a.nt;
-  const int s1 = s0 + 1 == a.nt ? 0 : s0 + 1;
-  L.l = s0;
-  L.l1 = s1;
-  L.ft = (R)((t - (a.t_met0 + (double)l * a.dt_met)) * a.inv_dt_met);
+  T.l = s0;
+  T.l1 = s0 + 1 == a.nt ? 0 : s0 + 1;
+  T.ft = (t - (a.t_met0 + (double)l * a.dt_met)) * a.inv_dt_met;
+  return T;
+}
+
+template <typename R>
+__device__ __forceinline__ void set_time(const TimeLoc &T, Loc<R> &L) {
+  L.la = T.la;
+  L.l = T.l;
+  L.l1 = T.l1;
+  L.ft = (R)T.ft;
+}
+
+template <typename R>
+__device__ __forceinline__ void locate_t(const StepArgs &a, double t, Loc<R> &L) {
+  set_time(time_loc(a, t), L);
+}
+
+// Time locations of a run of steps held across the lanes of a wave: lane e
+// has that of step step_base + e / 2 at its start (e even) or at its
+// midpoint, start + dt/2 (e odd).  time_at reads entry e (uniform) back into
+// scalar registers; 32 steps per table.
+constexpr int kTimeTableSteps = 32;
+struct TimeTable {
+  TimeLoc v;
+};
+
+__device__ __forceinline__ TimeTable time_table(const StepArgs &a, uint32_t step_base) {
+  const int e = (int)(threadIdx.x & 63);
+  double t = a.t_start + (double)(step_base + (uint32_t)(e >> 1)) * a.dt;
+  if (e & 1) t = t + 0.5 * a.dt;
+  return TimeTable{time_loc(a, t)};
+}
+
+__device__ __forceinline__ TimeLoc time_at(const TimeTable &tt, int e) {
+  TimeLoc T;
+  T.l = __builtin_amdgcn_readlane(tt.v.l, e);
+  T.l1 = __builtin_amdgcn_readlane(tt.v.l1, e);
+  T.la = __builtin_amdgcn_readlane(tt.v.la, e);
+  const uint64_t bits = __double_as_longlong(tt.v.ft);
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)bits, e);
+  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(bits >> 32), e);
+  T.ft = __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+  return T;
 }
 
 template <typename R>
@@ -563,13 +611,14 @@ __device__ __forceinline__ R cos_floor(const StepArgs &a, double lat) {
 
 // Explicit midpoint: x_mid = x + dt/2 f(x, t); x' = x + dt f(x_mid, t + dt/2),
 // f = (u / (R cos lat), v / R, omega) in degrees and hPa per second.  The
-// wind at a point and time comes from `wind(t, lon, lat, p, out)`; the new
-// position goes to (nlon, nlat, np).
+// wind at a point comes from `wind(h, lon, lat, p, out)`, at the step's time
+// t (h = 0) or at t + dt/2 (h = 1); the new position goes to (nlon, nlat,
+// np).
 template <typename R, typename Wind>
-__device__ __forceinline__ void midpoint(const StepArgs &a, double t, double lon, double lat, double p,
-                                         Wind &&wind, double &nlon, double &nlat, double &np) {
+__device__ __forceinline__ void midpoint(const StepArgs &a, double lon, double lat, double p, Wind &&wind,
+                                         double &nlon, double &nlat, double &np) {
   R w0[3], w1[3];
-  wind(t, lon, lat, p, w0);
+  wind(0, lon, lat, p, w0);
   const R hdt = (R)(0.5 * a.dt);
   const R kdeg = (R)kDeg;
   const R d0lon = w0[0] * kdeg * Math<R>::rcp(cos_floor<R>(a, lat));
@@ -577,7 +626,7 @@ __device__ __forceinline__ void midpoint(const StepArgs &a, double t, double lon
   const double lonm = lon + (double)(hdt * d0lon);
   const double latm = lat + (double)(hdt * d0lat);
   const double pm = p + (double)(hdt * w0[2]);
-  wind(t + 0.5 * a.dt, lonm, latm, pm, w1);
+  wind(1, lonm, latm, pm, w1);
   const R fdt = (R)a.dt;
   const R d1lon = w1[0] * kdeg * Math<R>::rcp(cos_floor<R>(a, latm));
   const R d1lat = w1[1] * kdeg;
@@ -591,16 +640,16 @@ template <int F, typename R>
 __device__ __forceinline__ void advect(const StepArgs &a, const double *s_plev, const double *s_idp,
                                        const uint16_t *s_lut, double t, double &lon, double &lat,
                                        double &p) {
-  auto wind = [&](double tt, double x, double y, double z, R out[3]) {
+  auto wind = [&](int h, double x, double y, double z, R out[3]) {
     Cell16<F> c;
     Loc<R> L;
     __builtin_amdgcn_s_setprio(2);   // locate and gather at raised priority
     locate_xyz<R>(a, s_plev, s_idp, s_lut, x, y, z, L);
-    locate_t<R>(a, tt, L);
+    locate_t<R>(a, h ? t + 0.5 * a.dt : t, L);
     load_cell<F, R>(a, L, c);
     interp_cell<F, R>(a, c, L, out);
   };
-  midpoint<R>(a, t, lon, lat, p, wind, lon, lat, p);
+  midpoint<R>(a, lon, lat, p, wind, lon, lat, p);
 }
 
 // Reflect over the poles, wrap lon to [0, 360), clamp p.  Equal to
@@ -661,11 +710,11 @@ __device__ __forceinline__ void meso_sigma(const StepArgs &a, const double *s_pl
 // read from the per-cell table of that pair (one record).
 template <typename R>
 __device__ __forceinline__ void meso_sigma_table(const StepArgs &a, const double *s_plev,
-                                                 const double *s_idp, const uint16_t *s_lut, double t_mid,
+                                                 const double *s_idp, const uint16_t *s_lut, const TimeLoc &T,
                                                  double lon, double lat, double p, R sg[3]) {
   Loc<R> L;
   locate_xyz<R>(a, s_plev, s_idp, s_lut, lon, lat, p, L);
-  locate_t<R>(a, t_mid, L);
+  set_time(T, L);
   const int off = (L.k * a.ny + L.j) * a.nx + L.i0;            // < 2^31: nx*ny*nz is
   if constexpr (sizeof(R) == 8) {
     const double2 *t = reinterpret_cast<const double2 *>(a.sig) + (size_t)L.l * (size_t)a.level_elems * 2;
@@ -697,14 +746,14 @@ __device__ __forceinline__ void meso_apply(const StepArgs &a, const R sg[3], con
 }
 
 // AR(1) sub-grid wind from the spread of the 16 values of the current cell
-// at the time-level pair of the step's midpoint time (from the per-cell
-// table), then displacement.
+// at the time-level pair of the step's midpoint time (T_mid, from the
+// per-cell table), then displacement.
 template <int F, typename R>
 __device__ __forceinline__ void meso(const StepArgs &a, const double *s_plev, const double *s_idp,
-                                     const uint16_t *s_lut, uint32_t id, uint32_t step, double t_mid,
+                                     const uint16_t *s_lut, uint32_t id, uint32_t step, const TimeLoc &T_mid,
                                      double &lon, double &lat, double &p, R &up, R &vp, R &wp) {
   R sg[3];
-  meso_sigma_table<R>(a, s_plev, s_idp, s_lut, t_mid, lon, lat, p, sg);
+  meso_sigma_table<R>(a, s_plev, s_idp, s_lut, T_mid, lon, lat, p, sg);
   R xi[3];
   normals3<R>(a.seed, id, step, 1u, xi);
   meso_apply<R>(a, sg, xi, lon, lat, p, up, vp, wp);

@@ -319,14 +319,16 @@ __device__ __forceinline__ void interp_box(const StepArgs &a, const StepLds<R> &
   interp_spatial<R>(cv, L, out);
 }
 
-// Wind at (lon, lat, p, t) for the active lanes; every thread of the block
-// calls it.  Staged through LDS when the block's box fits, else gathered.
+// Wind at (lon, lat, p) and the time located by T for the active lanes;
+// every thread of the block calls it.  Staged through LDS when the block's
+// box fits, else gathered.
 template <int F, typename R>
 __device__ __forceinline__ void wind_block(const StepArgs &a, const StepLds<R> &sm, const uint16_t *s_lut, bool act,
-                                           double t, double lon, double lat, double p, BoxRef &ref, R out[3]) {
+                                           const TimeLoc &T, double lon, double lat, double p, BoxRef &ref,
+                                           R out[3]) {
   Loc<R> L;
   locate_xyz<R>(a, sm.plev, sm.idp, s_lut, lon, lat, p, L);
-  locate_t<R>(a, t, L);
+  set_time(T, L);
   const Box b = block_box<R>(a, sm, act, L, ref);
   if (b.ok) stage_box<F, R>(a, sm, b, L);
   __syncthreads();
@@ -340,15 +342,17 @@ __device__ __forceinline__ void wind_block(const StepArgs &a, const StepLds<R> &
 }
 
 // Midpoint advection of the block's active lanes (positions of the others
-// are left alone); every thread of the block calls it with the same ref.
+// are left alone) with the time locations of the step's start (T0) and
+// midpoint (T1); every thread of the block calls it with the same ref.
 template <int F, typename R>
 __device__ __forceinline__ void advect_block(const StepArgs &a, const StepLds<R> &sm, const uint16_t *s_lut, bool act,
-                                             double t, double &lon, double &lat, double &p, BoxRef &ref) {
-  auto wind = [&](double tt, double x, double y, double z, R out[3]) {
-    wind_block<F, R>(a, sm, s_lut, act, tt, x, y, z, ref, out);
+                                             const TimeLoc &T0, const TimeLoc &T1, double &lon, double &lat,
+                                             double &p, BoxRef &ref) {
+  auto wind = [&](int h, double x, double y, double z, R out[3]) {
+    wind_block<F, R>(a, sm, s_lut, act, h ? T1 : T0, x, y, z, ref, out);
   };
   double nlon, nlat, np;
-  midpoint<R>(a, t, lon, lat, p, wind, nlon, nlat, np);
+  midpoint<R>(a, lon, lat, p, wind, nlon, nlat, np);
   if (act) {
     lon = nlon;
     lat = nlat;
