@@ -390,12 +390,27 @@ __device__ __forceinline__ void pack_ktile(const float (&g)[27], const float (&i
   }
 }
 
-__device__ __forceinline__ void store_ktile(const float (&g)[27], const float (&inv)[3],
-                                            const float *norm, uint16_t *dst) {
+// Stencil rows in global memory, chunk-major: the 16-byte chunk c (inputs
+// 8c .. 8c + 7 in the order above) of row r is at X + (c * ldc + r) * 8, so
+// that a wave's stores of one chunk of 64 consecutive rows are contiguous.
+__device__ __forceinline__ uint16_t *x_chunk(uint16_t *X, int64_t ldc, int c, int64_t r) {
+  return X + ((int64_t)c * ldc + r) * 8;
+}
+__device__ __forceinline__ const uint16_t *x_chunk(const uint16_t *X, int64_t ldc, int c, int64_t r) {
+  return X + ((int64_t)c * ldc + r) * 8;
+}
+
+// K tile sc of row r: chunks 4 sc .. 4 sc + 3.  The chunk bases are
+// uniform and the row's byte offset (r < 2^28) is shared by the four
+// stores.
+__device__ __forceinline__ void store_ktile(const float (&g)[27], const float (&inv)[3], const float *norm,
+                                            uint16_t *X, int64_t ldc, int sc, int64_t r) {
   bf16x8 t[4];
   pack_ktile(g, inv, norm, t);
+  const size_t roff = (size_t)((uint32_t)r * 16u);
 #pragma unroll
-  for (int c8 = 0; c8 < 4; ++c8) *reinterpret_cast<bf16x8 *>(dst + 8 * c8) = t[c8];
+  for (int c8 = 0; c8 < 4; ++c8)
+    *reinterpret_cast<bf16x8 *>(reinterpret_cast<char *>(x_chunk(X, ldc, 4 * sc + c8, 0)) + roff) = t[c8];
 }
 
 // The inference LDS image of the forward weights wt: layer 1 with K in the
@@ -424,10 +439,11 @@ __global__ void k_surr_pack_inf(const uint16_t *wt, uint16_t *wi) {
   wi[e] = v;
 }
 
-// Persistent over groups of 64 parcels: X rows (bf16, normalized, 96 wide)
-// -> Y[row * ldy + q] = de-normalized (east km, north km, dp hPa).
+// Persistent over groups of 64 parcels: X rows (bf16, normalized, 96 wide,
+// chunk-major with ldc rows per chunk) -> Y[row * ldy + q] = de-normalized
+// (east km, north km, dp hPa).
 __global__ __launch_bounds__(kMlpThreads) void k_surr_mlp(const SurrW W, const uint16_t *X, int64_t n,
-                                                          float *Y, int ldy) {
+                                                          int64_t ldc, float *Y, int ldy) {
   __shared__ __attribute__((aligned(16))) uint16_t sw[kWiSize];
   __shared__ __attribute__((aligned(16))) float sb[3 * kSurrHid + kSurrOutPad + 12];
   uint16_t *sw1 = sw, *sw2 = sw1 + kSurrHid * kW1Ld, *sw3 = sw2 + kSurrHid * kWLd, *sw4 = sw3 + kSurrHid * kWLd;
@@ -457,7 +473,7 @@ __global__ __launch_bounds__(kMlpThreads) void k_surr_mlp(const SurrW W, const u
       const int64_t row = grp * 64 + 16 * t + col;
 #pragma unroll
       for (int kt = 0; kt < kSurrInPad / 32; ++kt)
-        x[t][kt] = row < n ? frag8(X + row * kSurrInPad + 32 * kt + 8 * g) : frag8_zero();
+        x[t][kt] = row < n ? frag8(x_chunk(X, ldc, 4 * kt + g, row)) : frag8_zero();
     }
     bf16x8 h1[4][4], h2[4][4];
     mlp_layer<kSurrInPad / 32>(sw1, kW1Ld, sb, x, h1);
@@ -486,9 +502,9 @@ __global__ __launch_bounds__(kMlpThreads) void k_surr_mlp(const SurrW W, const u
 }
 
 // Raw inputs (FP32, 81 per row, input index order) -> normalized bf16 rows
-// of 96 in the MLP's input order (see store_ktile).
+// of 96 in the MLP's input order, chunk-major (see store_ktile).
 __global__ __launch_bounds__(256) void k_surr_xnorm(const SurrW W, const float *x, int64_t n,
-                                                    uint16_t *X) {
+                                                    uint16_t *X, int64_t ldc) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   float inv[3];
@@ -500,7 +516,7 @@ __global__ __launch_bounds__(256) void k_surr_xnorm(const SurrW W, const float *
     float g[27];
 #pragma unroll
     for (int j = 0; j < 27; ++j) g[j] = xr[(j % 3) * 27 + sc * 9 + j / 3];
-    store_ktile(g, inv, W.norm, X + i * kSurrInPad + 32 * sc);
+    store_ktile(g, inv, W.norm, X, ldc, sc, i);
   }
 }
 
@@ -681,28 +697,25 @@ __global__ __launch_bounds__(256) void k_surr_tfield(const StepArgs a, double t,
 }
 
 // Stencil inputs of parcels i0 .. i0 + cnt - 1 at the block's start time,
-// normalized, as bf16 rows of 96 in the MLP's input order; a parcel with a
-// non-finite position gets a zero row.  The block's 256 parcels (sorted by
-// tile) read their 4 x 4 x 4 stencil points from an LDS box: the bounding
-// box of their cells (mpt_stage.h) widened by one point below and two
-// above in each direction (rows and levels clamped to the grid), loaded
-// from the field at the block's start time with coalesced loads; a box that
-// does not fit makes the block read the points from global memory.  Rows
-// are staged in LDS and the block's 256 consecutive rows leave in one
-// coalesced copy.
-constexpr int kRowLd = kSurrInPad / 8 + 1;      // 16-byte units per staged row (padded)
+// normalized, as bf16 rows of 96 in the MLP's input order, chunk-major with
+// ldc rows per chunk (x_chunk); a parcel with a non-finite position gets a
+// zero row.  The block's 256 parcels (sorted by tile) read their 4 x 4 x 4
+// stencil points from an LDS box: the bounding box of their cells
+// (mpt_stage.h) widened by one point below and two above in each direction
+// (rows and levels clamped to the grid), loaded from the field at the
+// block's start time with coalesced loads; a box that does not fit makes
+// the block read the points from global memory.  Each lane stores its own
+// row; a wave's store of one chunk covers 64 consecutive rows.
 constexpr int kSurrBoxCap = 1536;               // grid points of the stencil box
 
 __global__ __launch_bounds__(256) void k_surr_x(const StepArgs a, const SurrW W, const float4 *F,
-                                                int64_t i0, int64_t cnt, uint16_t *X) {
-  __shared__ bf16x8 srow[256 * kRowLd];
+                                                int64_t i0, int64_t cnt, uint16_t *X, int64_t ldc) {
   __shared__ float bu[kSurrBoxCap], bv[kSurrBoxCap], bw[kSurrBoxCap];
   __shared__ __attribute__((aligned(16))) int red[kRedInts];
   const int lb = logical_block((int)blockIdx.x, a.per_xcd);
   if (lb >= a.nblk) return;                       // uniform over the block
   const int64_t r0 = (int64_t)lb * 256;
   const int64_t r = r0 + threadIdx.x;
-  bf16x8 *mine = srow + threadIdx.x * kRowLd;
   bool valid = false;
   double lon = 0.0, lat = 0.0, p = 0.0;
   if (r < cnt) {
@@ -741,16 +754,12 @@ __global__ __launch_bounds__(256) void k_surr_x(const StepArgs a, const SurrW W,
     }
   }
   __syncthreads();
+  if (r >= cnt) return;                           // no barrier follows
   if (valid) {
     float inv[3];
 #pragma unroll
     for (int v = 0; v < 3; ++v) inv[v] = 1.0f / W.norm[3 + v];
-    auto sink = [&](int sc, const float (&g)[27]) {
-      bf16x8 t[4];
-      pack_ktile(g, inv, W.norm, t);
-#pragma unroll
-      for (int c8 = 0; c8 < 4; ++c8) mine[4 * sc + c8] = t[c8];
-    };
+    auto sink = [&](int sc, const float (&g)[27]) { store_ktile(g, inv, W.norm, X, ldc, sc, r); };
     if (staged) {
       auto src = [&](int k, int j, int ii, float (&v)[3]) {
         int li = ii - gs;
@@ -762,7 +771,11 @@ __global__ __launch_bounds__(256) void k_surr_x(const StepArgs a, const SurrW W,
       };
       stencil81(a, L, src, sink);
     } else {
+      // blocks whose box does not fit (rare): the loads stay in program
+      // order (the empty asm), so the fallback does not hoist a whole
+      // level's loads and set the register budget of the kernel
       auto src = [&](int k, int j, int ii, float (&v)[3]) {
+        asm volatile("" ::: "memory");
         const float4 f = F[((int64_t)k * a.ny + j) * a.nx + ii];
         v[0] = f.x;
         v[1] = f.y;
@@ -772,13 +785,9 @@ __global__ __launch_bounds__(256) void k_surr_x(const StepArgs a, const SurrW W,
     }
   } else {
 #pragma unroll
-    for (int c = 0; c < kSurrInPad / 8; ++c) mine[c] = frag8_zero();
-  }
-  __syncthreads();
-  const int64_t rows = cnt - r0 < 256 ? cnt - r0 : 256;
-  for (int q = threadIdx.x; q < rows * (kSurrInPad / 8); q += 256) {
-    const int row = q / (kSurrInPad / 8), c = q % (kSurrInPad / 8);
-    *reinterpret_cast<bf16x8 *>(X + (r0 + row) * kSurrInPad + 8 * c) = srow[row * kRowLd + c];
+    for (int c = 0; c < kSurrInPad / 8; ++c)
+      *reinterpret_cast<bf16x8 *>(reinterpret_cast<char *>(x_chunk(X, ldc, c, 0)) + (size_t)((uint32_t)r * 16u)) =
+          frag8_zero();
   }
 }
 
@@ -973,18 +982,19 @@ hipError_t launch_surr_forward(const SurrW &W, const float *x, int64_t n, uint16
   for (int64_t i0 = 0; i0 < n; i0 += chunk) {
     const int64_t cnt = n - i0 < chunk ? n - i0 : chunk;
     hipLaunchKernelGGL(k_surr_xnorm, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, W,
-                       x + i0 * kSurrIn, cnt, X);
-    const hipError_t e = launch_surr_mlp(W, X, cnt, y + i0 * kSurrOut, kSurrOut, s);
+                       x + i0 * kSurrIn, cnt, X, chunk);
+    const hipError_t e = launch_surr_mlp(W, X, cnt, chunk, y + i0 * kSurrOut, kSurrOut, s);
     if (e != hipSuccess) return e;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_surr_mlp(const SurrW &W, const uint16_t *X, int64_t n, float *Y, int ldy, hipStream_t s) {
+hipError_t launch_surr_mlp(const SurrW &W, const uint16_t *X, int64_t n, int64_t ldc, float *Y, int ldy,
+                           hipStream_t s) {
   const int64_t groups = (n + 63) / 64;
   const int64_t want = (groups + kMlpThreads / 64 - 1) / (kMlpThreads / 64);
   const unsigned nb = (unsigned)(want < kMlpBlocks ? want : kMlpBlocks);
-  hipLaunchKernelGGL(k_surr_mlp, dim3(nb), dim3(kMlpThreads), 0, s, W, X, n, Y, ldy);
+  hipLaunchKernelGGL(k_surr_mlp, dim3(nb), dim3(kMlpThreads), 0, s, W, X, n, ldc, Y, ldy);
   return hipGetLastError();
 }
 
@@ -1003,9 +1013,10 @@ hipError_t launch_surr_tfield(const StepArgs &a, double t, float4 *F, hipStream_
 }
 
 hipError_t launch_surr_x(const StepArgs &a, const SurrW &W, const float4 *F, int64_t i0, int64_t cnt,
-                         uint16_t *X, hipStream_t s) {
+                         uint16_t *X, int64_t ldc, hipStream_t s) {
+  if (cnt > ldc) return hipErrorInvalidValue;
   const StepArgs c = chunk_args(a, cnt);
-  hipLaunchKernelGGL(k_surr_x, dim3((unsigned)(c.per_xcd * kXcds)), dim3(256), 0, s, c, W, F, i0, cnt, X);
+  hipLaunchKernelGGL(k_surr_x, dim3((unsigned)(c.per_xcd * kXcds)), dim3(256), 0, s, c, W, F, i0, cnt, X, ldc);
   return hipGetLastError();
 }
 

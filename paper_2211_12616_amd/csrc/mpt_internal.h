@@ -130,17 +130,21 @@ hipError_t launch_surr_stats(const float *x, const float *y, int64_t n, double *
 hipError_t launch_surr_init(float *params, uint64_t seed, hipStream_t s);
 hipError_t launch_surr_pack(const float *params, uint16_t *wt, uint16_t *wb, hipStream_t s);
 hipError_t launch_surr_pack_inf(const uint16_t *wt, uint16_t *wi, hipStream_t s);
-// raw inputs -> outputs, in chunks of at most `chunk` rows through X (bf16 [chunk][96])
+// Stencil rows X (normalized bf16, 96 per row) are stored chunk-major: the
+// 16-byte chunk c of row r at X + (c * ldc + r) * 8, ldc >= the rows held.
+// raw inputs -> outputs, in chunks of at most `chunk` rows through X
+// (bf16 [12][chunk][8])
 hipError_t launch_surr_forward(const SurrW &W, const float *x, int64_t n, uint16_t *X, float *y,
                                int64_t chunk, hipStream_t s);
-// normalized bf16 rows X [n][96] -> Y[row * ldy + 0..2]
-hipError_t launch_surr_mlp(const SurrW &W, const uint16_t *X, int64_t n, float *Y, int ldy, hipStream_t s);
+// rows X (n rows, ldc per chunk) -> Y[row * ldy + 0..2]
+hipError_t launch_surr_mlp(const SurrW &W, const uint16_t *X, int64_t n, int64_t ldc, float *Y, int ldy,
+                           hipStream_t s);
 // FP32 field interpolated to time t ([level_elems] float4)
 hipError_t launch_surr_tfield(const StepArgs &a, double t, float4 *F, hipStream_t s);
-// stencil rows of parcels i0 .. i0 + cnt - 1 at step a.step0 from the field
-// F at that step's time
+// stencil rows of parcels i0 .. i0 + cnt - 1 (cnt <= ldc) at step a.step0
+// from the field F at that step's time
 hipError_t launch_surr_x(const StepArgs &a, const SurrW &W, const float4 *F, int64_t i0, int64_t cnt,
-                         uint16_t *X, hipStream_t s);
+                         uint16_t *X, int64_t ldc, hipStream_t s);
 // consistency estimate and acceptance for parcels i0 .. i0 + cnt - 1 (i0 a
 // multiple of 64); fb_mask[i / 64] gets the wave's ballot of parcels that
 // fall back

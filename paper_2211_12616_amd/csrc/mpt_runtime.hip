@@ -60,7 +60,7 @@ struct mpt_ctx {
   double *hyb_ab;
   int hyb_nml;
   float *s_norm, *s_bias;               // loaded normalization and biases (FP32)
-  uint16_t *s_x;                        // stencil rows of one chunk (bf16 [s_chunk][96])
+  uint16_t *s_x;                        // stencil rows of one chunk (bf16 [12][s_chunk][8], chunk-major)
   float *s_y;                           // predictions of one chunk ([s_chunk][4])
   int64_t s_chunk;
   float4 *s_f;                          // FP32 field at a surrogate block's start time
@@ -1064,8 +1064,8 @@ mpt_status mpt_step_surrogate(mpt_ctx *c, mpt_particles *P, uint32_t step0, int3
       return MPT_ERR_HIP;
     for (int64_t i0 = 0; i0 < P->n; i0 += c->s_chunk) {
       const int64_t cnt = P->n - i0 < c->s_chunk ? P->n - i0 : c->s_chunk;
-      if (launch_surr_x(a, W, c->s_f, i0, cnt, c->s_x, s) != hipSuccess ||
-          launch_surr_mlp(W, c->s_x, cnt, c->s_y, 4, s) != hipSuccess ||
+      if (launch_surr_x(a, W, c->s_f, i0, cnt, c->s_x, c->s_chunk, s) != hipSuccess ||
+          launch_surr_mlp(W, c->s_x, cnt, c->s_chunk, c->s_y, 4, s) != hipSuccess ||
           launch_surr_apply(a, c->s_tau, c->s_y, i0, cnt, err_out, c->fb_mask, s) != hipSuccess)
         return MPT_ERR_HIP;
     }
