@@ -555,35 +555,6 @@ __device__ __forceinline__ void interp_cell(const StepArgs &a, const Cell16<F> &
   interp_spatial<R>(cv, L, out);
 }
 
-// Population standard deviation of the 16 values of each variable, in one
-// pass over values shifted by the first one (sum and sum of squares of
-// x - x_0; the shift bounds the cancellation by the spread of the cell).
-template <int F, typename R>
-__device__ __forceinline__ void sigma_cell(const StepArgs &a, const Cell16<F> &c, const Loc<R> &L,
-                                           R out[3]) {
-  float sc[2][2][3];
-  cell_scales<F, R>(a, L, sc);
-  R x0[3], s1[3] = {0, 0, 0}, s2[3] = {0, 0, 0};
-  Fetch<F, R>::get(c.r[0][0][0][0], sc[0][0], x0);
-#pragma unroll
-  for (int n = 1; n < 16; ++n) {
-    const int dl = n >> 3, dk = (n >> 2) & 1, dj = (n >> 1) & 1, di = n & 1;
-    R x[3];
-    Fetch<F, R>::get(c.r[dl][dk][dj][di], sc[dl][dk], x);
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      const R d = x[q] - x0[q];
-      s1[q] += d;
-      s2[q] = fma(d, d, s2[q]);
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    const R var = (s2[q] - s1[q] * s1[q] * (R)(1.0 / 16.0)) * (R)(1.0 / 16.0);
-    out[q] = Math<R>::sqrt_(var > (R)0 ? var : (R)0);
-  }
-}
-
 // cos(lat) floored at cos(89.999 deg).  The value must keep its relative
 // accuracy near the poles, where 1/cos(lat) scales the longitude increments
 // and a cosine of a rounded angle has an absolute error.  FP64: the sine of
@@ -691,23 +662,9 @@ __device__ __forceinline__ void turb(const StepArgs &a, uint32_t id, uint32_t st
   p = p + (double)dp;
 }
 
-// Spread of the 16 values of the cell holding (lon, lat, p), at the
-// time-level pair of t_mid.
-template <int F, typename R>
-__device__ __forceinline__ void meso_sigma(const StepArgs &a, const double *s_plev,
-                                           const double *s_idp, const uint16_t *s_lut, double t_mid,
-                                           double lon, double lat, double p, R sg[3]) {
-  Cell16<F> c;
-  Loc<R> L;
-  __builtin_amdgcn_s_setprio(2);   // locate and gather at raised priority
-  locate_xyz<R>(a, s_plev, s_idp, s_lut, lon, lat, p, L);
-  locate_t<R>(a, t_mid, L);
-  load_cell<F, R>(a, L, c);
-  sigma_cell<F, R>(a, c, L, sg);
-}
-
-// Spread of the cell holding (lon, lat, p) at the time-level pair of t_mid,
-// read from the per-cell table of that pair (one record).
+// Spread of the 16 values (2 time levels x 2 levels x 2 rows x 2 columns)
+// of the cell holding (lon, lat, p) at the time-level pair located by T,
+// read from the per-cell table of that pair (one record; k_cell_sigma).
 template <typename R>
 __device__ __forceinline__ void meso_sigma_table(const StepArgs &a, const double *s_plev,
                                                  const double *s_idp, const uint16_t *s_lut, const TimeLoc &T,
