@@ -234,9 +234,10 @@ mpt_status mpt_advect(mpt_ctx *ctx, const mpt_particles *particles, uint32_t ste
 mpt_status mpt_diffuse(mpt_ctx *ctx, const mpt_particles *particles, uint32_t step,
                        void *hip_stream);
 
-/* Sort parcels by grid box (the sorting modules of Sec. 6): key = 8 x 8 x 4
- * (lon x lat x level) tile of the cell holding the parcel, tiles numbered
- * lon fastest.  With scenarios, parcels not yet released at the step the
+/* Sort parcels by grid box (the sorting modules of Sec. 6): key = 8 x the
+ * 8 x 8 x 4 (lon x lat x level) tile of the cell holding the parcel (tiles
+ * numbered lon fastest) + the half-tile of 4 x 4 x 2 cells it lies in
+ * (upper half in level 4, in lat 2, in lon 1).  With scenarios, parcels not yet released at the step the
  * sort precedes go behind all tiles, grouped by their scenario's rank in
  * release order; parcels with non-finite positions go last.  Scatters the
  * whole state into the *2 set and swaps the primary and *2 pointers inside
@@ -253,7 +254,8 @@ mpt_status mpt_sort_particles(mpt_ctx *ctx, mpt_particles *particles, void *hip_
  * ends (about 40 MiB), instead of the context's workspace.  Allocates
  * nothing.  Limits: n <= MPT_NOALLOC_SORT_MAX_N (else MPT_ERR_WORKSPACE; n
  * may exceed the context's n_max) and a grid of at most
- * MPT_NOALLOC_SORT_MAX_KEYS - 65537 tiles (else MPT_ERR_UNSUPPORTED).  The
+ * (MPT_NOALLOC_SORT_MAX_KEYS - 65537) / 8 tiles (else
+ * MPT_ERR_UNSUPPORTED).  The
  * context's device must be current (else MPT_ERR_STATE).  Always runs its
  * own key pass (sort keys a step left are not used, and are dropped).
  * Every call on one device shares that array: calls that overlap on one

@@ -545,9 +545,13 @@ void orc_normals_many(uint64_t seed, int64_t n, const uint32_t *id, uint32_t ste
     for (int64_t i = 0; i < n; ++i) orc_normals3(seed, id[i], step, purpose, &out[3 * i]);
 }
 
-/* Grid-box sort key: the 8 x 8 x 4 (lon x lat x level) tile of the cell that
- * holds the position; tiles numbered with lon fastest, then lat, then level.
- * Non-finite positions get the key one past the last tile. */
+/* Grid-box sort key of the cell that holds the position: its 8 x 8 x 4
+ * (lon x lat x level) tile, tiles numbered with lon fastest, then lat, then
+ * level; then, inside the tile, which half of the tile the cell lies in
+ * along level, lat and lon (the upper half counting 4, 2 and 1), so that a
+ * tile's 8 half-tiles of 4 x 4 x 2 cells follow each other:
+ * key = 8 * tile + half-tile.  Non-finite positions get the key one past the
+ * last cell key. */
 void orc_tile_keys(const orc_met *m, int64_t n, const double *lon, const double *lat,
                    const double *p, uint32_t *out)
 {
@@ -556,12 +560,14 @@ void orc_tile_keys(const orc_met *m, int64_t n, const double *lon, const double 
     uint32_t ntz = (uint32_t)((m->nz - 1 + 3) / 4);
     for (int64_t i = 0; i < n; ++i) {
         if (!isfinite(lon[i]) || !isfinite(lat[i]) || !isfinite(p[i])) {
-            out[i] = ntx * nty * ntz;
+            out[i] = 8u * ntx * nty * ntz;
             continue;
         }
         orc_loc L;
         orc_locate(m, lon[i], lat[i], p[i], m->t_met0, &L);
-        out[i] = ((uint32_t)(L.k / 4) * nty + (uint32_t)(L.j / 8)) * ntx + (uint32_t)(L.i0 / 8);
+        uint32_t tile = ((uint32_t)(L.k / 4) * nty + (uint32_t)(L.j / 8)) * ntx + (uint32_t)(L.i0 / 8);
+        uint32_t half = 4u * (uint32_t)(L.k % 4 >= 2) + 2u * (uint32_t)(L.j % 8 >= 4) + (uint32_t)(L.i0 % 8 >= 4);
+        out[i] = 8u * tile + half;
     }
 }
 

@@ -52,7 +52,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_keys(const SortArgs a) {
   }
   uint32_t key[kSortPer];
   double pc[kSortPer];
-  int k[kSortPer];
+  int k[kSortPer], ci[kSortPer], cj[kSortPer];
 #pragma unroll
   for (int q = 0; q < kSortPer; ++q) {
     const double lam = lon[q] - 360.0 * floor((lon[q] - a.lon0) * (1.0 / 360.0));
@@ -62,7 +62,8 @@ __global__ __launch_bounds__(kBlock) void k_sort_keys(const SortArgs a) {
     const double phi = fmin(fmax(lat[q], a.lat0), a.lat_hi);
     int j = (int)floor((phi - a.lat0) * a.inv_dlat);
     j = min(max(j, 0), a.ny - 2);
-    key[q] = (uint32_t)(j >> 3) * a.ntx + (uint32_t)(i0 >> 3);     // level part added below
+    ci[q] = i0;
+    cj[q] = j;
     pc[q] = fmin(fmax(p[q], a.p_top), a.p_bot);
     int b = (int)((__log2f((float)pc[q]) - a.lut_lo) * a.lut_scale);
     b = min(max(b, 0), kLutBins - 1);
@@ -112,8 +113,8 @@ __global__ __launch_bounds__(kBlock) void k_sort_keys(const SortArgs a) {
         while (kk > 0 && a.plev[kk] < pc[q]) --kk;
       }
     }
-    key[q] += (uint32_t)(kk >> 2) * a.nty * a.ntx;
-    if (a.scen && (int64_t)step < (int64_t)rel[q]) key[q] = a.ntx * a.nty * a.ntz + (uint32_t)rk[q];
+    key[q] = cell_key(ci[q], cj[q], kk, a.ntx, a.nty);
+    if (a.scen && (int64_t)step < (int64_t)rel[q]) key[q] = a.ntx * a.nty * a.ntz * kSubKeys + (uint32_t)rk[q];
     if (!finite3(lon[q], lat[q], p[q])) key[q] = a.nkeys - 1;
     const bool valid = i_w + q * 64 + lane < a.n;
     if (!valid) key[q] = 0xFFFFFFFFu;

@@ -859,10 +859,29 @@ __device__ __forceinline__ bool finite3(double a, double b, double c) {
   return isfinite(a) && isfinite(b) && isfinite(c);
 }
 
-// ---- sort keys at the end of a launch ----------------------------------------
+// ---- sort keys ------------------------------------------------------------------
 
-// Tile key (8 x 8 x 4 cells, lon fastest) of a position, the cell found as
-// locate_xyz finds it; non-finite positions take the last key.
+// Sort key of a cell (i0, j, k): its 8 x 8 x 4 tile (tiles numbered lon
+// fastest, then lat, then level) times kSubKeys, plus the cell's sub-tile
+// inside the tile: kSubLevels halvings of the tile in lon, lat and level,
+// each contributing three bits (level, lat, lon from high to low), coarsest
+// first.  Consecutive keys then walk a tile's halves in order, so a run of
+// sorted parcels that ends one tile and starts the next covers the last
+// sub-tiles of one and the first of the other, not both tiles whole.
+constexpr int kSubLevels = 1;
+constexpr uint32_t kSubKeys = 1u << (3 * kSubLevels);
+__host__ __device__ __forceinline__ uint32_t cell_key(int i0, int j, int k, uint32_t ntx, uint32_t nty) {
+  uint32_t s = 0;
+#pragma unroll
+  for (int l = 0; l < kSubLevels; ++l) {
+    const int ib = 2 - l, kb = 1 - l;             // the bit each halving tests
+    s = (s << 3) | ((uint32_t)((k >> kb) & 1) << 2) | ((uint32_t)((j >> ib) & 1) << 1) | (uint32_t)((i0 >> ib) & 1);
+  }
+  return (((uint32_t)(k >> 2) * nty + (uint32_t)(j >> 3)) * ntx + (uint32_t)(i0 >> 3)) * kSubKeys + s;
+}
+
+// Sort key of a position (cell_key of the cell locate_xyz finds); non-finite
+// positions take the last key.
 __device__ __forceinline__ uint32_t tile_key(const StepArgs &a, const SortKeyArgs &sk, const double *s_plev,
                                              const uint16_t *s_lut, double lon, double lat, double p) {
   if (!finite3(lon, lat, p)) return sk.nkeys - 1;
@@ -874,7 +893,7 @@ __device__ __forceinline__ uint32_t tile_key(const StepArgs &a, const SortKeyArg
   int j = (int)floor((phi - a.lat0) * a.inv_dlat);
   j = min(max(j, 0), a.ny - 2);
   const int k = level_index(a, s_plev, s_lut, fmin(fmax(p, a.p_top), a.p_bot));
-  return ((uint32_t)(k >> 2) * sk.nty + (uint32_t)(j >> 3)) * sk.ntx + (uint32_t)(i0 >> 3);
+  return cell_key(i0, j, k, sk.ntx, sk.nty);
 }
 
 // Rank of each valid lane's key among the parcels of that key: runs of

@@ -193,7 +193,7 @@ Layout layout(const mpt_grid *g, const mpt_params *p, int64_t n_max) {
   L.ntx = (uint32_t)((g->nx + 7) / 8);
   L.nty = (uint32_t)((g->ny - 1 + 7) / 8);
   L.ntz = (uint32_t)((g->nz - 1 + 3) / 4);
-  L.ntiles = L.ntx * L.nty * L.ntz;
+  L.ntiles = L.ntx * L.nty * L.ntz * kSubKeys;   // cell keys: tiles x sub-tiles
   L.nkeys = L.ntiles + kMaxScen + 1;
   size_t off = 0;
   L.met = off;        off += align_up(npts * rec_bytes(g->dtype) * g->nt);

@@ -10,7 +10,7 @@
 * ``displacement`` (surrogate targets, row A15): under a uniform wind the
   8-step midpoint displacement is exact: east 8 U dt along the start
   latitude, north 8 V dt, dp 8 W dt (advection, Sec. 3.2).
-* ``tile_keys`` (the sort by grid box of Sec. 6, row A11): brute force
+* ``tile_keys`` (the sort by grid box of Sec. 6, row A11; tile then half-tile): brute force
   with the cell found by ``searchsorted`` on the level table, the tile
   numbered lon fastest, non-finite positions on the last key.
 """
@@ -202,13 +202,17 @@ def test_displacement_is_k_advection_steps(met_c1, orc_c1, rng):
 # ---- tile keys ---------------------------------------------------------------------
 
 def brute_keys(met, lon, lat, p):
+    """8 x tile + half-tile: the tile of the cell, lon fastest, then the
+    half of the tile it lies in along level (4), lat (2) and lon (1)."""
     ntx = -(-met.nx // 8)
     nty = -(-(met.ny - 1) // 8)
     ntz = -(-(met.nz - 1) // 4)
-    out = np.full(len(lon), ntx * nty * ntz, np.int64)
+    out = np.full(len(lon), 8 * ntx * nty * ntz, np.int64)
     ok = np.isfinite(lon) & np.isfinite(lat) & np.isfinite(p)
     i0, j, k, _, _, _ = cell_of(met, lon[ok], lat[ok], p[ok])
-    out[ok] = ((k // 4) * nty + j // 8) * ntx + i0 // 8
+    tile = ((k // 4) * nty + j // 8) * ntx + i0 // 8
+    half = 4 * (k - 4 * (k // 4) >= 2) + 2 * (j - 8 * (j // 8) >= 4) + (i0 - 8 * (i0 // 8) >= 4)
+    out[ok] = 8 * tile + half
     return out
 
 
@@ -237,5 +241,29 @@ def test_tile_keys_brute_force(met_c1, rng, grid):
     want = brute_keys(met, lon, lat, p)
     np.testing.assert_array_equal(got, want)
     ntiles = (-(-met.nx // 8)) * (-(-(met.ny - 1) // 8)) * (-(-(met.nz - 1) // 4))
-    assert np.all(got[660:690] == ntiles)
-    assert got[np.isfinite(lon) & np.isfinite(lat) & np.isfinite(p)].max() < ntiles
+    assert np.all(got[660:690] == 8 * ntiles)
+    assert got[np.isfinite(lon) & np.isfinite(lat) & np.isfinite(p)].max() < 8 * ntiles
+
+
+def test_tile_keys_walk_the_halves_of_a_tile(met_c1):
+    """The cell centres of one tile: keys 8t .. 8t + 7, each half-tile of
+    4 x 4 x 2 cells one key, in the order (level, lat, lon) halves."""
+    met = met_c1
+    m = oracle.Met(met)
+    ti, tj, tk = 3, 2, 1                       # a tile away from the grid edges
+    ii, jj, kk = np.meshgrid(np.arange(8), np.arange(8), np.arange(4), indexing="ij")
+    i0, j, k = 8 * ti + ii.ravel(), 8 * tj + jj.ravel(), 4 * tk + kk.ravel()
+    lon = met.lon0 + (i0 + 0.5) * met.dlon
+    lat = met.lat0 + (j + 0.5) * met.dlat
+    p = np.sqrt(np.asarray(met.plev)[k] * np.asarray(met.plev)[k + 1])
+    got = oracle.tile_keys(m, lon, lat, p).astype(np.int64)
+    ntx, nty = -(-met.nx // 8), -(-(met.ny - 1) // 8)
+    t = (tk * nty + tj) * ntx + ti
+    assert set(np.unique(got)) == set(range(8 * t, 8 * t + 8))
+    for key in range(8 * t, 8 * t + 8):
+        h = key - 8 * t
+        sel = got == key
+        assert sel.sum() == 32
+        assert np.all((ii.ravel()[sel] >= 4) == bool(h & 1))
+        assert np.all((jj.ravel()[sel] >= 4) == bool(h & 2))
+        assert np.all((kk.ravel()[sel] >= 2) == bool(h & 4))
