@@ -276,7 +276,10 @@ __device__ __forceinline__ void stage_box(const StepArgs &a, const StepLds<R> &s
     }
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-      const int q = q0 + u * kBlock;
+      // the clamped duplicate of the last point stores that point's own
+      // value again: no branch, so the compiler keeps both points' loads
+      // ahead of the first use instead of sinking the second into a branch
+      const int q = min(q0 + u * kBlock, npts - 1);
       const int k = kq[u];
       float sc0[3] = {1.0f, 1.0f, 1.0f}, sc1[3] = {1.0f, 1.0f, 1.0f};
       if constexpr (F != kF32) {
@@ -286,11 +289,9 @@ __device__ __forceinline__ void stage_box(const StepArgs &a, const StepLds<R> &s
       R v0[3], v1[3];
       Fetch<F, R>::get(r0[u], sc0, v0);
       Fetch<F, R>::get(r1[u], sc1, v1);
-      if (q < npts) {
-        sm.bu[q] = lerp(v0[0], v1[0], L.ft);
-        sm.bv[q] = lerp(v0[1], v1[1], L.ft);
-        sm.bw[q] = lerp(v0[2], v1[2], L.ft);
-      }
+      sm.bu[q] = lerp(v0[0], v1[0], L.ft);
+      sm.bv[q] = lerp(v0[1], v1[1], L.ft);
+      sm.bw[q] = lerp(v0[2], v1[2], L.ft);
     }
   }
 }
