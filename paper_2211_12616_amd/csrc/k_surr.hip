@@ -740,17 +740,29 @@ __global__ __launch_bounds__(256) void k_surr_x(const StepArgs a, const SurrW W,
   if (staged) {
     const int npts = ni * nj * nk;
     const uint32_t mi = kDivMagic.m[ni], mj = kDivMagic.m[nj];
-    for (int q = (int)threadIdx.x; q < npts; q += 256) {
-      const int rr = (int)__umulhi((uint32_t)q, mi);
-      const int ii = q - rr * ni;
-      const int kk = (int)__umulhi((uint32_t)rr, mj);
-      const int jj = rr - kk * nj;
-      int gi = gs + ii;
-      if (gi >= a.nx) gi -= a.nx;
-      const float4 v = F[((ks + kk) * a.ny + js + jj) * a.nx + gi];
-      bu[q] = v.x;
-      bv[q] = v.y;
-      bw[q] = v.z;
+    // four points per thread and pass, all loads issued before the stores;
+    // a clamped duplicate of the last point rewrites that point's own value
+    for (int q0 = (int)threadIdx.x; q0 < npts; q0 += 4 * 256) {
+      float4 v[4];
+      int qq[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int q = min(q0 + u * 256, npts - 1);
+        qq[u] = q;
+        const int rr = (int)__umulhi((uint32_t)q, mi);
+        const int ii = q - rr * ni;
+        const int kk = (int)__umulhi((uint32_t)rr, mj);
+        const int jj = rr - kk * nj;
+        int gi = gs + ii;
+        if (gi >= a.nx) gi -= a.nx;
+        v[u] = F[((ks + kk) * a.ny + js + jj) * a.nx + gi];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        bu[qq[u]] = v[u].x;
+        bv[qq[u]] = v[u].y;
+        bw[qq[u]] = v[u].z;
+      }
     }
   }
   __syncthreads();
