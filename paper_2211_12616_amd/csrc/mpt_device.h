@@ -284,9 +284,33 @@ __device__ __forceinline__ void locate_xyz(const StepArgs &a, const double *s_pl
   L.fy = (R)(y - (double)j);
 
   const double pc = fmin(fmax(p, a.p_top), a.p_bot);
-  const int k = level_index(a, s_plev, s_lut, pc);
+  // level_index with the table's guess k0 and the levels and inverse
+  // spacings around it read together (one LDS round trip after the
+  // table's), which settles the usual one step up without another; further
+  // steps (rare) walk on as level_index does.  Same k.
+  int b = (int)((__log2f((float)pc) - a.lut_lo) * a.lut_scale);
+  b = min(max(b, 0), kLutBins - 1);
+  const int k0 = s_lut[b];
+  const int k1 = min(k0 + 1, a.nz - 1);
+  const double p0 = s_plev[k0], p1 = s_plev[k1], d0 = s_idp[k0], d1 = s_idp[k1];
+  int k = k0;
+  double pk = p0, dk = d0;
+  if (k0 < a.nz - 2 && p1 >= pc) {
+    k = k1;
+    pk = p1;
+    dk = d1;
+    if (k < a.nz - 2 && s_plev[k + 1] >= pc) {
+      while (k < a.nz - 2 && s_plev[k + 1] >= pc) ++k;
+      pk = s_plev[k];
+      dk = s_idp[k];
+    }
+  } else if (k0 > 0 && p0 < pc) {
+    while (k > 0 && s_plev[k] < pc) --k;
+    pk = s_plev[k];
+    dk = s_idp[k];
+  }
   L.k = k;
-  L.fz = (R)((s_plev[k] - pc) * s_idp[k]);
+  L.fz = (R)((pk - pc) * dk);
 }
 
 // locate_xyz for tables read from global memory (kernels that visit each
