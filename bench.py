@@ -33,7 +33,7 @@ FP32_PEAK_TFLOPS = 157.3
 # interpolations of three winds, the spread of 16 values per wind, two
 # Philox blocks with Box-Muller, cos(lat) three times -- counted at 1,000
 # and used for every arithmetic form.  The kernels execute fewer (the F64
-# form 817 FP64 FLOP per parcel-step by counter): a grid point's time
+# form 815 FP64 FLOP per parcel-step by counter): a grid point's time
 # interpolation is shared by the parcels of a block and the spreads are
 # tabulated per cell, so `achieved` credits work the kernel avoids, as an
 # algorithmic roofline does; the executed rate is in the profiles.
@@ -42,7 +42,7 @@ FLOP_PER_PS = 1000.0
 # (KiB x 1024; a 1 GiB copy reads FETCH_SIZE = 512 MiB and WRITE_SIZE =
 # 1 GiB) from rocprofv3 --pmc runs of this workload on the current step
 # kernels (profiles/k_step_<form>_1e8_0p3deg.md); None where not measured.
-TRAFFIC_BYTES_PER_LAUNCH = {"f64": 15.810e9, "f32": 12.895e9, "bf16": 11.328e9, "f16": 11.328e9}
+TRAFFIC_BYTES_PER_LAUNCH = {"f64": 16.179e9, "f32": 13.252e9, "bf16": 11.683e9, "f16": 11.683e9}
 TRAFFIC_STEPS_PER_LAUNCH = 10
 # The convection / sedimentation kernel, F64 form, same workload
 # (profiles/k_step_phys_1e8_0p3deg.md): FP64 FLOP per parcel-step and HBM
