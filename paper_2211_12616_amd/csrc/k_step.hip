@@ -114,13 +114,21 @@ __device__ __forceinline__ int64_t active_bound(const StepArgs &a, uint32_t last
 }
 
 // Minimum waves per SIMD the compiler must allow (register budget) for the
-// FP64 and FP32 step kernels.
+// FP64 and FP32-arithmetic step kernels: 3 for FP64; in the XCD-block shape
+// 5 for the F32 and BF16 storage forms (their spills at 96 registers are a
+// few dwords and the extra wave hides more of the staging), 4 for FP16
+// storage (at 5 it spills 72 bytes per lane and runs slower); 4 for the
+// persistent and index-list shapes and the physics kernels.
 #ifndef MPT_WAVES_F64
 #define MPT_WAVES_F64 3
 #endif
 #ifndef MPT_WAVES_F32
 #define MPT_WAVES_F32 4
 #endif
+template <int M, int F>
+struct StepWaves {
+  static constexpr int value = (M == 0 && F != kF16) ? 5 : MPT_WAVES_F32;
+};
 
 enum : int { kModeBlock = 0, kModePersistent = 1, kModeIndex = 2 };
 
@@ -210,7 +218,7 @@ void k_step_f64(const StepArgs a) {
 }
 
 template <int M, int F>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MPT_WAVES_F32)))
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(StepWaves<M, F>::value)))
 void k_step_f32(const StepArgs a) {
   step_body<M, F, float, false>(a);
 }

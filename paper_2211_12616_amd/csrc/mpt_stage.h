@@ -32,7 +32,7 @@ namespace mpt {
 // Capacity of the staged box in grid points: 3 x 4 B (FP32 values) or
 // 3 x 8 B (FP64) per point.
 template <typename R> struct BoxCap;
-template <> struct BoxCap<float> { static constexpr int value = 2048; };
+template <> struct BoxCap<float> { static constexpr int value = 1280; };
 template <> struct BoxCap<double> { static constexpr int value = 1536; };
 
 __host__ __device__ constexpr size_t round16(size_t x) { return (x + 15) & ~(size_t)15; }

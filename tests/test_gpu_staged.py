@@ -21,7 +21,7 @@ from oracle import encode
 pytestmark = pytest.mark.gpu
 
 # capacity of the staged box in grid points: FP32-arithmetic and FP64 forms
-BOX_CAP = {0: 1536, 1: 2048}
+BOX_CAP = {0: 1536, 1: 1280}
 
 
 @pytest.fixture(scope="module")
