@@ -433,7 +433,7 @@ def run_physics(met, mpt, inputs, torch, args, nsteps=60, warm=10):
                 s = s0
                 while s < s0 + k:
                     if S > 0 and s % S == 0:
-                        ctx.sort(P)
+                        ctx.sort_deferred(P)
                     stop = min(s0 + k, (s // S + 1) * S if S > 0 else s0 + k, s + args.fuse)
                     if timed:
                         ev.append([torch.cuda.Event(enable_timing=True) for _ in range(2)])
@@ -649,7 +649,8 @@ def main():
                     if ev is not None:
                         ev["sort"].append([torch.cuda.Event(enable_timing=True) for _ in range(2)])
                         ev["sort"][-1][0].record(stream)
-                    ctx.sort(P)
+                    # the order only; the step launch that follows moves the parcels
+                    ctx.sort_deferred(P)
                     if ev is not None:
                         ev["sort"][-1][1].record(stream)
                 stop = min(end, (s // S + 1) * S) if S > 0 else end
@@ -701,7 +702,10 @@ def main():
 
     main_r = results[args.form]
     math_, dtype = FORMS[args.form]
-    state_b = 100 if math_ == 0 else 76
+    # state bytes a launch reads and writes per parcel: read lon, lat, p,
+    # id and the mesoscale state, write them all (the launch after a sort
+    # moves the whole state into sorted order)
+    state_b = 104 if math_ == 0 else 80
     rec_b = 12 if dtype == 0 else 6
     field_b = main_r["unique_pts"] * 2 * rec_b / n
     durations = main_r["step_ms"]

@@ -264,15 +264,32 @@ mpt_status mpt_sort_particles(mpt_ctx *ctx, mpt_particles *particles, void *hip_
 enum { MPT_NOALLOC_SORT_MAX_N = 1 << 22, MPT_NOALLOC_SORT_MAX_KEYS = 1 << 20 };
 mpt_status mpt_sort_particles_noalloc(mpt_ctx *ctx, mpt_particles *particles, void *hip_stream);
 
+/* The sort of mpt_sort_particles (Sec. 6) without moving the parcels: the
+ * sorted order is kept in the context's workspace, and the next mpt_step on
+ * the same parcels (same primary lon array and n) moves them as its first
+ * launch steps them: that launch reads each parcel through the order and
+ * writes its whole state into the *2 set in sorted order, and the call
+ * swaps the primary and *2 pointers inside *particles (so the state moves
+ * once instead of twice).  Until then *particles is unchanged and unsorted.
+ * The order is dropped, unused, by any other call that moves or sorts
+ * parcels (mpt_sort_particles*, mpt_advect, mpt_diffuse, mpt_step_graph,
+ * mpt_step_surrogate), by an mpt_step that starts with its own sort, and by
+ * an mpt_step on other parcels, with scenario indices, or with no module
+ * switched on; results never depend on the order.  Needs n <= n_max. */
+mpt_status mpt_sort_particles_deferred(mpt_ctx *ctx, mpt_particles *particles, void *hip_stream);
+
 /* nsteps time steps step0 .. step0+nsteps-1 (advection, turbulent and
  * mesoscale diffusion per params.flags; the time loop of Sec. 4.3), sorting
  * before every step that is a multiple of params.sort_interval (then the
  * pointers in *particles are swapped as by mpt_sort_particles).
  * Consecutive steps between sorts are fused into launches of at most
- * params.fuse steps.  With scenarios, launches that follow a sort inside
- * the same call use a persistent grid that walks only the parcels released
- * so far (their count is read from the sort's device-side cursors; no
- * host round trip). */
+ * params.fuse steps.  Without scenarios, a sort and the launch after it
+ * move the state once: the sort leaves its order and the launch reads the
+ * parcels through it and writes them in sorted order (as after
+ * mpt_sort_particles_deferred).  With scenarios, launches that follow a
+ * sort inside the same call use a persistent grid that walks only the
+ * parcels released so far (their count is read from the sort's device-side
+ * cursors; no host round trip). */
 mpt_status mpt_step(mpt_ctx *ctx, mpt_particles *particles, uint32_t step0, int32_t nsteps,
                     void *hip_stream);
 

@@ -98,6 +98,7 @@ def lib() -> ctypes.CDLL:
         L.mpt_diffuse.argtypes = [P, P, ctypes.c_uint32, P]
         L.mpt_sort_particles.argtypes = [P, P, P]
         L.mpt_sort_particles_noalloc.argtypes = [P, P, P]
+        L.mpt_sort_particles_deferred.argtypes = [P, P, P]
         L.mpt_step.argtypes = [P, P, ctypes.c_uint32, ctypes.c_int32, P]
         L.mpt_step_graph.argtypes = [P, P, ctypes.c_uint32, ctypes.c_int32, P]
         L.mpt_surrogate_datagen.argtypes = [P, ctypes.c_int64, P, P, P, P, P, P, P]
@@ -120,7 +121,7 @@ def lib() -> ctypes.CDLL:
         L.mpt_status_string.restype = ctypes.c_char_p
         for fn in ("mpt_create", "mpt_init_met", "mpt_copy_met_level", "mpt_set_release",
                    "mpt_advect", "mpt_diffuse", "mpt_sort_particles", "mpt_sort_particles_noalloc",
-                   "mpt_step", "mpt_step_graph",
+                   "mpt_sort_particles_deferred", "mpt_step", "mpt_step_graph",
                    "mpt_destroy", "mpt_surrogate_datagen", "mpt_surrogate_stats",
                    "mpt_surrogate_init", "mpt_surrogate_train_step", "mpt_surrogate_grad",
                    "mpt_surrogate_load", "mpt_surrogate_forward", "mpt_step_surrogate",
@@ -134,8 +135,8 @@ def lib() -> ctypes.CDLL:
 def exported_symbols():
     return ["mpt_workspace_bytes", "mpt_create", "mpt_init_met", "mpt_copy_met_level",
             "mpt_met_level_bytes", "mpt_set_release", "mpt_advect", "mpt_diffuse",
-            "mpt_sort_particles", "mpt_sort_particles_noalloc", "mpt_step", "mpt_step_graph",
-            "mpt_destroy",
+            "mpt_sort_particles", "mpt_sort_particles_noalloc", "mpt_sort_particles_deferred",
+            "mpt_step", "mpt_step_graph", "mpt_destroy",
             "mpt_status_string", "mpt_surrogate_datagen", "mpt_surrogate_stats",
             "mpt_surrogate_init", "mpt_surrogate_train_step", "mpt_surrogate_grad",
             "mpt_surrogate_load", "mpt_surrogate_forward", "mpt_step_surrogate",
@@ -401,6 +402,14 @@ class Context:
         s = P.cstruct()
         _check("mpt_sort_particles_noalloc", lib().mpt_sort_particles_noalloc(self.h, ctypes.byref(s),
                                                                               _stream_handle(stream)))
+        P.adopt(s)
+
+    def sort_deferred(self, P: DeviceParticles, stream=None):
+        """mpt_sort_particles_deferred: the sort's order only; the parcels move
+        in the next step() on them (the particle sets then swap)."""
+        s = P.cstruct()
+        _check("mpt_sort_particles_deferred", lib().mpt_sort_particles_deferred(self.h, ctypes.byref(s),
+                                                                                _stream_handle(stream)))
         P.adopt(s)
 
     def step(self, P: DeviceParticles, step0: int, nsteps: int, stream=None):

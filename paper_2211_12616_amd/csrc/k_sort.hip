@@ -281,6 +281,16 @@ hipError_t launch_clear_spread(uint32_t *spread, uint32_t spread_s, hipStream_t 
   return hipGetLastError();
 }
 
+// The sorted order as a list instead of a move: src[offsets[key] + rank] = i
+// (the step launch that follows reads its parcels through it).
+__global__ __launch_bounds__(kBlock) void k_sort_inverse(const ScatterArgs a) {
+  const int lb = logical_block((int)blockIdx.x, a.per_xcd);
+  if (lb >= a.nblk) return;
+  const int64_t i = (int64_t)lb * kBlock + threadIdx.x;
+  if (i >= a.n) return;
+  a.src[a.offsets[a.keys[i]] + a.ranks[i]] = (uint32_t)i;
+}
+
 hipError_t launch_sort(const SortArgs &sa, const ScatterArgs &xa, bool keys_done, hipStream_t stream) {
   const uint32_t nb = (uint32_t)scan_block_sums_len(sa.nkeys);
   if (!keys_done) {
@@ -293,7 +303,10 @@ hipError_t launch_sort(const SortArgs &sa, const ScatterArgs &xa, bool keys_done
   hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(256), 0, stream, sa.hist, sa.nkeys, sa.block_sums);
   hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(256), 0, stream, sa.block_sums, nb);
   hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(256), 0, stream, sa.hist, sa.nkeys, sa.block_sums);
-  hipLaunchKernelGGL(k_sort_scatter, dim3((unsigned)(xa.per_xcd * kXcds)), dim3(kBlock), 0, stream, xa);
+  if (xa.src)
+    hipLaunchKernelGGL(k_sort_inverse, dim3((unsigned)(xa.per_xcd * kXcds)), dim3(kBlock), 0, stream, xa);
+  else
+    hipLaunchKernelGGL(k_sort_scatter, dim3((unsigned)(xa.per_xcd * kXcds)), dim3(kBlock), 0, stream, xa);
   return hipGetLastError();
 }
 

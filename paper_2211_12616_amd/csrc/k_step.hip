@@ -44,19 +44,22 @@ __device__ __forceinline__ void step_parcel(const StepLds<R> &sm, const uint16_t
   uint32_t id = 0;
   int64_t rel = INT64_MIN;
   const bool do_meso = (a.flags & kMeso) != 0;
+  // deferred sort: the whole state moves, so all of it is read
+  const bool moving = a.src != nullptr;
   R up = 0, vp = 0, wp = 0;
   if (valid) {
-    lon = a.lon[i];
-    lat = a.lat[i];
-    p = a.p[i];
+    const int64_t j = moving ? (int64_t)a.src[i] : i;
+    lon = a.lon[j];
+    lat = a.lat[j];
+    p = a.p[j];
     live = finite3(lon, lat, p);
-    if (live) {
-      id = a.id[i];
-      if (a.scen) rel = a.release[a.scen[i]];
-      if (do_meso) {
-        up = static_cast<const R *>(a.up)[i];
-        vp = static_cast<const R *>(a.vp)[i];
-        wp = static_cast<const R *>(a.wp)[i];
+    if (live || moving) {
+      id = a.id[j];
+      if (a.scen) rel = a.release[a.scen[j]];
+      if (do_meso || (moving && a.up)) {
+        up = static_cast<const R *>(a.up)[j];
+        vp = static_cast<const R *>(a.vp)[j];
+        wp = static_cast<const R *>(a.wp)[j];
       }
     }
   }
@@ -89,8 +92,21 @@ __device__ __forceinline__ void step_parcel(const StepLds<R> &sm, const uint16_t
       }
     }
   }
-  if (!moved) return;
   const StepArgs &b = reload_args();
+  if (b.src) {
+    if (!valid) return;
+    b.lon_o[i] = lon;
+    b.lat_o[i] = lat;
+    b.p_o[i] = p;
+    b.id_o[i] = id;
+    if (b.up) {
+      static_cast<R *>(b.up_o)[i] = up;
+      static_cast<R *>(b.vp_o)[i] = vp;
+      static_cast<R *>(b.wp_o)[i] = wp;
+    }
+    return;
+  }
+  if (!moved) return;
   b.lon[i] = lon;
   b.lat[i] = lat;
   b.p[i] = p;

@@ -91,6 +91,14 @@ struct StepArgs {
   // Device memory, read after the step loop, so its fields hold no scalar
   // registers during it.
   const struct SortKeyArgs *sk;
+  // Deferred sort (block launches only; null: none): parcel i of the sorted
+  // order is read from index src[i] of the arrays above and its whole state
+  // (position, id, mesoscale state) is written to index i of the *_o
+  // arrays, for every parcel, moved or not.
+  const uint32_t *src;
+  double *lon_o, *lat_o, *p_o;
+  uint32_t *id_o;
+  void *up_o, *vp_o, *wp_o;
 };
 
 // Where a launch leaves the sort keys: tile key and rank within the key

@@ -78,6 +78,8 @@ struct ScatterArgs {
   void *up2, *vp2, *wp2;
   uint16_t *scen2;
   int meso_bytes;                  // 8 (double), 4 (float) or 0 (no meso state)
+  uint32_t *src;                   // not null: write the sorted order here (src[position] =
+                                   // parcel index) instead of moving the state
   int nblk, per_xcd;
 };
 

@@ -47,6 +47,11 @@ struct mpt_ctx {
   bool keyed;
   const double *keyed_lon;
   int64_t keyed_n;
+  // a deferred sort's order (in fb_list) for the parcels whose primary lon
+  // array and count these are, consumed by the next mpt_step on them
+  bool ordered;
+  const double *ordered_lon;
+  int64_t ordered_n;
   int32_t nscen;
   // surrogate: bf16 weight copies, normalization, training scratch
   uint16_t *s_wt, *s_wb, *s_wi;
@@ -296,6 +301,10 @@ void fill_step_args(const mpt_ctx *c, const mpt_particles *P, uint32_t step0, in
   a.index = nullptr;
   a.index_count = nullptr;
   a.sk = nullptr;
+  a.src = nullptr;
+  a.lon_o = a.lat_o = a.p_o = nullptr;
+  a.id_o = nullptr;
+  a.up_o = a.vp_o = a.wp_o = nullptr;
   a.sfc = c->sfc;
   a.t_scales = c->t_scales;
   a.conv_cape = q.conv_cape;
@@ -362,8 +371,13 @@ struct SortBufs {
   uint32_t *keys, *ranks, *hist, *spread, *block_sums;
 };
 
+void swap_sets(mpt_particles *P);
+
+// inverse: not null = leave the sorted order in inverse (inverse[position] =
+// parcel index) instead of moving the state (no swap); the next step launch
+// moves it (run_steps with src).
 mpt_status do_sort(mpt_ctx *c, mpt_particles *P, uint32_t step, bool dev_step, hipStream_t s,
-                   bool keys_done = false, const SortBufs *bufs = nullptr) {
+                   bool keys_done = false, const SortBufs *bufs = nullptr, uint32_t *inverse = nullptr) {
   const SortBufs b = bufs ? *bufs : SortBufs{c->keys, c->ranks, c->hist, c->spread, c->block_sums};
   const mpt_grid &g = c->grid;
   SortArgs sa;
@@ -394,12 +408,18 @@ mpt_status do_sort(mpt_ctx *c, mpt_particles *P, uint32_t step, bool dev_step, h
   xa.lon2 = P->lon2; xa.lat2 = P->lat2; xa.p2 = P->p2; xa.id2 = P->id2;
   xa.up2 = P->up2; xa.vp2 = P->vp2; xa.wp2 = P->wp2; xa.scen2 = P->scen2;
   xa.meso_bytes = c->params.math == MPT_MATH_F64 ? 8 : 4;
+  xa.src = inverse;
   const int64_t nblk_x = (P->n + kBlock - 1) / kBlock;
   xa.nblk = (int)nblk_x;
   xa.per_xcd = (int)((nblk_x + kXcds - 1) / kXcds);
   const mpt_status st = from_hip(launch_sort(sa, xa, keys_done, s));
   if (st != MPT_OK) return st;
-  // the sorted state now lives in the *2 set: swap the sets
+  if (!inverse) swap_sets(P);
+  return MPT_OK;
+}
+
+// The sorted state lives in the *2 set: swap the sets.
+void swap_sets(mpt_particles *P) {
   double *t;
   t = P->lon; P->lon = P->lon2; P->lon2 = t;
   t = P->lat; P->lat = P->lat2; P->lat2 = t;
@@ -410,17 +430,24 @@ mpt_status do_sort(mpt_ctx *c, mpt_particles *P, uint32_t step, bool dev_step, h
   tv = P->vp; P->vp = P->vp2; P->vp2 = tv;
   tv = P->wp; P->wp = P->wp2; P->wp2 = tv;
   uint16_t *ts = P->scen; P->scen = P->scen2; P->scen2 = ts;
-  return MPT_OK;
 }
 
 // persistent: parcels are in the order the last sort of this call left
 // them (scenario runs only), so the launch may walk the active prefix.
 // keys: the (block-shaped) launch also leaves the sort keys of the final
 // positions for the sort that follows.
+// src: not null = the deferred sort's order; the launch reads the parcels
+// through it and writes the whole state into the *2 set (the caller swaps).
 mpt_status run_steps(mpt_ctx *c, const mpt_particles *P, uint32_t step0, int nsteps, uint32_t flags,
-                     bool dev_step, bool persistent, hipStream_t s, bool keys = false) {
+                     bool dev_step, bool persistent, hipStream_t s, bool keys = false,
+                     const uint32_t *src = nullptr) {
   StepArgs a;
   fill_step_args(c, P, step0, nsteps, flags, a);
+  if (src) {
+    a.src = src;
+    a.lon_o = P->lon2; a.lat_o = P->lat2; a.p_o = P->p2; a.id_o = P->id2;
+    a.up_o = P->up2; a.vp_o = P->vp2; a.wp_o = P->wp2;
+  }
   if (dev_step) a.step_dev = c->step_dev;
   if (persistent && P->scen) {
     a.persistent = 1;
@@ -454,11 +481,23 @@ mpt_status enqueue_steps(mpt_ctx *c, mpt_particles *P, int64_t first, int64_t co
   bool sorted = false;
   int64_t cur = first;
   const int64_t end = first + count;
+  // Without scenarios and outside graph capture, a sort followed by a
+  // step launch is deferred into it: the sort leaves its order as a list
+  // (in the fallback-list buffer, free outside the surrogate) and the launch
+  // reads its parcels through it and writes them in sorted order, so the
+  // state moves once instead of twice.
+  const bool defer = flags && !P->scen && !dev_step && P->n <= c->n_max;
+  // a deferred sort of these parcels (mpt_sort_particles_deferred) is
+  // completed by the first launch, unless this call starts with its own sort
+  const uint32_t *order =
+      defer && c->ordered && c->ordered_lon == P->lon && c->ordered_n == P->n ? c->fb_list : nullptr;
+  c->ordered = false;
   while (cur < end) {
     if (S > 0 && cur % S == 0) {
-      mpt_status st = do_sort(c, P, (uint32_t)cur, dev_step, s, keys_ready);
+      mpt_status st = do_sort(c, P, (uint32_t)cur, dev_step, s, keys_ready, nullptr, defer ? c->fb_list : nullptr);
       if (st != MPT_OK) return st;
       sorted = true;
+      order = defer ? c->fb_list : nullptr;
     }
     keys_ready = false;
     int64_t stop = end;
@@ -475,8 +514,12 @@ mpt_status enqueue_steps(mpt_ctx *c, mpt_particles *P, int64_t first, int64_t co
       // (the key buffers hold n_max parcels)
       const bool keys = !P->scen && P->n <= c->n_max &&
                         (stop < end ? S > 0 && stop % S == 0 : c->params.presort && !dev_step);
-      mpt_status st = run_steps(c, P, (uint32_t)cur, (int)(stop - cur), flags, dev_step, sorted, s, keys);
+      mpt_status st = run_steps(c, P, (uint32_t)cur, (int)(stop - cur), flags, dev_step, sorted, s, keys, order);
       if (st != MPT_OK) return st;
+      if (order) {
+        swap_sets(P);
+        order = nullptr;
+      }
       keys_ready = keys;
     }
     cur = stop;
@@ -808,6 +851,7 @@ mpt_status mpt_advect(mpt_ctx *c, const mpt_particles *P, uint32_t step, void *h
   st = check_time(c, step, 1);
   if (st != MPT_OK) return st;
   c->keyed = false;                                  // positions move
+  c->ordered = false;
   if (P->n == 0 || !(c->params.flags & MPT_ADVECT)) return MPT_OK;
   return run_steps(c, P, step, 1, MPT_ADVECT, false, false, static_cast<hipStream_t>(hip_stream));
 }
@@ -819,6 +863,7 @@ mpt_status mpt_diffuse(mpt_ctx *c, const mpt_particles *P, uint32_t step, void *
   st = check_time(c, step, 1);
   if (st != MPT_OK) return st;
   c->keyed = false;                                  // positions move
+  c->ordered = false;
   const uint32_t f = c->params.flags & (MPT_TURB | MPT_MESO);
   if (P->n == 0 || !f) return MPT_OK;
   return run_steps(c, P, step, 1, f, false, false, static_cast<hipStream_t>(hip_stream));
@@ -831,7 +876,25 @@ mpt_status mpt_sort_particles(mpt_ctx *c, mpt_particles *P, void *hip_stream) {
   if (P->n == 0) return MPT_OK;
   const bool keys_done = c->keyed && !P->scen && c->keyed_lon == P->lon && c->keyed_n == P->n;
   c->keyed = false;
+  c->ordered = false;
   return do_sort(c, P, 0u, false, static_cast<hipStream_t>(hip_stream), keys_done);
+}
+
+mpt_status mpt_sort_particles_deferred(mpt_ctx *c, mpt_particles *P, void *hip_stream) {
+  if (!c) return MPT_ERR_ARG;
+  const mpt_status st = check_particles(c, P, true);
+  if (st != MPT_OK) return st;
+  c->ordered = false;
+  if (P->n == 0) return MPT_OK;
+  const bool keys_done = c->keyed && !P->scen && c->keyed_lon == P->lon && c->keyed_n == P->n;
+  c->keyed = false;
+  const mpt_status r = do_sort(c, P, 0u, false, static_cast<hipStream_t>(hip_stream), keys_done, nullptr,
+                               c->fb_list);
+  if (r != MPT_OK) return r;
+  c->ordered = true;
+  c->ordered_lon = P->lon;
+  c->ordered_n = P->n;
+  return MPT_OK;
 }
 
 mpt_status mpt_sort_particles_noalloc(mpt_ctx *c, mpt_particles *P, void *hip_stream) {
@@ -845,6 +908,7 @@ mpt_status mpt_sort_particles_noalloc(mpt_ctx *c, mpt_particles *P, void *hip_st
   if (hipGetDevice(&dev) != hipSuccess || !c->static_scratch) return MPT_ERR_HIP;
   if (dev != c->device) return MPT_ERR_STATE;     // the scratch address is the context's device's
   c->keyed = false;                    // the keys a step left are not used here
+  c->ordered = false;
   unsigned char *base = c->static_scratch;
   const SortBufs b{reinterpret_cast<uint32_t *>(base + kNaKeys), reinterpret_cast<uint32_t *>(base + kNaRanks),
                    reinterpret_cast<uint32_t *>(base + kNaHist), reinterpret_cast<uint32_t *>(base + kNaSpread),
@@ -885,6 +949,7 @@ mpt_status mpt_step_graph(mpt_ctx *c, mpt_particles *P, uint32_t step0, int32_t 
   if (st != MPT_OK) return st;
   if (P->n == 0 || nsteps == 0) return MPT_OK;
   c->keyed = false;                                  // replays keep no keys across calls
+  c->ordered = false;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   const bool same = c->graph_exec && memcmp(&c->graph_key, P, sizeof(*P)) == 0 &&
                     c->graph_nsteps == 2 * S;
@@ -1039,6 +1104,7 @@ mpt_status mpt_step_surrogate(mpt_ctx *c, mpt_particles *P, uint32_t step0, int3
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   if (P->n > c->n_max) return MPT_ERR_WORKSPACE;      // fallback list and sort keys hold n_max
   c->keyed = false;
+  c->ordered = false;                                // the fallback list buffer is reused
   const SurrW W = loaded_weights(c);
   const int64_t end = (int64_t)step0 + nsteps;
   // a block sorts first when a multiple of sort_interval falls in it; the

@@ -160,3 +160,81 @@ def test_presort_keys_dropped_by_other_calls(mpt, met3):
     ctx.sort(P)
     torch.cuda.synchronize()
     sorted_by_oracle_keys(met3, P.to_host())
+
+
+@pytest.mark.parametrize("form", [(0, 0), (1, 0), (1, 1)])
+def test_deferred_sort_equals_sort_then_step(mpt, met3, form):
+    """mpt_sort_particles_deferred + mpt_step: the launch reads the parcels
+    through the sort's order and writes them sorted.  Final states by id
+    equal those of mpt_sort_particles + mpt_step bit for bit (parcels are
+    independent); the order left is the order of the oracle's keys of the
+    positions at the sort; every field moved with its parcel, non-finite
+    parcels included (the clustered set has 2 % of them)."""
+    import torch
+    math, dtype = form
+    say(f"[sort] deferred math={math} dtype={dtype}")
+    part = clustered(met3, 50_003, 71)
+    out = []
+    for deferred in (False, True):
+        ctx = mpt.Context(met3, mpt.make_params(math=math, fuse=10), n_max=part.n, dtype=dtype)
+        ctx.upload_met(met3)
+        P = mpt.DeviceParticles.from_host(part, math=math)
+        (ctx.sort_deferred if deferred else ctx.sort)(P)
+        ctx.step(P, 0, 10)
+        torch.cuda.synchronize()
+        h = P.to_host()
+        np.testing.assert_array_equal(np.sort(h.id), np.arange(part.n, dtype=np.uint32))
+        keys = oracle.tile_keys(oracle.Met(met3), part.lon, part.lat, part.p).astype(np.int64)[h.id]
+        assert np.all(np.diff(keys) >= 0)
+        out.append(by_id(h))
+    for f in ("lon", "lat", "p", "up", "vp", "wp"):
+        np.testing.assert_array_equal(getattr(out[0], f), getattr(out[1], f))
+
+
+def test_deferred_sort_dropped_by_other_calls(mpt, met3):
+    """A deferred order is dropped, unused, by a sort in between, and by a
+    step on other parcels; nothing moves until a step consumes it."""
+    import torch
+    part = clustered(met3, 20_000, 72)
+    ctx = mpt.Context(met3, mpt.make_params(math=0, fuse=10), n_max=part.n)
+    ctx.upload_met(met3)
+    P = mpt.DeviceParticles.from_host(part, math=0)
+    ctx.sort_deferred(P)
+    torch.cuda.synchronize()
+    h0 = P.to_host()
+    np.testing.assert_array_equal(h0.id, part.id)               # nothing moved yet
+    ctx.sort(P)                                                  # drops the order
+    Q = mpt.DeviceParticles.from_host(part, math=0)
+    ctx.sort_deferred(Q)
+    ctx.step(P, 0, 10)                                           # other parcels: Q's order unused
+    ctx.step(Q, 0, 10)                                           # dropped by the step on P
+    torch.cuda.synchronize()
+    hq = Q.to_host()
+    np.testing.assert_array_equal(hq.id, part.id)               # Q kept its order
+    a, b = by_id(P.to_host()), by_id(hq)
+    for f in ("lon", "lat", "p", "up", "vp", "wp"):
+        np.testing.assert_array_equal(getattr(a, f), getattr(b, f))
+
+
+def test_sorts_inside_a_call_equal_explicit_sorts(mpt, met3):
+    """mpt_step with sort_interval 10 (each sort deferred into the launch
+    after it) against explicit sorts and steps of 10: the same final states
+    by id, bit for bit, over 30 steps with all modules."""
+    import torch
+    part = clustered(met3, 30_001, 73)
+    res = []
+    for internal in (True, False):
+        ctx = mpt.Context(met3, mpt.make_params(math=1, sort_interval=10 if internal else 0, fuse=10),
+                          n_max=part.n)
+        ctx.upload_met(met3)
+        P = mpt.DeviceParticles.from_host(part, math=1)
+        if internal:
+            ctx.step(P, 0, 30)
+        else:
+            for s0 in (0, 10, 20):
+                ctx.sort(P)
+                ctx.step(P, s0, 10)
+        torch.cuda.synchronize()
+        res.append(by_id(P.to_host()))
+    for f in ("lon", "lat", "p", "up", "vp", "wp"):
+        np.testing.assert_array_equal(getattr(res[0], f), getattr(res[1], f))
