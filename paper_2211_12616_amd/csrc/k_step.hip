@@ -131,10 +131,11 @@ __device__ __forceinline__ int64_t active_bound(const StepArgs &a, uint32_t last
 
 // Minimum waves per SIMD the compiler must allow (register budget) for the
 // FP64 and FP32-arithmetic step kernels: 3 for FP64; in the XCD-block shape
-// 5 for the F32 and BF16 storage forms (their spills at 96 registers are a
-// few dwords and the extra wave hides more of the staging), 4 for FP16
-// storage (at 5 it spills 72 bytes per lane and runs slower); 4 for the
-// persistent and index-list shapes and the physics kernels.
+// 5 for BF16 storage (it spills 12 bytes per lane at 96 registers, and the
+// extra wave hides more of the staging), 4 for F32 (at 5 it spills 44
+// bytes per lane, a loss once the launch also moves the sorted state) and
+// FP16 storage (72 bytes); 4 for the persistent and index-list shapes and
+// the physics kernels.
 #ifndef MPT_WAVES_F64
 #define MPT_WAVES_F64 3
 #endif
@@ -143,7 +144,7 @@ __device__ __forceinline__ int64_t active_bound(const StepArgs &a, uint32_t last
 #endif
 template <int M, int F>
 struct StepWaves {
-  static constexpr int value = (M == 0 && F != kF16) ? 5 : MPT_WAVES_F32;
+  static constexpr int value = (M == 0 && F == kBF16) ? 5 : MPT_WAVES_F32;
 };
 
 enum : int { kModeBlock = 0, kModePersistent = 1, kModeIndex = 2 };
