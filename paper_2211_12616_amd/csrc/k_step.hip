@@ -47,19 +47,30 @@ __device__ __forceinline__ void step_parcel(const StepLds<R> &sm, const uint16_t
   // deferred sort: the whole state moves, so all of it is read
   const bool moving = a.src != nullptr;
   R up = 0, vp = 0, wp = 0;
-  if (valid) {
-    const int64_t j = moving ? (int64_t)a.src[i] : i;
+  if (valid && moving) {                    // every field at once (no scenarios here)
+    const int64_t j = (int64_t)a.src[i];
     lon = a.lon[j];
     lat = a.lat[j];
     p = a.p[j];
+    id = a.id[j];
+    if (a.up) {
+      up = static_cast<const R *>(a.up)[j];
+      vp = static_cast<const R *>(a.vp)[j];
+      wp = static_cast<const R *>(a.wp)[j];
+    }
     live = finite3(lon, lat, p);
-    if (live || moving) {
-      id = a.id[j];
-      if (a.scen) rel = a.release[a.scen[j]];
-      if (do_meso || (moving && a.up)) {
-        up = static_cast<const R *>(a.up)[j];
-        vp = static_cast<const R *>(a.vp)[j];
-        wp = static_cast<const R *>(a.wp)[j];
+  } else if (valid) {
+    lon = a.lon[i];
+    lat = a.lat[i];
+    p = a.p[i];
+    live = finite3(lon, lat, p);
+    if (live) {
+      id = a.id[i];
+      if (a.scen) rel = a.release[a.scen[i]];
+      if (do_meso) {
+        up = static_cast<const R *>(a.up)[i];
+        vp = static_cast<const R *>(a.vp)[i];
+        wp = static_cast<const R *>(a.wp)[i];
       }
     }
   }
