@@ -309,3 +309,16 @@ def test_errors_on_gpu(mpt, met3):
     with pytest.raises(mpt.MptError) as e:
         ctx2.step(Q, 0, 1)                        # scenarios without a release table
     assert e.value.code == -2
+
+
+@pytest.mark.parametrize("math", [0, 1])
+def test_long_launches_equal_short_ones(mpt, met3, math):
+    """Launches of 40 fused steps (the step's time locations are formed 32
+    steps at a time, so a launch crosses that boundary) starting at an
+    unaligned step and crossing a met level (step 120) equal launches of 10,
+    bit for bit, with all modules."""
+    say(f"long launches math={math}")
+    part = inputs.make_particles(20_000, 91)
+    a = gpu_run(met3, part, 97, 80, math=math, fuse=40)
+    b = gpu_run(met3, part, 97, 80, math=math, fuse=10)
+    assert_bitwise(a, b)
