@@ -590,7 +590,7 @@ __device__ __forceinline__ void interp_cell(const StepArgs &a, const Cell16<F> &
 // cos(lat) floored at cos(89.999 deg).  The value must keep its relative
 // accuracy near the poles, where 1/cos(lat) scales the longitude increments
 // and a cosine of a rounded angle has an absolute error.  FP64: the sine of
-// the co-latitude by its series to x^21.  FP32: within 0.5 rad of a pole the
+// the co-latitude by its minimax polynomial.  FP32: within 0.5 rad of a pole the
 // sine of the co-latitude (formed in FP64) by its series to x^7 (relative
 // error below 1e-9), elsewhere (cos >= 0.48) the hardware cosine.
 template <typename R>

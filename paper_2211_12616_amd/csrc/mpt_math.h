@@ -1,9 +1,11 @@
 // mpt_math.h -- FP64 elementary functions on the restricted ranges that the
-// particle step needs, written from their Taylor series: no tables, no
-// large-argument reduction, no special-value handling beyond what the
-// ranges require.  Each stays within a few ulp of the exact value on its
-// range.  Host and device compile the same code, so their accuracy can be
-// checked on the host.
+// particle step needs: argument reductions written out, then minimax
+// polynomials for the smooth remainders of the series (coefficients from
+// gen_minimax.py, a Remez exchange in 50-digit arithmetic, rounded to
+// double).  No tables, no large-argument reduction, no special-value
+// handling beyond what the ranges require.  Each stays within a few ulp of
+// the exact value on its range.  Host and device compile the same code, so
+// their accuracy can be checked on the host.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -64,8 +66,9 @@ __host__ __device__ __forceinline__ double sqrt_pos(double x) {
 
 // ln x for a positive normal x.  x = m 2^e with m in [1/sqrt 2, sqrt 2);
 // ln m = 2 atanh(s), s = (m - 1) / (m + 1), |s| <= 0.1716 (m - 1 is exact);
-// atanh s = s (1 + z/3 + z^2/5 + ... + z^10/21), z = s^2 <= 0.0295, whose
-// remainder is below 1e-18 relative.
+// atanh s = s (1 + z q(z)), z = s^2 <= 0.0295, with q the degree-6 minimax
+// polynomial of (atanh(s)/s - 1)/z (1/3 + z/5 + ...), whose error adds
+// below 2e-18 relative.
 __host__ __device__ __forceinline__ double ln_pos(double x) {
   int e;
   double m = frexp(x, &e);                            // m in [1/2, 1)
@@ -75,36 +78,32 @@ __host__ __device__ __forceinline__ double ln_pos(double x) {
   }
   const double s = div_1to4(m - 1.0, m + 1.0);
   const double z = s * s;
-  double q = 1.0 / 21.0;
-  q = fma(q, z, 1.0 / 19.0);
-  q = fma(q, z, 1.0 / 17.0);
-  q = fma(q, z, 1.0 / 15.0);
-  q = fma(q, z, 1.0 / 13.0);
-  q = fma(q, z, 1.0 / 11.0);
-  q = fma(q, z, 1.0 / 9.0);
-  q = fma(q, z, 1.0 / 7.0);
-  q = fma(q, z, 1.0 / 5.0);
-  q = fma(q, z, 1.0 / 3.0);
+  double q = 0x1.2f0008a2b99ecp-4;
+  q = fma(q, z, 0x1.39a2503857f5bp-4);
+  q = fma(q, z, 0x1.74663874e7961p-4);
+  q = fma(q, z, 0x1.c71c522d05652p-4);                 // ~1/9
+  q = fma(q, z, 0x1.24924941be083p-3);                 // ~1/7
+  q = fma(q, z, 0x1.999999998021bp-3);                 // ~1/5
+  q = fma(q, z, 0x1.5555555555591p-2);                 // ~1/3
   const double t = s + s;
   const double lnm = fma(t * z, q, t);
   const double fe = (double)e;
   return fma(fe, kLn2Hi, fma(fe, kLn2Lo, lnm));
 }
 
-// sin x for |x| <= pi/2 (and a little beyond): odd Taylor series to x^21;
-// the first omitted term is below 1.2e-18 at pi/2.
+// sin x for |x| <= pi/2 + 0.02: sin x = x + x z h(z), z = x^2, with h the
+// degree-7 minimax polynomial of (sin(x)/x - 1)/z (-1/6 + z/120 - ...),
+// whose error adds below 4e-18 relative.
 __host__ __device__ __forceinline__ double sin_half(double x) {
   const double z = x * x;
-  double q = 1.0 / 51090942171709440000.0;            // 1/21!
-  q = fma(q, z, -1.0 / 121645100408832000.0);         // 1/19!
-  q = fma(q, z, 1.0 / 355687428096000.0);             // 1/17!
-  q = fma(q, z, -1.0 / 1307674368000.0);              // 1/15!
-  q = fma(q, z, 1.0 / 6227020800.0);                  // 1/13!
-  q = fma(q, z, -1.0 / 39916800.0);                   // 1/11!
-  q = fma(q, z, 1.0 / 362880.0);                      // 1/9!
-  q = fma(q, z, -1.0 / 5040.0);                       // 1/7!
-  q = fma(q, z, 1.0 / 120.0);                         // 1/5!
-  q = fma(q, z, -1.0 / 6.0);                          // 1/3!
+  double q = 0x1.88019a32e3114p-49;
+  q = fma(q, z, -0x1.ae41c365249b1p-41);
+  q = fma(q, z, 0x1.6123c688a4d1cp-33);
+  q = fma(q, z, -0x1.ae6454bb7bb20p-26);
+  q = fma(q, z, 0x1.71de3a526b757p-19);
+  q = fma(q, z, -0x1.a01a01a0145aap-13);               // ~-1/7!
+  q = fma(q, z, 0x1.11111111110bfp-7);                 // ~1/5!
+  q = fma(q, z, -0x1.5555555555555p-3);                // ~-1/3!
   return fma(x * z, q, x);
 }
 
@@ -116,30 +115,28 @@ __host__ __device__ __forceinline__ double cos_lat_deg(double lat) {
 }
 
 // sin(pi t) and cos(pi t) for t in [0, 2].  n = rint(2 t) quarter periods,
-// r = t - n/2 in [-1/4, 1/4] (exact), x = pi r: sine to x^17 and cosine to
-// x^16 by Taylor (first omitted terms below 1e-19 and 3e-18), then the
-// rotation by n quarter turns.
+// r = t - n/2 in [-1/4, 1/4] (exact), x = pi r, z = x^2: sin x = x + x z h(z)
+// and cos x = 1 - z/2 + z^2 g(z) with degree-5 minimax polynomials h and g
+// (errors adding below 4e-18 and 1e-18), then the rotation by n quarter
+// turns.
 __host__ __device__ __forceinline__ void sincospi_02(double t, double *s, double *c) {
   const double n = rint(t + t);
   const double r = fma(-0.5, n, t);
   const double x = r * kPiD;
   const double z = x * x;
-  double ps = 1.0 / 355687428096000.0;                // 1/17!
-  ps = fma(ps, z, -1.0 / 1307674368000.0);
-  ps = fma(ps, z, 1.0 / 6227020800.0);
-  ps = fma(ps, z, -1.0 / 39916800.0);
-  ps = fma(ps, z, 1.0 / 362880.0);
-  ps = fma(ps, z, -1.0 / 5040.0);
-  ps = fma(ps, z, 1.0 / 120.0);
-  ps = fma(ps, z, -1.0 / 6.0);
+  double ps = 0x1.5d93a7ca6a89dp-33;
+  ps = fma(ps, z, -0x1.ae5e68bcab28fp-26);
+  ps = fma(ps, z, 0x1.71de357b5cdfap-19);
+  ps = fma(ps, z, -0x1.a01a019c16899p-13);             // ~-1/7!
+  ps = fma(ps, z, 0x1.111111110f8abp-7);               // ~1/5!
+  ps = fma(ps, z, -0x1.5555555555549p-3);              // ~-1/3!
   ps = fma(x * z, ps, x);
-  double pc = 1.0 / 20922789888000.0;                 // 1/16!
-  pc = fma(pc, z, -1.0 / 87178291200.0);              // 1/14!
-  pc = fma(pc, z, 1.0 / 479001600.0);                 // 1/12!
-  pc = fma(pc, z, -1.0 / 3628800.0);                  // 1/10!
-  pc = fma(pc, z, 1.0 / 40320.0);                     // 1/8!
-  pc = fma(pc, z, -1.0 / 720.0);                      // 1/6!
-  pc = fma(pc, z, 1.0 / 24.0);                        // 1/4!
+  double pc = -0x1.8fae9e9c70fa5p-37;
+  pc = fma(pc, z, 0x1.1ee9ebedb59f5p-29);
+  pc = fma(pc, z, -0x1.27e4f809f803ap-22);
+  pc = fma(pc, z, 0x1.a01a019cb1c94p-16);               // ~1/8!
+  pc = fma(pc, z, -0x1.6c16c16c1517ep-10);              // ~-1/6!
+  pc = fma(pc, z, 0x1.555555555554cp-5);                // ~1/4!
   pc = fma(pc, z, -0.5);
   pc = fma(pc, z, 1.0);
   const int q = (int)n & 3;
