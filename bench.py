@@ -432,9 +432,9 @@ def run_physics(met, mpt, inputs, torch, args, nsteps=60, warm=10):
             def run(s0, k, timed):
                 s = s0
                 while s < s0 + k:
-                    if S > 0 and s % S == 0:
+                    if S > 0 and (s - s0) % S == 0:            # cadence from the run's first step
                         ctx.sort_deferred(P)
-                    stop = min(s0 + k, (s // S + 1) * S if S > 0 else s0 + k, s + args.fuse)
+                    stop = min(s0 + k, s0 + ((s - s0) // S + 1) * S if S > 0 else s0 + k, s + args.fuse)
                     if timed:
                         ev.append([torch.cuda.Event(enable_timing=True) for _ in range(2)])
                         ev[-1][0].record(stream)
@@ -642,10 +642,13 @@ def main():
         S = args.sort_interval
 
         def run(step0, nsteps, ev=None, fuse=args.fuse):
+            # sorts every S steps counted from the run's first step, so a
+            # timed run is whole sort intervals (a sort, then S steps) and
+            # no launch is cut short by where the warm-up ended
             s = step0
             end = step0 + nsteps
             while s < end:
-                if S > 0 and s % S == 0:
+                if S > 0 and (s - step0) % S == 0:
                     if ev is not None:
                         ev["sort"].append([torch.cuda.Event(enable_timing=True) for _ in range(2)])
                         ev["sort"][-1][0].record(stream)
@@ -653,7 +656,7 @@ def main():
                     ctx.sort_deferred(P)
                     if ev is not None:
                         ev["sort"][-1][1].record(stream)
-                stop = min(end, (s // S + 1) * S) if S > 0 else end
+                stop = min(end, step0 + ((s - step0) // S + 1) * S) if S > 0 else end
                 stop = min(stop, s + fuse)
                 if ev is not None:
                     ev["step"].append(([torch.cuda.Event(enable_timing=True) for _ in range(2)],

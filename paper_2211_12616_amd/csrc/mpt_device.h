@@ -155,11 +155,7 @@ template <> struct Math<double> {
   static __device__ __forceinline__ void sincospi_(double x, double *s, double *c) {
     m64::sincospi_02(x, s, c);
   }
-  static __device__ __forceinline__ double cospi_(double x) {
-    double s, c;
-    m64::sincospi_02(x, &s, &c);
-    return c;
-  }
+  static __device__ __forceinline__ double cospi_(double x) { return m64::cospi_02(x); }
   // 1/x for x in [cos 89.999 deg, 1]: hardware estimate + two Newton steps
   // (error squared per step, final error at the rounding level)
   static __device__ __forceinline__ double rcp(double x) {

@@ -148,5 +148,16 @@ __host__ __device__ __forceinline__ void sincospi_02(double t, double *s, double
   *c = cc;
 }
 
+// cos(pi t) for t in (0, 2) a multiple of 2^-24 (twice a uniform): with
+// h = 1/2 - t (exact), n = rint(h) in {-1, 0} and y = h - n in [-1/2, 1/2]
+// (exact), cos(pi t) = sin(pi h) = (-1)^n sin(pi y); one polynomial
+// (sin_half) where the quarter-period form evaluates two.
+__host__ __device__ __forceinline__ double cospi_02(double t) {
+  const double h = 0.5 - t;
+  const double n = rint(h);
+  const double s = sin_half((h - n) * kPiD);
+  return n != 0.0 ? -s : s;
+}
+
 }  // namespace m64
 }  // namespace mpt

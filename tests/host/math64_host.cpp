@@ -26,6 +26,8 @@ int main(int argc, char **argv) {
       mpt::m64::sincospi_02(v, &s, &c);
       y.push_back(s);
       y.push_back(c);
+    } else if (!strcmp(argv[1], "cospi")) {
+      y.push_back(mpt::m64::cospi_02(v));
     } else if (strcmp(argv[1], "div")) {
       return 2;
     }

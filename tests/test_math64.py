@@ -7,7 +7,8 @@ the argument ranges the step feeds them:
   number around the reduction boundaries;
 * cos of a latitude in degrees, including the poles and a small overshoot
   past them (the midpoint position is not reflected before it is used);
-* sin(pi t), cos(pi t) for t = 2u in [0, 2], including every quarter period;
+* sin(pi t), cos(pi t) for t = 2u in [0, 2], including every quarter period,
+  and cos(pi t) alone by the half-period form;
 * the square root of Box-Muller radii (-2 ln u) and of variances, and the
   division inside ln (numerator in [-0.3, 0.42], denominator in [1.7, 2.42]),
   both refined from reciprocal seeds: within 1 ulp.
@@ -122,6 +123,28 @@ def test_sincospi_on_twice_a_uniform(m64):
     q = sc[len(k):len(k) + 9][0::2]
     np.testing.assert_array_equal(q[:, 0] + 0.0, [0.0, 1.0, 0.0, -1.0, 0.0])
     np.testing.assert_array_equal(q[:, 1] + 0.0, [1.0, 0.0, -1.0, 0.0, 1.0])
+
+
+def test_cospi_half_period_form(m64):
+    # t = 2u for every uniform of the form ((k >> 8) + 1/2) / 2^24 near the
+    # ends, the zeros and the extremes of cos(pi t), and a random sample
+    rng = np.random.default_rng(10)
+    k = np.concatenate([np.arange(0, 4096), (1 << 24) - 1 - np.arange(0, 4096),
+                        (1 << 22) + np.arange(-2048, 2048), (3 << 22) + np.arange(-2048, 2048),
+                        (1 << 23) + np.arange(-2048, 2048), rng.integers(0, 1 << 24, 400_000)])
+    t = 2.0 * ((k.astype(np.float64) + 0.5) / 16777216.0)
+    got = m64("cospi", t)
+    tl = t.astype(LD)
+    fl = np.floor(tl)
+    f = tl - fl
+    ref = np.where(fl % 2 == 0, LD(1), LD(-1)) * np.sin(PI * (LD(0.5) - f))
+    assert np.abs(got.astype(LD) - ref).max() <= 2.5e-16
+    big = np.abs(ref) > 1e-8
+    assert ulp_err(got[big], ref[big]).max() <= 4.0
+    # the same values as the quarter-period form within 2 ulp of 1
+    sc = m64("sincospi", t).reshape(-1, 2)
+    assert np.abs(got - sc[:, 1]).max() <= 4.5e-16
+    np.testing.assert_array_equal(m64("cospi", np.array([0.5, 1.0, 1.5])) + 0.0, [0.0, -1.0, 0.0])
 
 
 def test_sqrt_on_radii_and_variances(m64):
