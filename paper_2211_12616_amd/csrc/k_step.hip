@@ -29,12 +29,24 @@ __device__ __forceinline__ const StepArgs &reload_args() {
   return *(const StepArgs *)q;
 }
 
-// Advances parcel i (valid: the thread holds a parcel) with the launch's
+// Whether a step kernel makes the step's random draws during the
+// advection's staging loads (the turbulent diffusion's in the first wind
+// evaluation, the mesoscale's in the second) instead of just before their
+// use.  The draws then stay live across the advection: only the FP32 form
+// with FP32 fields, no convection or sedimentation and one block per 256
+// parcels (launch shape M 0) has the registers for them.
+template <int M, int F, typename R, bool P>
+struct EarlyDraws {
+  static constexpr bool value = M == 0 && F == kF32 && sizeof(R) == 4 && !P;
+};
+
+// Advances parcel i (valid: the thread holds a parcel; M: the launch shape)
+// with the launch's
 // arguments (reload_args); lon, lat, p receive
 // its final position.  Every thread of the block calls it and runs the same
 // steps: the advection's winds are staged for the whole block
 // (mpt_stage.h), with barriers inside.
-template <int F, typename R, bool P>
+template <int M, int F, typename R, bool P>
 __device__ __forceinline__ void step_parcel(const StepLds<R> &sm, const uint16_t *s_lut,
                                             int64_t i, bool valid, uint32_t step0, BoxRef ref, double &lon,
                                             double &lat, double &p) {
@@ -85,14 +97,34 @@ __device__ __forceinline__ void step_parcel(const StepLds<R> &sm, const uint16_t
     const TimeLoc T0 = time_at(tt, e), T1 = time_at(tt, e + 1);
     const bool act = live && (int64_t)step >= rel && finite3(lon, lat, p);
     moved = moved || act;
-    if (a.flags & kAdvect) {
-      advect_block<F, R>(a, sm, s_lut, act, T0, T1, lon, lat, p, ref);
-      if (act) position(a, lon, lat, p);
-    }
-    if (act && (a.flags & (kTurb | kMeso))) {
-      if (a.flags & kTurb) turb<R>(a, id, step, lon, lat, p);
-      if (do_meso) meso<F, R>(a, sm.plev, sm.idp, s_lut, id, step, T1, lon, lat, p, up, vp, wp);
-      position(a, lon, lat, p);
+    if constexpr (EarlyDraws<M, F, R, P>::value) {
+      // the step's random draws depend on (id, step) only: each is made
+      // while one of the advection's staging loads is in flight
+      R xt[3], xm[3];
+      auto draw_turb = [&] { if (a.flags & kTurb) normals3<R>(a.seed, id, step, 0u, xt); };
+      auto draw_meso = [&] { if (do_meso) normals3<R>(a.seed, id, step, 1u, xm); };
+      if (a.flags & kAdvect) {
+        advect_block_fill<F, R>(a, sm, s_lut, act, T0, T1, lon, lat, p, ref, draw_turb, draw_meso);
+        if (act) position(a, lon, lat, p);
+      } else {
+        draw_turb();
+        draw_meso();
+      }
+      if (act && (a.flags & (kTurb | kMeso))) {
+        if (a.flags & kTurb) turb_drawn<R>(a, xt, lon, lat, p);
+        if (do_meso) meso_drawn<F, R>(a, sm.plev, sm.idp, s_lut, xm, T1, lon, lat, p, up, vp, wp);
+        position(a, lon, lat, p);
+      }
+    } else {
+      if (a.flags & kAdvect) {
+        advect_block<F, R>(a, sm, s_lut, act, T0, T1, lon, lat, p, ref);
+        if (act) position(a, lon, lat, p);
+      }
+      if (act && (a.flags & (kTurb | kMeso))) {
+        if (a.flags & kTurb) turb<R>(a, id, step, lon, lat, p);
+        if (do_meso) meso<F, R>(a, sm.plev, sm.idp, s_lut, id, step, T1, lon, lat, p, up, vp, wp);
+        position(a, lon, lat, p);
+      }
     }
     if constexpr (P) {
       if (act && (a.flags & (kConv | kSedi))) {
@@ -208,7 +240,7 @@ __device__ __forceinline__ void step_body(const StepArgs &a) {
       const int64_t i = valid ? (int64_t)a.index[j] : 0;
       const int64_t j0 = c * kBlock;
       const BoxRef ref = block_ref(a, sm.plev, s_lut, j0 < cnt ? (int64_t)a.index[j0] : 0, j0 < cnt);
-      step_parcel<F, R, P>(sm, s_lut, i, valid, step0, ref, lon, lat, p);
+      step_parcel<M, F, R, P>(sm, s_lut, i, valid, step0, ref, lon, lat, p);
       const StepArgs &b = reload_args();
       if (b.sk) leave_sort_key(b, sm.plev, s_lut, i, valid, lon, lat, p);   // uniform
     }
@@ -219,7 +251,7 @@ __device__ __forceinline__ void step_body(const StepArgs &a) {
     double lon, lat, p;
     const bool valid = i < a.n;
     const BoxRef ref = block_ref(a, sm.plev, s_lut, (int64_t)lb * kBlock, true);
-    step_parcel<F, R, P>(sm, s_lut, i, valid, step0, ref, lon, lat, p);
+    step_parcel<M, F, R, P>(sm, s_lut, i, valid, step0, ref, lon, lat, p);
     const StepArgs &b = reload_args();
     if (b.sk) leave_sort_key(b, sm.plev, s_lut, i, valid, lon, lat, p);     // uniform
   } else {
@@ -234,7 +266,7 @@ __device__ __forceinline__ void step_body(const StepArgs &a) {
       const int64_t i = c * kBlock + threadIdx.x;
       double lon, lat, p;
       const BoxRef ref = block_ref(a, sm.plev, s_lut, c * kBlock, true);
-      step_parcel<F, R, P>(sm, s_lut, i, i < bound, step0, ref, lon, lat, p);
+      step_parcel<M, F, R, P>(sm, s_lut, i, i < bound, step0, ref, lon, lat, p);
     }
   }
 }

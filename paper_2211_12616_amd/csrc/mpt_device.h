@@ -690,6 +690,23 @@ __device__ __forceinline__ void turb(const StepArgs &a, uint32_t id, uint32_t st
   p = p + (double)dp;
 }
 
+// turb with the step's normals of purpose 0 (xi) drawn by the caller (the
+// same displacement; a copy, so that turb's own code stays as it is).
+template <typename R>
+__device__ __forceinline__ void turb_drawn(const StepArgs &a, const R xi[3], double &lon, double &lat,
+                                           double &p) {
+  const R kdeg = (R)kDeg;
+  const R dx = (R)a.sig_h * xi[0];
+  const R dy = (R)a.sig_h * xi[1];
+  const R dz = (R)a.sig_z * xi[2];
+  const R dlon = dx * kdeg * Math<R>::rcp(cos_floor<R>(a, lat));
+  const R dlat = dy * kdeg;
+  const R dp = -dz * (R)p * (R)(1.0 / kH0);
+  lon = lon + (double)dlon;
+  lat = lat + (double)dlat;
+  p = p + (double)dp;
+}
+
 // Spread of the 16 values (2 time levels x 2 levels x 2 rows x 2 columns)
 // of the cell holding (lon, lat, p) at the time-level pair located by T,
 // read from the per-cell table of that pair (one record; k_cell_sigma).
@@ -741,6 +758,16 @@ __device__ __forceinline__ void meso(const StepArgs &a, const double *s_plev, co
   meso_sigma_table<R>(a, s_plev, s_idp, s_lut, T_mid, lon, lat, p, sg);
   R xi[3];
   normals3<R>(a.seed, id, step, 1u, xi);
+  meso_apply<R>(a, sg, xi, lon, lat, p, up, vp, wp);
+}
+
+// meso with the step's normals of purpose 1 (xi) drawn by the caller.
+template <int F, typename R>
+__device__ __forceinline__ void meso_drawn(const StepArgs &a, const double *s_plev, const double *s_idp,
+                                           const uint16_t *s_lut, const R xi[3], const TimeLoc &T_mid,
+                                           double &lon, double &lat, double &p, R &up, R &vp, R &wp) {
+  R sg[3];
+  meso_sigma_table<R>(a, s_plev, s_idp, s_lut, T_mid, lon, lat, p, sg);
   meso_apply<R>(a, sg, xi, lon, lat, p, up, vp, wp);
 }
 
