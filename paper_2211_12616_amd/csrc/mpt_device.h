@@ -140,8 +140,12 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
 template <typename R> struct Math;
 
 template <> struct Math<double> {
+  // ((x >> 8) + 1/2) / 2^24 and twice that, each one exact FMA
   static __device__ __forceinline__ double uni(uint32_t x) {
-    return ((double)(x >> 8) + 0.5) * (1.0 / 16777216.0);
+    return fma((double)(x >> 8), 0x1p-24, 0x1p-25);
+  }
+  static __device__ __forceinline__ double uni2(uint32_t x) {
+    return fma((double)(x >> 8), 0x1p-23, 0x1p-24);
   }
   // ln of a uniform in (0, 1): always a positive normal number
   static __device__ __forceinline__ double log_(double x) { return m64::ln_pos(x); }
@@ -198,15 +202,28 @@ __device__ __forceinline__ void normals3(uint64_t seed, uint32_t id, uint32_t st
   uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
   asm("" : "+s"(k0), "+s"(k1) : "s"(step));
   philox4x32_10(id, step, purpose, 0u, k0, k1, x);
-  const R u0 = Math<R>::uni(x[0]), u1 = Math<R>::uni(x[1]);
-  const R u2 = Math<R>::uni(x[2]), u3 = Math<R>::uni(x[3]);
-  const R r0 = Math<R>::sqrt_((R)-2 * Math<R>::log_(u0));
-  const R r1 = Math<R>::sqrt_((R)-2 * Math<R>::log_(u2));
-  R s1, c1;
-  Math<R>::sincospi_((R)2 * u1, &s1, &c1);      // angle 2 pi u1
-  xi[0] = r0 * c1;
-  xi[1] = r0 * s1;
-  xi[2] = r1 * Math<R>::cospi_((R)2 * u3);
+  if constexpr (sizeof(R) == 8) {
+    // the angles' 2 u1 and 2 u3 formed directly (one exact FMA each)
+    const R u0 = Math<R>::uni(x[0]), t1 = Math<R>::uni2(x[1]);
+    const R u2 = Math<R>::uni(x[2]), t3 = Math<R>::uni2(x[3]);
+    const R r0 = Math<R>::sqrt_((R)-2 * Math<R>::log_(u0));
+    const R r1 = Math<R>::sqrt_((R)-2 * Math<R>::log_(u2));
+    R s1, c1;
+    Math<R>::sincospi_(t1, &s1, &c1);           // angle 2 pi u1
+    xi[0] = r0 * c1;
+    xi[1] = r0 * s1;
+    xi[2] = r1 * Math<R>::cospi_(t3);
+  } else {
+    const R u0 = Math<R>::uni(x[0]), u1 = Math<R>::uni(x[1]);
+    const R u2 = Math<R>::uni(x[2]), u3 = Math<R>::uni(x[3]);
+    const R r0 = Math<R>::sqrt_((R)-2 * Math<R>::log_(u0));
+    const R r1 = Math<R>::sqrt_((R)-2 * Math<R>::log_(u2));
+    R s1, c1;
+    Math<R>::sincospi_((R)2 * u1, &s1, &c1);    // angle 2 pi u1
+    xi[0] = r0 * c1;
+    xi[1] = r0 * s1;
+    xi[2] = r1 * Math<R>::cospi_((R)2 * u3);
+  }
 }
 
 // ---- field records -----------------------------------------------------------
