@@ -33,7 +33,7 @@ FP32_PEAK_TFLOPS = 157.3
 # interpolations of three winds, the spread of 16 values per wind, two
 # Philox blocks with Box-Muller, cos(lat) three times -- counted at 1,000
 # and used for every arithmetic form.  The kernels execute fewer (the F64
-# form 729 FP64 FLOP per parcel-step by counter): a grid point's time
+# form 717 FP64 FLOP per parcel-step by counter): a grid point's time
 # interpolation is shared by the parcels of a block and the spreads are
 # tabulated per cell, so `achieved` credits work the kernel avoids, as an
 # algorithmic roofline does; the executed rate is in the profiles.
