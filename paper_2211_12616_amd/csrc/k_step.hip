@@ -40,6 +40,14 @@ struct EarlyDraws {
   static constexpr bool value = M == 0 && F == kF32 && sizeof(R) == 4 && !P;
 };
 
+// Whether a step kernel stages its winds once per step (advect_block_one):
+// the FP64 form, launched one block per 256 parcels, without convection or
+// sedimentation.
+template <int M, int F, typename R, bool P>
+struct OneStaging {
+  static constexpr bool value = M == 0 && sizeof(R) == 8 && !P;
+};
+
 // Advances parcel i (valid: the thread holds a parcel; M: the launch shape)
 // with the launch's
 // arguments (reload_args); lon, lat, p receive
@@ -117,7 +125,8 @@ __device__ __forceinline__ void step_parcel(const StepLds<R> &sm, const uint16_t
       }
     } else {
       if (a.flags & kAdvect) {
-        advect_block<F, R>(a, sm, s_lut, act, T0, T1, lon, lat, p, ref);
+        if constexpr (OneStaging<M, F, R, P>::value) advect_block_one<F, R>(a, sm, s_lut, act, T0, T1, lon, lat, p, ref);
+        else advect_block<F, R>(a, sm, s_lut, act, T0, T1, lon, lat, p, ref);
         if (act) position(a, lon, lat, p);
       }
       if (act && (a.flags & (kTurb | kMeso))) {

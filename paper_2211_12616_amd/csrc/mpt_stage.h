@@ -468,4 +468,189 @@ __device__ __forceinline__ void advect_block_fill(const StepArgs &a, const StepL
   }
 }
 
+// ---- one staging per step ------------------------------------------------------
+//
+// The midpoint of a step lies within one cell of its start in each
+// direction (the half-step displacement is far below a cell), so one box,
+// that of the block's start cells widened by one cell, serves both wind
+// evaluations of the step.  It is staged once with the two time levels'
+// values of each point as they come from the records (FP32, after the R16
+// decode and scale), a pair per point and variable; each corner is weighted
+// in time when it is read, with the evaluation's own weight, as the gather
+// path weights it.  This saves the second box exchange, staging and pair of
+// barriers at the price of the per-corner time weights.  The pair planes
+// take the memory of the three one-time planes (8 bytes per point and
+// variable).
+
+// The widened box: one more column on each side (periodic), one more row
+// and one more level on each side (clamped at the grid's edges); ok when
+// it fits cap points.
+__device__ __forceinline__ Box widen_box(const StepArgs &a, const Box &b, int cap) {
+  Box w = b;
+  w.ok = false;
+  if (!b.ok || b.bi + 2 > a.nx) return w;
+  w.gi = b.gi - 1;
+  if (w.gi < 0) w.gi += a.nx;
+  w.bi = b.bi + 2;
+  w.j0 = max(b.j0 - 1, 0);
+  w.bj = min(b.j0 + b.bj, a.ny - 1) - w.j0 + 1;
+  w.k0 = max(b.k0 - 1, 0);
+  w.bk = min(b.k0 + b.bk, a.nz - 1) - w.k0 + 1;
+  w.ok = w.bi <= kMaxExtent && w.bj <= kMaxExtent && w.bi * w.bj * w.bk <= cap;
+  return w;
+}
+
+// Whether L's cell (all 8 corners) lies in box b.
+template <typename R>
+__device__ __forceinline__ bool in_box(const StepArgs &a, const Box &b, const Loc<R> &L) {
+  int ci = L.i0 - b.gi;
+  if (ci < 0) ci += a.nx;
+  return ci <= b.bi - 2 && (unsigned)(L.j - b.j0) <= (unsigned)(b.bj - 2) &&
+         (unsigned)(L.k - b.k0) <= (unsigned)(b.bk - 2);
+}
+
+// The three pair planes (u, v, w; point q's pair at [q]) in the memory of
+// the one-time planes.
+template <typename R>
+__device__ __forceinline__ void pair_planes(const StepLds<R> &sm, float2 *pp[3]) {
+  constexpr int cap = BoxCap<R>::value * (int)sizeof(R) / 8;
+  float2 *base = reinterpret_cast<float2 *>(sm.bu);
+  pp[0] = base;
+  pp[1] = base + cap;
+  pp[2] = base + 2 * cap;
+}
+template <typename R>
+constexpr int pair_cap() {
+  return BoxCap<R>::value * (int)sizeof(R) / 8;
+}
+
+// Stages box b's points as pairs (the values of time levels l and l1 of L,
+// decoded and scaled for R16 storage, in FP32).
+template <int F, typename R>
+__device__ __forceinline__ void stage_box_pairs(const StepArgs &a, float2 *const pp[3], const Box &b, const Loc<R> &L) {
+  using T = typename Rec<F>::T;
+  const T *lev0 = reinterpret_cast<const T *>(a.met) + (size_t)L.l * (size_t)a.level_elems;
+  const T *lev1 = reinterpret_cast<const T *>(a.met) + (size_t)L.l1 * (size_t)a.level_elems;
+  const int npts = b.bi * b.bj * b.bk;
+  const uint32_t mi = kDivMagic.m[b.bi];
+  const uint32_t mj = kDivMagic.m[b.bj];
+  const float *sw0 = s_scale_win + (L.la % kScaleWin) * 3 * a.nz;
+  const float *sw1 = s_scale_win + ((L.la + 1) % kScaleWin) * 3 * a.nz;
+  for (int q0 = (int)threadIdx.x; q0 < npts; q0 += 2 * kBlock) {
+    T r0[2], r1[2];
+    int kq[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int q = min(q0 + u * kBlock, npts - 1);   // a duplicate of the last point is harmless
+      const int r = (int)__umulhi((uint32_t)q, mi);
+      const int ii = q - r * b.bi;
+      const int kk = (int)__umulhi((uint32_t)r, mj);
+      const int jj = r - kk * b.bj;
+      int gi = b.gi + ii;
+      if (gi >= a.nx) gi -= a.nx;
+      kq[u] = b.k0 + kk;
+      const int off = (kq[u] * a.ny + b.j0 + jj) * a.nx + gi;   // < 2^31: nx*ny*nz is
+      r0[u] = lev0[off];
+      r1[u] = lev1[off];
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int q = min(q0 + u * kBlock, npts - 1);
+      const int k = kq[u];
+      float v0[3], v1[3];
+      if constexpr (F == kF32) {
+        v0[0] = r0[u].x; v0[1] = r0[u].y; v0[2] = r0[u].z;
+        v1[0] = r1[u].x; v1[1] = r1[u].y; v1[2] = r1[u].z;
+      } else {
+        v0[0] = dec<F>(r0[u].x) * sw0[k]; v0[1] = dec<F>(r0[u].y) * sw0[a.nz + k];
+        v0[2] = dec<F>(r0[u].z) * sw0[2 * a.nz + k];
+        v1[0] = dec<F>(r1[u].x) * sw1[k]; v1[1] = dec<F>(r1[u].y) * sw1[a.nz + k];
+        v1[2] = dec<F>(r1[u].z) * sw1[2 * a.nz + k];
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) pp[c][q] = make_float2(v0[c], v1[c]);
+    }
+  }
+}
+
+// The wind at L from the pair planes of box b: each corner's pair weighted
+// in time with L.ft (as Fetch and the lerp of the gather path), then the
+// spatial interpolation.
+template <typename R>
+__device__ __forceinline__ void interp_pairs(const StepArgs &a, float2 *const pp[3], const Box &b, const Loc<R> &L,
+                                             R out[3]) {
+  int ci = L.i0 - b.gi;
+  if (ci < 0) ci += a.nx;
+  const int sj = b.bi, sk = b.bi * b.bj;
+  const int base = (L.k - b.k0) * sk + (L.j - b.j0) * sj + ci;
+  R cv[2][2][2][3];
+#pragma unroll
+  for (int dk = 0; dk < 2; ++dk)
+#pragma unroll
+    for (int dj = 0; dj < 2; ++dj)
+#pragma unroll
+      for (int di = 0; di < 2; ++di) {
+        const int q = base + dk * sk + dj * sj + di;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const float2 v = pp[c][q];
+          cv[dk][dj][di][c] = lerp((R)v.x, (R)v.y, L.ft);
+        }
+      }
+  interp_spatial<R>(cv, L, out);
+}
+
+// advect_block with one box exchange and one staging per step: the box of
+// the start cells widened by one cell (or, when that does not fit, the box
+// itself) is staged as pairs; the start winds read it, and so do the
+// midpoint winds of the lanes whose midpoint cell lies in it when the
+// midpoint time uses the start's time-level pair; the other lanes gather.
+// Every thread of the block calls it with the same ref; the winds are
+// those of advect_block bit for bit.
+template <int F, typename R>
+__device__ __forceinline__ void advect_block_one(const StepArgs &a, const StepLds<R> &sm, const uint16_t *s_lut,
+                                                 bool act, const TimeLoc &T0, const TimeLoc &T1, double &lon,
+                                                 double &lat, double &p, BoxRef &ref) {
+  float2 *pp[3];
+  pair_planes<R>(sm, pp);
+  const bool same = T0.l == T1.l && T0.l1 == T1.l1 && T0.la == T1.la;   // uniform
+  Box s;
+  s.ok = false;
+  auto wind = [&](int h, double x, double y, double z, R out[3]) {
+    Loc<R> L;
+    locate_xyz<R>(a, sm.plev, sm.idp, s_lut, x, y, z, L);
+    if (h == 0) {
+      set_time(T0, L);
+      const Box b = block_box<R>(a, sm, act, L, ref);
+      const Box w = widen_box(a, b, pair_cap<R>());
+      s = w.ok ? w : b;
+      s.ok = s.ok && s.bi * s.bj * s.bk <= pair_cap<R>();
+      if (s.ok) stage_box_pairs<F, R>(a, pp, s, L);
+      __syncthreads();
+      if (!act) return;
+      if (s.ok) {
+        interp_pairs<R>(a, pp, s, L, out);
+        return;
+      }
+    } else {
+      set_time(T1, L);
+      if (!act) return;
+      if (same && s.ok && in_box(a, s, L)) {
+        interp_pairs<R>(a, pp, s, L, out);
+        return;
+      }
+    }
+    Cell16<F> c;
+    load_cell<F, R>(a, L, c);
+    interp_cell<F, R>(a, c, L, out);
+  };
+  double nlon, nlat, np;
+  midpoint<R>(a, lon, lat, p, wind, nlon, nlat, np);
+  if (act) {
+    lon = nlon;
+    lat = nlat;
+    p = np;
+  }
+}
+
 }  // namespace mpt
