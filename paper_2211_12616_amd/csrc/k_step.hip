@@ -41,11 +41,13 @@ struct EarlyDraws {
 };
 
 // Whether a step kernel stages its winds once per step (advect_block_one):
-// the FP64 form, launched one block per 256 parcels, without convection or
-// sedimentation.
+// the FP64 form and the FP32 form with FP32 fields, launched one block per
+// 256 parcels, without convection or sedimentation.  The FP32 form's pairs
+// take a wider box region (Wide: kWidePairs points).
 template <int M, int F, typename R, bool P>
 struct OneStaging {
-  static constexpr bool value = M == 0 && sizeof(R) == 8 && !P;
+  static constexpr bool value = M == 0 && !P && (sizeof(R) == 8 || F == kF32);
+  static constexpr bool wide = value && sizeof(R) == 4;
 };
 
 // Advances parcel i (valid: the thread holds a parcel; M: the launch shape)
@@ -112,7 +114,16 @@ __device__ __forceinline__ void step_parcel(const StepLds<R> &sm, const uint16_t
       auto draw_turb = [&] { if (a.flags & kTurb) normals3<R>(a.seed, id, step, 0u, xt); };
       auto draw_meso = [&] { if (do_meso) normals3<R>(a.seed, id, step, 1u, xm); };
       if (a.flags & kAdvect) {
-        advect_block_fill<F, R>(a, sm, s_lut, act, T0, T1, lon, lat, p, ref, draw_turb, draw_meso);
+        if constexpr (OneStaging<M, F, R, P>::value) {
+          auto draws = [&] {
+            draw_turb();
+            draw_meso();
+          };
+          advect_block_one_fill<F, R, OneStaging<M, F, R, P>::wide>(a, sm, s_lut, act, T0, T1, lon, lat, p, ref,
+                                                                    draws);
+        } else {
+          advect_block_fill<F, R>(a, sm, s_lut, act, T0, T1, lon, lat, p, ref, draw_turb, draw_meso);
+        }
         if (act) position(a, lon, lat, p);
       } else {
         draw_turb();
@@ -219,7 +230,7 @@ __device__ __forceinline__ void leave_sort_key(const StepArgs &a, const double *
 template <int M, int F, typename R, bool P>
 __device__ __forceinline__ void step_body(const StepArgs &a) {
   __shared__ __attribute__((aligned(16))) uint16_t s_lut[kLutBins];
-  const StepLds<R> sm = step_lds<R>(a.nz, F != kF32);
+  const StepLds<R> sm = step_lds<R>(a.nz, F != kF32, OneStaging<M, F, R, P>::wide);
   for (int q = threadIdx.x; q < a.nz; q += kBlock) {
     sm.plev[q] = a.plev[q];
     sm.idp[q] = (q < a.nz - 1) ? a.inv_dp[q] : 0.0;
@@ -306,8 +317,8 @@ void k_step_phys_f32(const StepArgs a) {
 
 // Dynamic LDS of the step kernels (mpt_stage.h).
 template <typename R>
-static size_t lds_bytes(int field, const StepArgs &a) {
-  return step_lds_bytes<R>(a.nz, field != kF32);
+static size_t lds_bytes(int field, const StepArgs &a, bool wide = false) {
+  return step_lds_bytes<R>(a.nz, field != kF32, wide);
 }
 
 template <int M>
@@ -318,7 +329,8 @@ static hipError_t launch_mode(int field, int math_f64, const StepArgs &args, dim
     if (field != kF32) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_step_f64<M>, grid, block, lds_bytes<double>(field, args), stream, args);
   } else if (field == kF32) {
-    hipLaunchKernelGGL((k_step_f32<M, kF32>), grid, block, lds_bytes<float>(field, args), stream, args);
+    hipLaunchKernelGGL((k_step_f32<M, kF32>), grid, block,
+                       lds_bytes<float>(field, args, OneStaging<M, kF32, float, false>::wide), stream, args);
   } else if (field == kBF16) {
     hipLaunchKernelGGL((k_step_f32<M, kBF16>), grid, block, lds_bytes<float>(field, args), stream, args);
   } else {

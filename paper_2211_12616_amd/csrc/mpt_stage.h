@@ -41,14 +41,27 @@ __host__ __device__ constexpr size_t round16(size_t x) { return (x + 15) & ~(siz
 // bounds, then 2 per wave for the offset masks.
 constexpr int kRedInts = (kBlock / 64) * 8 + (kBlock / 64) * 2 + 8;
 
+// Points of the widened pair box of the FP32 form's one staging per step
+// (3 x 8 bytes per point: 28.8 KB, so that four blocks still fit a CU).
+constexpr int kWidePairs = 1200;
+
+// Bytes of the box region: u, v, w planes of BoxCap values each, or (wide)
+// enough for kWidePairs FP32 pairs per variable.
+template <typename R>
+__host__ __device__ constexpr size_t box_bytes(bool wide) {
+  return round16(wide && (size_t)3 * kWidePairs * 8 > (size_t)3 * BoxCap<R>::value * sizeof(R)
+                     ? (size_t)3 * kWidePairs * 8
+                     : (size_t)3 * BoxCap<R>::value * sizeof(R));
+}
+
 // Dynamic LDS of the step kernels, in this order: the R16 scale window
 // (kScaleWin x 3 x nz floats; it starts the dynamic region), the level
-// pressures and inverse spacings (nz doubles each), the box (u, v, w planes
-// of BoxCap values each) and the reduction slots.
+// pressures and inverse spacings (nz doubles each), the box region
+// (box_bytes) and the reduction slots.
 template <typename R>
-__host__ __device__ constexpr size_t step_lds_bytes(int nz, bool r16) {
+__host__ __device__ constexpr size_t step_lds_bytes(int nz, bool r16, bool wide = false) {
   return (r16 ? round16((size_t)kScaleWin * 3 * nz * sizeof(float)) : 0) + round16((size_t)2 * nz * sizeof(double)) +
-         round16((size_t)3 * BoxCap<R>::value * sizeof(R)) + (size_t)kRedInts * sizeof(int);
+         box_bytes<R>(wide) + (size_t)kRedInts * sizeof(int);
 }
 
 template <typename R>
@@ -59,7 +72,7 @@ struct StepLds {
 };
 
 template <typename R>
-__device__ __forceinline__ StepLds<R> step_lds(int nz, bool r16) {
+__device__ __forceinline__ StepLds<R> step_lds(int nz, bool r16, bool wide = false) {
   unsigned char *base = reinterpret_cast<unsigned char *>(s_scale_win);
   size_t off = r16 ? round16((size_t)kScaleWin * 3 * nz * sizeof(float)) : 0;
   StepLds<R> sm;
@@ -69,7 +82,7 @@ __device__ __forceinline__ StepLds<R> step_lds(int nz, bool r16) {
   sm.bu = reinterpret_cast<R *>(base + off);
   sm.bv = sm.bu + BoxCap<R>::value;
   sm.bw = sm.bv + BoxCap<R>::value;
-  off += round16((size_t)3 * BoxCap<R>::value * sizeof(R));
+  off += box_bytes<R>(wide);
   sm.red = reinterpret_cast<int *>(base + off);
   return sm;
 }
@@ -509,19 +522,21 @@ __device__ __forceinline__ bool in_box(const StepArgs &a, const Box &b, const Lo
          (unsigned)(L.k - b.k0) <= (unsigned)(b.bk - 2);
 }
 
-// The three pair planes (u, v, w; point q's pair at [q]) in the memory of
-// the one-time planes.
-template <typename R>
+// Points per pair plane: the memory of the one-time planes, or (Wide) the
+// wide box region.
+template <typename R, bool Wide = false>
+constexpr int pair_cap() {
+  return Wide ? kWidePairs : BoxCap<R>::value * (int)sizeof(R) / 8;
+}
+
+// The three pair planes (u, v, w; point q's pair at [q]) in the box region.
+template <typename R, bool Wide = false>
 __device__ __forceinline__ void pair_planes(const StepLds<R> &sm, float2 *pp[3]) {
-  constexpr int cap = BoxCap<R>::value * (int)sizeof(R) / 8;
+  constexpr int cap = pair_cap<R, Wide>();
   float2 *base = reinterpret_cast<float2 *>(sm.bu);
   pp[0] = base;
   pp[1] = base + cap;
   pp[2] = base + 2 * cap;
-}
-template <typename R>
-constexpr int pair_cap() {
-  return BoxCap<R>::value * (int)sizeof(R) / 8;
 }
 
 // Stages box b's points as pairs (the values of time levels l and l1 of L,
@@ -626,6 +641,117 @@ __device__ __forceinline__ void advect_block_one(const StepArgs &a, const StepLd
       s = w.ok ? w : b;
       s.ok = s.ok && s.bi * s.bj * s.bk <= pair_cap<R>();
       if (s.ok) stage_box_pairs<F, R>(a, pp, s, L);
+      __syncthreads();
+      if (!act) return;
+      if (s.ok) {
+        interp_pairs<R>(a, pp, s, L, out);
+        return;
+      }
+    } else {
+      set_time(T1, L);
+      if (!act) return;
+      if (same && s.ok && in_box(a, s, L)) {
+        interp_pairs<R>(a, pp, s, L, out);
+        return;
+      }
+    }
+    Cell16<F> c;
+    load_cell<F, R>(a, L, c);
+    interp_cell<F, R>(a, c, L, out);
+  };
+  double nlon, nlat, np;
+  midpoint<R>(a, lon, lat, p, wind, nlon, nlat, np);
+  if (act) {
+    lon = nlon;
+    lat = nlat;
+    p = np;
+  }
+}
+
+// One pass of stage_box_pairs over points q0 and q0 + kBlock (each clamped
+// to the box's last point), with mid() run between the loads and their use.
+template <int F, typename R, typename Mid>
+__device__ __forceinline__ void pair_pass(const StepArgs &a, float2 *const pp[3], const Box &b, const Loc<R> &L,
+                                          int q0, Mid &&mid) {
+  using T = typename Rec<F>::T;
+  const T *lev0 = reinterpret_cast<const T *>(a.met) + (size_t)L.l * (size_t)a.level_elems;
+  const T *lev1 = reinterpret_cast<const T *>(a.met) + (size_t)L.l1 * (size_t)a.level_elems;
+  const int npts = b.bi * b.bj * b.bk;
+  const uint32_t mi = kDivMagic.m[b.bi];
+  const uint32_t mj = kDivMagic.m[b.bj];
+  const float *sw0 = s_scale_win + (L.la % kScaleWin) * 3 * a.nz;
+  const float *sw1 = s_scale_win + ((L.la + 1) % kScaleWin) * 3 * a.nz;
+  T r0[2], r1[2];
+  int kq[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int q = min(q0 + u * kBlock, npts - 1);
+    const int r = (int)__umulhi((uint32_t)q, mi);
+    const int ii = q - r * b.bi;
+    const int kk = (int)__umulhi((uint32_t)r, mj);
+    const int jj = r - kk * b.bj;
+    int gi = b.gi + ii;
+    if (gi >= a.nx) gi -= a.nx;
+    kq[u] = b.k0 + kk;
+    const int off = (kq[u] * a.ny + b.j0 + jj) * a.nx + gi;   // < 2^31: nx*ny*nz is
+    r0[u] = lev0[off];
+    r1[u] = lev1[off];
+  }
+  mid();
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int q = min(q0 + u * kBlock, npts - 1);
+    const int k = kq[u];
+    float v0[3], v1[3];
+    if constexpr (F == kF32) {
+      v0[0] = r0[u].x; v0[1] = r0[u].y; v0[2] = r0[u].z;
+      v1[0] = r1[u].x; v1[1] = r1[u].y; v1[2] = r1[u].z;
+    } else {
+      v0[0] = dec<F>(r0[u].x) * sw0[k]; v0[1] = dec<F>(r0[u].y) * sw0[a.nz + k];
+      v0[2] = dec<F>(r0[u].z) * sw0[2 * a.nz + k];
+      v1[0] = dec<F>(r1[u].x) * sw1[k]; v1[1] = dec<F>(r1[u].y) * sw1[a.nz + k];
+      v1[2] = dec<F>(r1[u].z) * sw1[2 * a.nz + k];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) pp[c][q] = make_float2(v0[c], v1[c]);
+  }
+}
+
+// stage_box_pairs with fill() run once in every thread between the first
+// pass's loads and their use (the first pass runs in every thread: npts >= 8,
+// a thread past the box rewrites the box's last point).
+template <int F, typename R, typename Fill>
+__device__ __forceinline__ void stage_box_pairs_fill(const StepArgs &a, float2 *const pp[3], const Box &b,
+                                                     const Loc<R> &L, Fill &&fill) {
+  const int npts = b.bi * b.bj * b.bk;
+  pair_pass<F, R>(a, pp, b, L, (int)threadIdx.x, fill);
+  for (int q0 = (int)threadIdx.x + 2 * kBlock; q0 < npts; q0 += 2 * kBlock) pair_pass<F, R>(a, pp, b, L, q0, [] {});
+}
+
+// advect_block_one with the box region of pair_cap<R, Wide>() points and
+// fill() run once in every thread while the staging's first loads are in
+// flight (or before the gathers when nothing is staged).
+template <int F, typename R, bool Wide, typename Fill>
+__device__ __forceinline__ void advect_block_one_fill(const StepArgs &a, const StepLds<R> &sm, const uint16_t *s_lut,
+                                                      bool act, const TimeLoc &T0, const TimeLoc &T1, double &lon,
+                                                      double &lat, double &p, BoxRef &ref, Fill &&fill) {
+  float2 *pp[3];
+  pair_planes<R, Wide>(sm, pp);
+  constexpr int cap = pair_cap<R, Wide>();
+  const bool same = T0.l == T1.l && T0.l1 == T1.l1 && T0.la == T1.la;   // uniform
+  Box s;
+  s.ok = false;
+  auto wind = [&](int h, double x, double y, double z, R out[3]) {
+    Loc<R> L;
+    locate_xyz<R>(a, sm.plev, sm.idp, s_lut, x, y, z, L);
+    if (h == 0) {
+      set_time(T0, L);
+      const Box b = block_box<R>(a, sm, act, L, ref);
+      const Box w = widen_box(a, b, cap);
+      s = w.ok ? w : b;
+      s.ok = s.ok && s.bi * s.bj * s.bk <= cap;
+      if (s.ok) stage_box_pairs_fill<F, R>(a, pp, s, L, fill);
+      else fill();
       __syncthreads();
       if (!act) return;
       if (s.ok) {
