@@ -41,8 +41,8 @@ __host__ __device__ constexpr size_t round16(size_t x) { return (x + 15) & ~(siz
 // bounds, then 2 per wave for the offset masks.
 constexpr int kRedInts = (kBlock / 64) * 8 + (kBlock / 64) * 2 + 8;
 
-// Points of the widened pair box of the FP32 form's one staging per step
-// (3 x 8 bytes per point: 28.8 KB, so that four blocks still fit a CU).
+// Points of the pair box of the FP32 form's one staging per step (3 x 8
+// bytes per point: 28.8 KB, so that four blocks still fit a CU).
 constexpr int kWidePairs = 1200;
 
 // Bytes of the box region: u, v, w planes of BoxCap values each, or (wide)
@@ -483,40 +483,18 @@ __device__ __forceinline__ void advect_block_fill(const StepArgs &a, const StepL
 
 // ---- one staging per step ------------------------------------------------------
 //
-// The midpoint of a step lies within one cell of its start in each
-// direction (the half-step displacement is far below a cell), so one box,
-// that of the block's start cells widened by one cell, serves both wind
-// evaluations of the step.  It is staged once with the two time levels'
-// values of each point as they come from the records (FP32, after the R16
-// decode and scale), a pair per point and variable; each corner is weighted
-// in time when it is read, with the evaluation's own weight, as the gather
-// path weights it.  This saves the second box exchange, staging and pair of
-// barriers at the price of the per-corner time weights.  The pair planes
-// take the memory of the three one-time planes (8 bytes per point and
-// variable).
-
-// The widened box: one more column on each side (periodic), one more row
-// on each side and (wk) one more level on each side (clamped at the grid's
-// edges); ok when it fits cap points.  A midpoint changes level far less
-// often than column or row (at 0.3 deg: 0.2 % of parcels against 2.5 % and
-// 0.8 %), so the FP64 form, whose staging costs it more than the few
-// midpoints that then gather, widens in longitude and latitude only.
-__device__ __forceinline__ Box widen_box(const StepArgs &a, const Box &b, int cap, bool wk) {
-  Box w = b;
-  w.ok = false;
-  if (!b.ok || b.bi + 2 > a.nx) return w;
-  w.gi = b.gi - 1;
-  if (w.gi < 0) w.gi += a.nx;
-  w.bi = b.bi + 2;
-  w.j0 = max(b.j0 - 1, 0);
-  w.bj = min(b.j0 + b.bj, a.ny - 1) - w.j0 + 1;
-  if (wk) {
-    w.k0 = max(b.k0 - 1, 0);
-    w.bk = min(b.k0 + b.bk, a.nz - 1) - w.k0 + 1;
-  }
-  w.ok = w.bi <= kMaxExtent && w.bj <= kMaxExtent && w.bi * w.bj * w.bk <= cap;
-  return w;
-}
+// The midpoint of a step lies in or next to the cell of its start (the
+// half-step displacement is far below a cell), so the box of the block's
+// start cells holds most midpoint cells too, and one staging serves both
+// wind evaluations of the step: the box is staged once with the two time
+// levels' values of each point as they come from the records (FP32, after
+// the R16 decode and scale), a pair per point and variable, and each corner
+// is weighted in time when it is read, with the evaluation's own weight, as
+// the gather path weights it.  The lanes whose midpoint cell leaves the box
+// gather its records.  This saves the second box exchange, staging and pair
+// of barriers at the price of the per-corner time weights.  (Widening the
+// box by a cell, so that every midpoint reads LDS, staged twice the points
+// and was slower than the gathers it saved.)
 
 // Whether L's cell (all 8 corners) lies in box b.
 template <typename R>
@@ -621,9 +599,8 @@ __device__ __forceinline__ void interp_pairs(const StepArgs &a, float2 *const pp
 }
 
 // advect_block with one box exchange and one staging per step: the box of
-// the start cells widened by one cell in longitude and latitude (or, when
-// that does not fit, the box itself) is staged as pairs; the start winds read it, and so do the
-// midpoint winds of the lanes whose midpoint cell lies in it when the
+// the start cells is staged as pairs; the start winds read it, and so do
+// the midpoint winds of the lanes whose midpoint cell lies in it when the
 // midpoint time uses the start's time-level pair; the other lanes gather.
 // Every thread of the block calls it with the same ref; the winds are
 // those of advect_block bit for bit.
@@ -641,9 +618,7 @@ __device__ __forceinline__ void advect_block_one(const StepArgs &a, const StepLd
     locate_xyz<R>(a, sm.plev, sm.idp, s_lut, x, y, z, L);
     if (h == 0) {
       set_time(T0, L);
-      const Box b = block_box<R>(a, sm, act, L, ref);
-      const Box w = widen_box(a, b, pair_cap<R>(), false);
-      s = w.ok ? w : b;
+      s = block_box<R>(a, sm, act, L, ref);
       s.ok = s.ok && s.bi * s.bj * s.bk <= pair_cap<R>();
       if (s.ok) stage_box_pairs<F, R>(a, pp, s, L);
       __syncthreads();
@@ -751,9 +726,7 @@ __device__ __forceinline__ void advect_block_one_fill(const StepArgs &a, const S
     locate_xyz<R>(a, sm.plev, sm.idp, s_lut, x, y, z, L);
     if (h == 0) {
       set_time(T0, L);
-      const Box b = block_box<R>(a, sm, act, L, ref);
-      const Box w = widen_box(a, b, cap, true);
-      s = w.ok ? w : b;
+      s = block_box<R>(a, sm, act, L, ref);
       s.ok = s.ok && s.bi * s.bj * s.bk <= cap;
       if (s.ok) stage_box_pairs_fill<F, R>(a, pp, s, L, fill);
       else fill();
