@@ -33,7 +33,7 @@ FP32_PEAK_TFLOPS = 157.3
 # interpolations of three winds, the spread of 16 values per wind, two
 # Philox blocks with Box-Muller, cos(lat) three times -- counted at 1,000
 # and used for every arithmetic form.  The kernels execute fewer (the F64
-# form 804 FP64 FLOP per parcel-step by counter): a grid point's time
+# form 810 FP64 FLOP per parcel-step by counter): a grid point's time
 # interpolation is shared by the parcels of a block and the spreads are
 # tabulated per cell, so `achieved` credits work the kernel avoids, as an
 # algorithmic roofline does; the executed rate is in the profiles.
@@ -44,14 +44,14 @@ FLOP_PER_PS = 1000.0
 # kernels (profiles/k_step_<form>_1e8_0p3deg.md; the timed launches, each
 # after a sort whose order it applies as it reads the parcels); None where
 # not measured.
-TRAFFIC_BYTES_PER_LAUNCH = {"f64": 20.695e9, "f32": 17.847e9, "bf16": 17.434e9, "f16": 14.613e9}
+TRAFFIC_BYTES_PER_LAUNCH = {"f64": 19.243e9, "f32": 17.501e9, "bf16": 17.416e9, "f16": 14.613e9}
 TRAFFIC_STEPS_PER_LAUNCH = 10
 # The convection / sedimentation kernel, F64 form, same workload
 # (profiles/k_step_phys_1e8_0p3deg.md): FP64 FLOP per parcel-step and HBM
 # bytes per 10-step launch (2 x FETCH_SIZE + WRITE_SIZE), with sedimentation
 # alone and with both modules.
 FLOP_PER_PS_PHYS = {"f64_sedi": 947.0, "f64_phys": 1026.0}
-TRAFFIC_BYTES_PER_LAUNCH_PHYS = {"f64_sedi": 64.176e9, "f64_phys": 176.246e9}
+TRAFFIC_BYTES_PER_LAUNCH_PHYS = {"f64_sedi": 64.225e9, "f64_phys": 176.242e9}
 METRIC = "particle-steps/s (advect+diffuse, 1e8 particles, 0.3° grid); surrogate vs plain"
 FORMS = {"f64": (0, 0), "f32": (1, 0), "bf16": (1, 1), "f16": (1, 2)}   # (math, dtype)
 
