@@ -74,9 +74,9 @@ def cells(met, part):
     return i0, j, k
 
 
-def run(mpt, met, part, math, dtype, sort_interval, nsteps, flags=7):
+def run(mpt, met, part, math, dtype, sort_interval, nsteps, flags=7, dt=180.0):
     import torch
-    ctx = mpt.Context(met, mpt.make_params(math=math, sort_interval=sort_interval, fuse=10, flags=flags),
+    ctx = mpt.Context(met, mpt.make_params(dt=dt, math=math, sort_interval=sort_interval, fuse=10, flags=flags),
                       n_max=part.n, dtype=dtype)
     ctx.upload_met(met)
     P = mpt.DeviceParticles.from_host(part, math=math, pingpong=sort_interval > 0)
@@ -105,6 +105,32 @@ def test_staged_equals_gathered_bitwise(mpt, met3, form):
     b = run(mpt, met3, both, math, dtype, 0, 60)
     b = b.subset(np.arange(n))                       # ids 0 .. n-1, by id
     assert_bitwise(a, b)
+
+
+@pytest.mark.parametrize("form", [(0, 0), (1, 0)])
+def test_one_staging_with_midpoints_off_the_box(mpt, met3, form):
+    """The F64 and F32 forms stage each step's box once, for the start
+    cells, and the lanes whose midpoint cell leaves it (or whose midpoint
+    falls in the next time-level pair) gather.  A step of 1500 s sends many
+    more midpoints off the box than the 180 s of the workload, and the step
+    from 21000 s has its midpoint past the time level at 21600 s; the result
+    must still equal the all-gather run bit for bit."""
+    math, dtype = form
+    n = 100_000
+    part = dense(n, 33)
+    a = run(mpt, met3, part, math, dtype, 10, 20, dt=1500.0)
+    rng = np.random.default_rng(6)
+    dec = part.copy()
+    dec.lon = np.mod(part.lon + 180.0, 360.0)
+    dec.id = part.id + np.uint32(n)
+    both = inputs.Particles(*(np.concatenate([getattr(part, f), getattr(dec, f)])
+                              for f in ("lon", "lat", "p", "id", "up", "vp", "wp")))
+    both = both.subset(rng.permutation(2 * n))
+    b = run(mpt, met3, both, math, dtype, 0, 20, dt=1500.0)
+    b = b.subset(np.arange(n))
+    assert_bitwise(a, b)
+    moved = oracle.chord_deg(part.lon, part.lat, a.lon, a.lat)
+    say(f"[one staging] form {form}: median distance after 20 steps of 1500 s {np.median(moved):.2f} deg")
 
 
 @pytest.mark.parametrize("form", [(0, 0), (1, 0), (1, 1)])
