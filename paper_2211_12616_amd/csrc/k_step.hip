@@ -30,9 +30,8 @@ __device__ __forceinline__ const StepArgs &reload_args() {
 }
 
 // Whether a step kernel makes the step's random draws during the
-// advection's staging loads (the turbulent diffusion's in the first wind
-// evaluation, the mesoscale's in the second) instead of just before their
-// use.  The draws then stay live across the advection: only the FP32 form
+// advection's staging loads (both in the shadow of the one staging per
+// step) instead of just before their use.  The draws then stay live across the advection: only the FP32 form
 // with FP32 fields, no convection or sedimentation and one block per 256
 // parcels (launch shape M 0) has the registers for them.
 template <int M, int F, typename R, bool P>
@@ -113,17 +112,14 @@ __device__ __forceinline__ void step_parcel(const StepLds<R> &sm, const uint16_t
       R xt[3], xm[3];
       auto draw_turb = [&] { if (a.flags & kTurb) normals3<R>(a.seed, id, step, 0u, xt); };
       auto draw_meso = [&] { if (do_meso) normals3<R>(a.seed, id, step, 1u, xm); };
+      static_assert(OneStaging<M, F, R, P>::value, "the early draws ride on the one staging per step");
       if (a.flags & kAdvect) {
-        if constexpr (OneStaging<M, F, R, P>::value) {
-          auto draws = [&] {
-            draw_turb();
-            draw_meso();
-          };
-          advect_block_one_fill<F, R, OneStaging<M, F, R, P>::wide>(a, sm, s_lut, act, T0, T1, lon, lat, p, ref,
-                                                                    draws);
-        } else {
-          advect_block_fill<F, R>(a, sm, s_lut, act, T0, T1, lon, lat, p, ref, draw_turb, draw_meso);
-        }
+        auto draws = [&] {
+          draw_turb();
+          draw_meso();
+        };
+        advect_block_one_fill<F, R, OneStaging<M, F, R, P>::wide>(a, sm, s_lut, act, T0, T1, lon, lat, p, ref,
+                                                                  draws);
         if (act) position(a, lon, lat, p);
       } else {
         draw_turb();

@@ -254,57 +254,6 @@ __device__ __forceinline__ BoxRef block_ref(const StepArgs &a, const double *ple
   return r;
 }
 
-// One pass of stage_box_fill over points q0 and q0 + kBlock (stage_box's
-// loop body with a hook; stage_box keeps its own copy of the loop, whose
-// code the compiler schedules better inline).  Each point is clamped to
-// the box's last point (a duplicate rewrites that point's own value);
-// mid() runs between the loads and their use.
-template <int F, typename R, typename Mid>
-__device__ __forceinline__ void stage_pass(const StepArgs &a, const StepLds<R> &sm, const Box &b, const Loc<R> &L,
-                                           int q0, Mid &&mid) {
-  using T = typename Rec<F>::T;
-  const T *lev0 = reinterpret_cast<const T *>(a.met) + (size_t)L.l * (size_t)a.level_elems;
-  const T *lev1 = reinterpret_cast<const T *>(a.met) + (size_t)L.l1 * (size_t)a.level_elems;
-  const int npts = b.bi * b.bj * b.bk;
-  const uint32_t mi = kDivMagic.m[b.bi];
-  const uint32_t mj = kDivMagic.m[b.bj];
-  const float *sw0 = s_scale_win + (L.la % kScaleWin) * 3 * a.nz;
-  const float *sw1 = s_scale_win + ((L.la + 1) % kScaleWin) * 3 * a.nz;
-  T r0[2], r1[2];
-  int kq[2];
-#pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int q = min(q0 + u * kBlock, npts - 1);
-    const int r = (int)__umulhi((uint32_t)q, mi);
-    const int ii = q - r * b.bi;
-    const int kk = (int)__umulhi((uint32_t)r, mj);
-    const int jj = r - kk * b.bj;
-    int gi = b.gi + ii;
-    if (gi >= a.nx) gi -= a.nx;
-    kq[u] = b.k0 + kk;
-    const int off = (kq[u] * a.ny + b.j0 + jj) * a.nx + gi;   // < 2^31: nx*ny*nz is
-    r0[u] = lev0[off];
-    r1[u] = lev1[off];
-  }
-  mid();
-#pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int q = min(q0 + u * kBlock, npts - 1);
-    const int k = kq[u];
-    float sc0[3] = {1.0f, 1.0f, 1.0f}, sc1[3] = {1.0f, 1.0f, 1.0f};
-    if constexpr (F != kF32) {
-      sc0[0] = sw0[k]; sc0[1] = sw0[a.nz + k]; sc0[2] = sw0[2 * a.nz + k];
-      sc1[0] = sw1[k]; sc1[1] = sw1[a.nz + k]; sc1[2] = sw1[2 * a.nz + k];
-    }
-    R v0[3], v1[3];
-    Fetch<F, R>::get(r0[u], sc0, v0);
-    Fetch<F, R>::get(r1[u], sc1, v1);
-    sm.bu[q] = lerp(v0[0], v1[0], L.ft);
-    sm.bv[q] = lerp(v0[1], v1[1], L.ft);
-    sm.bw[q] = lerp(v0[2], v1[2], L.ft);
-  }
-}
-
 // Loads the box's points from the two time levels of L (slots l, l1; R16:
 // decoded with the scales of levels la and la + 1 from the window), weights
 // them in time with L.ft and stores u, v, w in LDS.  Point q of the box is
@@ -358,18 +307,6 @@ __device__ __forceinline__ void stage_box(const StepArgs &a, const StepLds<R> &s
       sm.bw[q] = lerp(v0[2], v1[2], L.ft);
     }
   }
-}
-
-// stage_box with fill() run once in every thread between the first pass's
-// loads and their use: work that does not depend on the winds done while
-// the loads are in flight.  The first pass runs in every thread (npts >= 8;
-// a thread past the box rewrites the box's last point).
-template <int F, typename R, typename Fill>
-__device__ __forceinline__ void stage_box_fill(const StepArgs &a, const StepLds<R> &sm, const Box &b,
-                                               const Loc<R> &L, Fill &&fill) {
-  const int npts = b.bi * b.bj * b.bk;
-  stage_pass<F, R>(a, sm, b, L, (int)threadIdx.x, fill);
-  for (int q0 = (int)threadIdx.x + 2 * kBlock; q0 < npts; q0 += 2 * kBlock) stage_pass<F, R>(a, sm, b, L, q0, [] {});
 }
 
 // The 8 time-weighted corners of L's cell from the staged box, then the
@@ -427,50 +364,6 @@ __device__ __forceinline__ void advect_block(const StepArgs &a, const StepLds<R>
                                              double &p, BoxRef &ref) {
   auto wind = [&](int h, double x, double y, double z, R out[3]) {
     wind_block<F, R>(a, sm, s_lut, act, h ? T1 : T0, x, y, z, ref, out);
-  };
-  double nlon, nlat, np;
-  midpoint<R>(a, lon, lat, p, wind, nlon, nlat, np);
-  if (act) {
-    lon = nlon;
-    lat = nlat;
-    p = np;
-  }
-}
-
-// wind_block with fill() run once in every thread: during the staging's
-// first loads, or before the gathers when the box does not fit.
-template <int F, typename R, typename Fill>
-__device__ __forceinline__ void wind_block_fill(const StepArgs &a, const StepLds<R> &sm, const uint16_t *s_lut,
-                                                bool act, const TimeLoc &T, double lon, double lat, double p,
-                                                BoxRef &ref, R out[3], Fill &&fill) {
-  Loc<R> L;
-  locate_xyz<R>(a, sm.plev, sm.idp, s_lut, lon, lat, p, L);
-  set_time(T, L);
-  const Box b = block_box<R>(a, sm, act, L, ref);
-  if (b.ok) stage_box_fill<F, R>(a, sm, b, L, fill);
-  __syncthreads();
-  if (b.ok) {
-    if (act) interp_box<R>(a, sm, b, L, out);
-  } else {
-    fill();
-    if (act) {
-      Cell16<F> c;
-      load_cell<F, R>(a, L, c);
-      interp_cell<F, R>(a, c, L, out);
-    }
-  }
-}
-
-// advect_block with fill0 and fill1 run once each, inside the first and the
-// second wind evaluation.
-template <int F, typename R, typename Fill0, typename Fill1>
-__device__ __forceinline__ void advect_block_fill(const StepArgs &a, const StepLds<R> &sm, const uint16_t *s_lut,
-                                                  bool act, const TimeLoc &T0, const TimeLoc &T1, double &lon,
-                                                  double &lat, double &p, BoxRef &ref, Fill0 &&fill0,
-                                                  Fill1 &&fill1) {
-  auto wind = [&](int h, double x, double y, double z, R out[3]) {
-    if (h) wind_block_fill<F, R>(a, sm, s_lut, act, T1, x, y, z, ref, out, fill1);
-    else wind_block_fill<F, R>(a, sm, s_lut, act, T0, x, y, z, ref, out, fill0);
   };
   double nlon, nlat, np;
   midpoint<R>(a, lon, lat, p, wind, nlon, nlat, np);
