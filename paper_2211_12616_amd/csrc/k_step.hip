@@ -31,21 +31,24 @@ __device__ __forceinline__ const StepArgs &reload_args() {
 
 // Whether a step kernel makes the step's random draws during the
 // advection's staging loads (both in the shadow of the one staging per
-// step) instead of just before their use.  The draws then stay live across the advection: only the FP32 form
-// with FP32 fields, no convection or sedimentation and one block per 256
-// parcels (launch shape M 0) has the registers for them.
+// step) instead of just before their use.  The draws then stay live across
+// the advection: only the FP32 arithmetic forms with FP32 or FP16 fields
+// (four waves per SIMD), no convection or sedimentation and one block per
+// 256 parcels (launch shape M 0) have the registers for them.
 template <int M, int F, typename R, bool P>
 struct EarlyDraws {
-  static constexpr bool value = M == 0 && F == kF32 && sizeof(R) == 4 && !P;
+  static constexpr bool value = M == 0 && (F == kF32 || F == kF16) && sizeof(R) == 4 && !P;
 };
 
 // Whether a step kernel stages its winds once per step (advect_block_one):
-// the FP64 form and the FP32 form with FP32 fields, launched one block per
-// 256 parcels, without convection or sedimentation.  The FP32 form's pairs
-// take a wider box region (Wide: kWidePairs points).
+// the FP64 form and the FP32 arithmetic form with FP32 or FP16 fields,
+// launched one block per 256 parcels, without convection or sedimentation.
+// The latter two take a wider box region for their pairs (Wide).  The BF16
+// form runs five waves per SIMD, whose LDS share leaves no room for the
+// pairs, and stages twice.
 template <int M, int F, typename R, bool P>
 struct OneStaging {
-  static constexpr bool value = M == 0 && !P && (sizeof(R) == 8 || F == kF32);
+  static constexpr bool value = M == 0 && !P && (sizeof(R) == 8 || F == kF32 || F == kF16);
   static constexpr bool wide = value && sizeof(R) == 4;
 };
 
@@ -330,7 +333,8 @@ static hipError_t launch_mode(int field, int math_f64, const StepArgs &args, dim
   } else if (field == kBF16) {
     hipLaunchKernelGGL((k_step_f32<M, kBF16>), grid, block, lds_bytes<float>(field, args), stream, args);
   } else {
-    hipLaunchKernelGGL((k_step_f32<M, kF16>), grid, block, lds_bytes<float>(field, args), stream, args);
+    hipLaunchKernelGGL((k_step_f32<M, kF16>), grid, block,
+                       lds_bytes<float>(field, args, OneStaging<M, kF16, float, false>::wide), stream, args);
   }
   return hipGetLastError();
 }

@@ -41,16 +41,19 @@ __host__ __device__ constexpr size_t round16(size_t x) { return (x + 15) & ~(siz
 // bounds, then 2 per wave for the offset masks.
 constexpr int kRedInts = (kBlock / 64) * 8 + (kBlock / 64) * 2 + 8;
 
-// Points of the pair box of the FP32 form's one staging per step (3 x 8
-// bytes per point: 28.8 KB, so that four blocks still fit a CU).
+// Points of the pair box of the one staging per step in the FP32 form (3 x
+// 8 bytes per point: 28.8 KB) and the FP16-storage form (24 KB, beside its
+// scale window), so that four blocks still fit a CU.
 constexpr int kWidePairs = 1200;
+constexpr int kWidePairsR16 = 1000;
 
 // Bytes of the box region: u, v, w planes of BoxCap values each, or (wide)
-// enough for kWidePairs FP32 pairs per variable.
+// enough for kWidePairs (R16 storage: kWidePairsR16) FP32 pairs per
+// variable.
 template <typename R>
-__host__ __device__ constexpr size_t box_bytes(bool wide) {
-  return round16(wide && (size_t)3 * kWidePairs * 8 > (size_t)3 * BoxCap<R>::value * sizeof(R)
-                     ? (size_t)3 * kWidePairs * 8
+__host__ __device__ constexpr size_t box_bytes(bool wide, bool r16) {
+  return round16(wide && (size_t)3 * (r16 ? kWidePairsR16 : kWidePairs) * 8 > (size_t)3 * BoxCap<R>::value * sizeof(R)
+                     ? (size_t)3 * (r16 ? kWidePairsR16 : kWidePairs) * 8
                      : (size_t)3 * BoxCap<R>::value * sizeof(R));
 }
 
@@ -61,7 +64,7 @@ __host__ __device__ constexpr size_t box_bytes(bool wide) {
 template <typename R>
 __host__ __device__ constexpr size_t step_lds_bytes(int nz, bool r16, bool wide = false) {
   return (r16 ? round16((size_t)kScaleWin * 3 * nz * sizeof(float)) : 0) + round16((size_t)2 * nz * sizeof(double)) +
-         box_bytes<R>(wide) + (size_t)kRedInts * sizeof(int);
+         box_bytes<R>(wide, r16) + (size_t)kRedInts * sizeof(int);
 }
 
 template <typename R>
@@ -82,7 +85,7 @@ __device__ __forceinline__ StepLds<R> step_lds(int nz, bool r16, bool wide = fal
   sm.bu = reinterpret_cast<R *>(base + off);
   sm.bv = sm.bu + BoxCap<R>::value;
   sm.bw = sm.bv + BoxCap<R>::value;
-  off += box_bytes<R>(wide);
+  off += box_bytes<R>(wide, r16);
   sm.red = reinterpret_cast<int *>(base + off);
   return sm;
 }
@@ -399,16 +402,16 @@ __device__ __forceinline__ bool in_box(const StepArgs &a, const Box &b, const Lo
 }
 
 // Points per pair plane: the memory of the one-time planes, or (Wide) the
-// wide box region.
-template <typename R, bool Wide = false>
+// wide box region (R16: R16 storage).
+template <typename R, bool Wide = false, bool R16 = false>
 constexpr int pair_cap() {
-  return Wide ? kWidePairs : BoxCap<R>::value * (int)sizeof(R) / 8;
+  return Wide ? (R16 ? kWidePairsR16 : kWidePairs) : BoxCap<R>::value * (int)sizeof(R) / 8;
 }
 
 // The three pair planes (u, v, w; point q's pair at [q]) in the box region.
-template <typename R, bool Wide = false>
+template <typename R, bool Wide = false, bool R16 = false>
 __device__ __forceinline__ void pair_planes(const StepLds<R> &sm, float2 *pp[3]) {
-  constexpr int cap = pair_cap<R, Wide>();
+  constexpr int cap = pair_cap<R, Wide, R16>();
   float2 *base = reinterpret_cast<float2 *>(sm.bu);
   pp[0] = base;
   pp[1] = base + cap;
@@ -609,8 +612,8 @@ __device__ __forceinline__ void advect_block_one_fill(const StepArgs &a, const S
                                                       bool act, const TimeLoc &T0, const TimeLoc &T1, double &lon,
                                                       double &lat, double &p, BoxRef &ref, Fill &&fill) {
   float2 *pp[3];
-  pair_planes<R, Wide>(sm, pp);
-  constexpr int cap = pair_cap<R, Wide>();
+  pair_planes<R, Wide, F != kF32>(sm, pp);
+  constexpr int cap = pair_cap<R, Wide, F != kF32>();
   const bool same = T0.l == T1.l && T0.l1 == T1.l1 && T0.la == T1.la;   // uniform
   Box s;
   s.ok = false;
