@@ -25,6 +25,8 @@
 // block_ref gives the reference cell the first box is measured from.
 #pragma once
 
+#include <type_traits>
+
 #include "mpt_device.h"
 
 namespace mpt {
@@ -41,19 +43,24 @@ __host__ __device__ constexpr size_t round16(size_t x) { return (x + 15) & ~(siz
 // bounds, then 2 per wave for the offset masks.
 constexpr int kRedInts = (kBlock / 64) * 8 + (kBlock / 64) * 2 + 8;
 
-// Points of the pair box of the one staging per step in the FP32 form (3 x
-// 8 bytes per point: 28.8 KB) and the FP16-storage form (24 KB, beside its
-// scale window), so that four blocks still fit a CU.
+// The one staging per step keeps an FP32 pair per point and variable (8
+// bytes).  Points of its box: FP64 form 1536 (the memory of its one-time
+// planes), FP32 form 1200 (28.8 KB) and FP16-storage form 1000 (24 KB,
+// beside its scale window; both four blocks per CU).
 constexpr int kWidePairs = 1200;
 constexpr int kWidePairsR16 = 1000;
+using Pair = float2;
+template <typename R>
+__host__ __device__ constexpr int wide_pairs(bool r16) {
+  return sizeof(R) == 8 ? BoxCap<double>::value : (r16 ? kWidePairsR16 : kWidePairs);
+}
 
 // Bytes of the box region: u, v, w planes of BoxCap values each, or (wide)
-// enough for kWidePairs (R16 storage: kWidePairsR16) FP32 pairs per
-// variable.
+// also enough for wide_pairs pairs per variable.
 template <typename R>
 __host__ __device__ constexpr size_t box_bytes(bool wide, bool r16) {
-  return round16(wide && (size_t)3 * (r16 ? kWidePairsR16 : kWidePairs) * 8 > (size_t)3 * BoxCap<R>::value * sizeof(R)
-                     ? (size_t)3 * (r16 ? kWidePairsR16 : kWidePairs) * 8
+  return round16(wide && (size_t)3 * wide_pairs<R>(r16) * sizeof(Pair) > (size_t)3 * BoxCap<R>::value * sizeof(R)
+                     ? (size_t)3 * wide_pairs<R>(r16) * sizeof(Pair)
                      : (size_t)3 * BoxCap<R>::value * sizeof(R));
 }
 
@@ -382,11 +389,14 @@ __device__ __forceinline__ void advect_block(const StepArgs &a, const StepLds<R>
 // The midpoint of a step lies in or next to the cell of its start (the
 // half-step displacement is far below a cell), so the box of the block's
 // start cells holds most midpoint cells too, and one staging serves both
-// wind evaluations of the step: the box is staged once with the two time
-// levels' values of each point as they come from the records (FP32, after
-// the R16 decode and scale), a pair per point and variable, and each corner
-// is weighted in time when it is read, with the evaluation's own weight, as
-// the gather path weights it.  The lanes whose midpoint cell leaves the box
+// wind evaluations of the step: the box is staged once with an FP32 pair
+// per point and variable from the two time levels' values a (the earlier)
+// and b (after the R16 decode and scale), and each corner is weighted in
+// time when it is read, with the evaluation's own weight f, as the gather
+// path's lerp, fma(f, b - a, a) in R.  For R = FP32 the pair is (a, b - a),
+// one FMA per corner; for R = FP64 it is (a, b), converted when read (an
+// FP64 pair would double the LDS reads, which cost more than the
+// conversions).  The lanes whose midpoint cell leaves the box
 // gather its records.  This saves the second box exchange, staging and pair
 // of barriers at the price of the per-corner time weights.  (Widening the
 // box by a cell, so that every midpoint reads LDS, staged twice the points
@@ -405,23 +415,31 @@ __device__ __forceinline__ bool in_box(const StepArgs &a, const Box &b, const Lo
 // wide box region (R16: R16 storage).
 template <typename R, bool Wide = false, bool R16 = false>
 constexpr int pair_cap() {
-  return Wide ? (R16 ? kWidePairsR16 : kWidePairs) : BoxCap<R>::value * (int)sizeof(R) / 8;
+  return Wide ? wide_pairs<R>(R16) : BoxCap<R>::value * (int)sizeof(R) / (int)sizeof(Pair);
 }
 
 // The three pair planes (u, v, w; point q's pair at [q]) in the box region.
 template <typename R, bool Wide = false, bool R16 = false>
-__device__ __forceinline__ void pair_planes(const StepLds<R> &sm, float2 *pp[3]) {
+__device__ __forceinline__ void pair_planes(const StepLds<R> &sm, Pair *pp[3]) {
   constexpr int cap = pair_cap<R, Wide, R16>();
-  float2 *base = reinterpret_cast<float2 *>(sm.bu);
+  Pair *base = reinterpret_cast<Pair *>(sm.bu);
   pp[0] = base;
   pp[1] = base + cap;
   pp[2] = base + 2 * cap;
 }
 
-// Stages box b's points as pairs (the values of time levels l and l1 of L,
-// decoded and scaled for R16 storage, in FP32).
+// A point's pair from the values a, b of its two time levels: (a, b - a)
+// for R = FP32, (a, b) for R = FP64.
+template <typename R>
+__device__ __forceinline__ Pair pair_of(float a, float b) {
+  if constexpr (sizeof(R) == 8) return make_float2(a, b);
+  else return make_float2(a, b - a);
+}
+
+// Stages box b's points as pairs (pair_of) of the values of time levels l
+// and l1 of L (decoded and scaled for R16 storage).
 template <int F, typename R>
-__device__ __forceinline__ void stage_box_pairs(const StepArgs &a, float2 *const pp[3], const Box &b, const Loc<R> &L) {
+__device__ __forceinline__ void stage_box_pairs(const StepArgs &a, Pair *const pp[3], const Box &b, const Loc<R> &L) {
   using T = typename Rec<F>::T;
   const T *lev0 = reinterpret_cast<const T *>(a.met) + (size_t)L.l * (size_t)a.level_elems;
   const T *lev1 = reinterpret_cast<const T *>(a.met) + (size_t)L.l1 * (size_t)a.level_elems;
@@ -462,36 +480,61 @@ __device__ __forceinline__ void stage_box_pairs(const StepArgs &a, float2 *const
         v1[2] = dec<F>(r1[u].z) * sw1[2 * a.nz + k];
       }
 #pragma unroll
-      for (int c = 0; c < 3; ++c) pp[c][q] = make_float2(v0[c], v1[c]);
+      for (int c = 0; c < 3; ++c) pp[c][q] = pair_of<R>(v0[c], v1[c]);
     }
   }
 }
 
 // The wind at L from the pair planes of box b: each corner's pair weighted
-// in time with L.ft (as Fetch and the lerp of the gather path), then the
-// spatial interpolation.
+// in time with L.ft (the lerp of the gather path), then the spatial
+// interpolation (interp_spatial's operations; for R = FP32 one variable at
+// a time, so that only one variable's pairs are held at once).
 template <typename R>
-__device__ __forceinline__ void interp_pairs(const StepArgs &a, float2 *const pp[3], const Box &b, const Loc<R> &L,
+__device__ __forceinline__ void interp_pairs(const StepArgs &a, Pair *const pp[3], const Box &b, const Loc<R> &L,
                                              R out[3]) {
   int ci = L.i0 - b.gi;
   if (ci < 0) ci += a.nx;
   const int sj = b.bi, sk = b.bi * b.bj;
   const int base = (L.k - b.k0) * sk + (L.j - b.j0) * sj + ci;
-  R cv[2][2][2][3];
+  if constexpr (sizeof(R) == 8) {
+    R cv[2][2][2][3];
 #pragma unroll
-  for (int dk = 0; dk < 2; ++dk)
+    for (int dk = 0; dk < 2; ++dk)
 #pragma unroll
-    for (int dj = 0; dj < 2; ++dj)
+      for (int dj = 0; dj < 2; ++dj)
 #pragma unroll
-      for (int di = 0; di < 2; ++di) {
-        const int q = base + dk * sk + dj * sj + di;
+        for (int di = 0; di < 2; ++di) {
+          const int q = base + dk * sk + dj * sj + di;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const float2 v = pp[c][q];
-          cv[dk][dj][di][c] = lerp((R)v.x, (R)v.y, L.ft);
+          for (int c = 0; c < 3; ++c) {
+            const float2 v = pp[c][q];
+            cv[dk][dj][di][c] = lerp((R)v.x, (R)v.y, L.ft);
+          }
         }
+    interp_spatial<R>(cv, L, out);
+  } else {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      R cv[2][2][2];
+#pragma unroll
+      for (int dk = 0; dk < 2; ++dk)
+#pragma unroll
+        for (int dj = 0; dj < 2; ++dj)
+#pragma unroll
+          for (int di = 0; di < 2; ++di) {
+            const float2 v = pp[c][base + dk * sk + dj * sj + di];
+            cv[dk][dj][di] = fma(L.ft, v.y, v.x);
+          }
+      R yk[2];
+#pragma unroll
+      for (int dk = 0; dk < 2; ++dk) {
+        const R x0 = lerp(cv[dk][0][0], cv[dk][0][1], L.fx);
+        const R x1 = lerp(cv[dk][1][0], cv[dk][1][1], L.fx);
+        yk[dk] = lerp(x0, x1, L.fy);
       }
-  interp_spatial<R>(cv, L, out);
+      out[c] = lerp(yk[0], yk[1], L.fz);
+    }
+  }
 }
 
 // advect_block with one box exchange and one staging per step: the box of
@@ -504,8 +547,8 @@ template <int F, typename R>
 __device__ __forceinline__ void advect_block_one(const StepArgs &a, const StepLds<R> &sm, const uint16_t *s_lut,
                                                  bool act, const TimeLoc &T0, const TimeLoc &T1, double &lon,
                                                  double &lat, double &p, BoxRef &ref) {
-  float2 *pp[3];
-  pair_planes<R>(sm, pp);
+  Pair *pp[3];
+  pair_planes<R, true>(sm, pp);
   const bool same = T0.l == T1.l && T0.l1 == T1.l1 && T0.la == T1.la;   // uniform
   Box s;
   s.ok = false;
@@ -515,7 +558,7 @@ __device__ __forceinline__ void advect_block_one(const StepArgs &a, const StepLd
     if (h == 0) {
       set_time(T0, L);
       s = block_box<R>(a, sm, act, L, ref);
-      s.ok = s.ok && s.bi * s.bj * s.bk <= pair_cap<R>();
+      s.ok = s.ok && s.bi * s.bj * s.bk <= pair_cap<R, true>();
       if (s.ok) stage_box_pairs<F, R>(a, pp, s, L);
       __syncthreads();
       if (!act) return;
@@ -547,7 +590,7 @@ __device__ __forceinline__ void advect_block_one(const StepArgs &a, const StepLd
 // One pass of stage_box_pairs over points q0 and q0 + kBlock (each clamped
 // to the box's last point), with mid() run between the loads and their use.
 template <int F, typename R, typename Mid>
-__device__ __forceinline__ void pair_pass(const StepArgs &a, float2 *const pp[3], const Box &b, const Loc<R> &L,
+__device__ __forceinline__ void pair_pass(const StepArgs &a, Pair *const pp[3], const Box &b, const Loc<R> &L,
                                           int q0, Mid &&mid) {
   using T = typename Rec<F>::T;
   const T *lev0 = reinterpret_cast<const T *>(a.met) + (size_t)L.l * (size_t)a.level_elems;
@@ -589,7 +632,7 @@ __device__ __forceinline__ void pair_pass(const StepArgs &a, float2 *const pp[3]
       v1[2] = dec<F>(r1[u].z) * sw1[2 * a.nz + k];
     }
 #pragma unroll
-    for (int c = 0; c < 3; ++c) pp[c][q] = make_float2(v0[c], v1[c]);
+    for (int c = 0; c < 3; ++c) pp[c][q] = pair_of<R>(v0[c], v1[c]);
   }
 }
 
@@ -597,7 +640,7 @@ __device__ __forceinline__ void pair_pass(const StepArgs &a, float2 *const pp[3]
 // pass's loads and their use (the first pass runs in every thread: npts >= 8,
 // a thread past the box rewrites the box's last point).
 template <int F, typename R, typename Fill>
-__device__ __forceinline__ void stage_box_pairs_fill(const StepArgs &a, float2 *const pp[3], const Box &b,
+__device__ __forceinline__ void stage_box_pairs_fill(const StepArgs &a, Pair *const pp[3], const Box &b,
                                                      const Loc<R> &L, Fill &&fill) {
   const int npts = b.bi * b.bj * b.bk;
   pair_pass<F, R>(a, pp, b, L, (int)threadIdx.x, fill);
@@ -611,7 +654,7 @@ template <int F, typename R, bool Wide, typename Fill>
 __device__ __forceinline__ void advect_block_one_fill(const StepArgs &a, const StepLds<R> &sm, const uint16_t *s_lut,
                                                       bool act, const TimeLoc &T0, const TimeLoc &T1, double &lon,
                                                       double &lat, double &p, BoxRef &ref, Fill &&fill) {
-  float2 *pp[3];
+  Pair *pp[3];
   pair_planes<R, Wide, F != kF32>(sm, pp);
   constexpr int cap = pair_cap<R, Wide, F != kF32>();
   const bool same = T0.l == T1.l && T0.l1 == T1.l1 && T0.la == T1.la;   // uniform
