@@ -44,14 +44,14 @@ FLOP_PER_PS = 1000.0
 # kernels (profiles/k_step_<form>_1e8_0p3deg.md; the timed launches, each
 # after a sort whose order it applies as it reads the parcels); None where
 # not measured.
-TRAFFIC_BYTES_PER_LAUNCH = {"f64": 19.244e9, "f32": 16.072e9, "bf16": 17.416e9, "f16": 14.586e9}
+TRAFFIC_BYTES_PER_LAUNCH = {"f64": 19.244e9, "f32": 16.072e9, "bf16": 17.416e9, "f16": 14.588e9}
 TRAFFIC_STEPS_PER_LAUNCH = 10
 # The convection / sedimentation kernel, F64 form, same workload
 # (profiles/k_step_phys_1e8_0p3deg.md): FP64 FLOP per parcel-step and HBM
 # bytes per 10-step launch (2 x FETCH_SIZE + WRITE_SIZE), with sedimentation
 # alone and with both modules.
 FLOP_PER_PS_PHYS = {"f64_sedi": 947.0, "f64_phys": 1026.0}
-TRAFFIC_BYTES_PER_LAUNCH_PHYS = {"f64_sedi": 64.209e9, "f64_phys": 176.241e9}
+TRAFFIC_BYTES_PER_LAUNCH_PHYS = {"f64_sedi": 64.262e9, "f64_phys": 176.239e9}
 METRIC = "particle-steps/s (advect+diffuse, 1e8 particles, 0.3° grid); surrogate vs plain"
 FORMS = {"f64": (0, 0), "f32": (1, 0), "bf16": (1, 1), "f16": (1, 2)}   # (math, dtype)
 
