@@ -43,13 +43,14 @@ struct EarlyDraws {
 // Whether a step kernel stages its winds once per step (advect_block_one):
 // the FP64 form and the FP32 arithmetic form with FP32 or FP16 fields,
 // launched one block per 256 parcels, without convection or sedimentation.
-// The latter two take a wider box region for their pairs (Wide).  The BF16
-// form runs five waves per SIMD, whose LDS share leaves no room for the
-// pairs, and stages twice.
+// Their pairs take the wide box region (Wide: for FP64 the memory of its
+// one-time planes, for FP32 and FP16 fields a region wider than those).
+// The BF16 form runs five waves per SIMD, whose LDS share leaves no room
+// for the pairs, and stages twice.
 template <int M, int F, typename R, bool P>
 struct OneStaging {
   static constexpr bool value = M == 0 && !P && (sizeof(R) == 8 || F == kF32 || F == kF16);
-  static constexpr bool wide = value && sizeof(R) == 4;
+  static constexpr bool wide = value;
 };
 
 // Advances parcel i (valid: the thread holds a parcel; M: the launch shape)
@@ -326,7 +327,8 @@ static hipError_t launch_mode(int field, int math_f64, const StepArgs &args, dim
   const dim3 block(kBlock);
   if (math_f64) {
     if (field != kF32) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_step_f64<M>, grid, block, lds_bytes<double>(field, args), stream, args);
+    hipLaunchKernelGGL(k_step_f64<M>, grid, block,
+                       lds_bytes<double>(field, args, OneStaging<M, kF32, double, false>::wide), stream, args);
   } else if (field == kF32) {
     hipLaunchKernelGGL((k_step_f32<M, kF32>), grid, block,
                        lds_bytes<float>(field, args, OneStaging<M, kF32, float, false>::wide), stream, args);
